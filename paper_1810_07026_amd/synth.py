@@ -1,0 +1,560 @@
+"""Seeded synthetic hydrocarbon systems (inputs only, no potential arithmetic).
+
+Every generator returns a dict with ``x`` [n,3] positions (A), ``species``
+[n] (0 = C, 1 = H), ``box`` [3] (A), ``periodic`` [3], ``v`` [n,3] (A/fs,
+when velocities are requested) and ``meta``.  Geometry: C-C 1.54 A, C-H 1.09
+A, tetrahedral angles; these stand in for the paper's polyethylene benchmark
+and model problems (Sec. 5.1), which are not available.
+
+Both the GPU tests and the CPU oracle tests draw their inputs from here; the
+module holds none of the AIREBO method's arithmetic.
+"""
+import math
+
+import numpy as np
+
+CC, CH = 1.54, 1.09
+TETRA = math.acos(-1.0 / 3.0)          # 109.47 degrees
+MASS = (12.011, 1.008)                 # amu
+KB = 8.617333262e-5                    # eV/K
+MVV2E = 103.642691                     # amu A^2/fs^2 -> eV
+SEED0 = 1810070260
+
+# Non-bonded distances when placing atoms (A), by species pair: never below
+# the hard floor (keeps every non-bonded pair outside the bonding range), and
+# the trial torsion that best clears the soft target is kept.
+_HARD = np.array([[2.05, 1.85], [1.85, 1.75]])
+_SOFT = np.array([[3.0, 2.5], [2.5, 2.2]])
+# Growth at melt density uses a low floor and relies on _relax() afterwards.
+_GROW_FLOOR = np.array([[1.7, 1.45], [1.45, 1.3]])
+# Non-bonded targets of the relaxation (every pair ends at or above _HARD).
+_RELAX = np.array([[2.15, 1.95], [1.95, 1.85]])
+
+
+def _unit(v):
+    return v / np.linalg.norm(v)
+
+
+def _nerf(a, b, c, bond, angle, torsion):
+    """Position of d with |cd| = bond, angle(b,c,d) = angle, dihedral(a,b,c,d) = torsion."""
+    bc = _unit(c - b)
+    n = _unit(np.cross(b - a, bc))
+    m = np.cross(n, bc)
+    d2 = np.array([-bond * math.cos(angle), bond * math.sin(angle) * math.cos(torsion),
+                   bond * math.sin(angle) * math.sin(torsion)])
+    return c + d2[0] * bc + d2[1] * m + d2[2] * n
+
+
+def _ch2_hydrogens(prev, cur, nxt):
+    """Two tetrahedral hydrogens of a CH2 carbon between two backbone carbons."""
+    a, b = _unit(prev - cur), _unit(nxt - cur)
+    u = -_unit(a + b)
+    n = _unit(np.cross(a, b))
+    half = TETRA / 2.0
+    return [cur + CH * (math.cos(half) * u + math.sin(half) * n),
+            cur + CH * (math.cos(half) * u - math.sin(half) * n)]
+
+
+def _ch3_hydrogens(a, b, c):
+    """Three staggered hydrogens on carbon c bonded to b (a: the atom before b)."""
+    return [_nerf(a, b, c, CH, TETRA, t) for t in (math.pi, math.pi / 3, -math.pi / 3)]
+
+
+def _random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def maxwell_velocities(species, T, rng):
+    """Gaussian velocities at temperature T, zero net momentum, rescaled to exactly T (3N-3 dof)."""
+    m = np.asarray(MASS)[np.asarray(species)]
+    n = len(m)
+    v = rng.normal(size=(n, 3)) * np.sqrt(KB * T / (m * MVV2E))[:, None]
+    v -= (m[:, None] * v).sum(0) / m.sum()
+    ke = 0.5 * (m[:, None] * v * v).sum() * MVV2E
+    if n > 1 and ke > 0:
+        v *= math.sqrt(T / (2.0 * ke / ((3 * n - 3) * KB)))
+    return v
+
+
+class _Packer:
+    """Cell grid of placed atoms for distance checks in a periodic box."""
+
+    def __init__(self, box, cap, cell=5.6, zwall=None, floor=None):
+        self.box = np.asarray(box, float)
+        self.floor = _HARD if floor is None else floor
+        self.nc = np.maximum(1, np.floor(self.box / cell).astype(int))
+        self.cells = {}
+        self.x = np.zeros((cap, 3))
+        self.s = np.zeros(cap, dtype=np.int32)
+        self.chain = np.zeros(cap, dtype=np.int64)
+        self.pos = np.zeros(cap, dtype=np.int64)
+        self.alive = np.zeros(cap, dtype=bool)
+        self.free = []
+        self.n = 0
+        self.zwall = zwall
+
+    def _key(self, p):
+        f = np.floor((p % self.box) / self.box * self.nc).astype(int) % self.nc
+        return (int(f[0]), int(f[1]), int(f[2]))
+
+    def near(self, p):
+        """Indices of placed atoms in the 27 cells around p."""
+        k = self._key(p)
+        seen = set()
+        idx = []
+        for a in (-1, 0, 1):
+            for b in (-1, 0, 1):
+                for c in (-1, 0, 1):
+                    q = ((k[0] + a) % self.nc[0], (k[1] + b) % self.nc[1], (k[2] + c) % self.nc[2])
+                    if q in seen:
+                        continue
+                    seen.add(q)
+                    lst = self.cells.get(q)
+                    if lst:
+                        idx.extend(lst)
+        return np.asarray(idx, dtype=np.int64)
+
+    def score(self, trial_x, trial_s, idx):
+        """Per trial: (all distances >= hard floor, min over atoms of r - soft target).
+
+        trial_x [K, m, 3], trial_s [m]; idx: atoms to test against."""
+        K = trial_x.shape[0]
+        if self.zwall is not None:
+            z = trial_x[..., 2]
+            inside = np.all((z >= self.zwall[0]) & (z <= self.zwall[1]), axis=1)
+        else:
+            inside = np.ones(K, bool)
+        if len(idx) == 0:
+            return inside, np.full(K, 10.0)
+        d = self.x[idx][None, None, :, :] - trial_x[:, :, None, :]
+        d -= self.box * np.round(d / self.box)
+        r = np.sqrt((d * d).sum(-1))                      # [K, m, n]
+        hard = self.floor[trial_s[:, None], self.s[idx][None, :]]
+        soft = _SOFT[trial_s[:, None], self.s[idx][None, :]]
+        ok = np.all(r >= hard[None], axis=(1, 2)) & inside
+        return ok, (r - soft[None]).min(axis=(1, 2))
+
+    def add(self, p, sp, chain, pos):
+        i = self.free.pop() if self.free else self.n
+        if i == self.n:
+            self.n += 1
+        self.x[i] = p
+        self.s[i] = sp
+        self.chain[i] = chain
+        self.pos[i] = pos
+        self.alive[i] = True
+        self.cells.setdefault(self._key(p), []).append(i)
+        return i
+
+    def remove(self, i):
+        self.cells[self._key(self.x[i])].remove(i)
+        self.alive[i] = False
+        self.free.append(i)
+
+    def compact(self):
+        """Drop removed slots; order atoms chain by chain, backbone position, C before H."""
+        keep = np.where(self.alive[:self.n])[0]
+        order = keep[np.lexsort((self.s[keep], self.pos[keep], self.chain[keep]))]
+        return self.x[order].copy(), self.s[order].copy()
+
+
+def _ch2_h_batch(prev, cur, nxt):
+    """CH2 hydrogens of carbon cur for a batch of next-carbon positions nxt [K,3] -> [K,2,3]."""
+    a = _unit(prev - cur)
+    b = nxt - cur
+    b /= np.linalg.norm(b, axis=1, keepdims=True)
+    u = -(a + b)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    n = np.cross(np.broadcast_to(a, b.shape), b)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    half = TETRA / 2.0
+    h1 = cur + CH * (math.cos(half) * u + math.sin(half) * n)
+    h2 = cur + CH * (math.cos(half) * u - math.sin(half) * n)
+    return np.stack([h1, h2], axis=1)
+
+
+def _nerf_batch(a, b, c, bond, angle, tors):
+    bc = _unit(c - b)
+    n = _unit(np.cross(b - a, bc))
+    m = np.cross(n, bc)
+    return (c + (-bond * math.cos(angle)) * bc + (bond * math.sin(angle) * np.cos(tors))[:, None] * m
+            + (bond * math.sin(angle) * np.sin(tors))[:, None] * n)
+
+
+class _Chain:
+    def __init__(self, cid):
+        self.cid = cid
+        self.bb = []       # backbone carbon positions
+        self.cidx = []     # packer index of each backbone carbon
+        self.hidx = []     # packer indices of the hydrogens of each backbone carbon
+        self.fails = 0
+        self.done = False
+
+
+def _grow_all(pk, n_chains, nC, rng, K=24, lo=None, hi=None):
+    """Grow n_chains CnH(2n+2) chains together, one backbone carbon per chain
+    per sweep.  Torsions are drawn uniformly; of K trials the one that best
+    clears the soft distance targets is kept (never below the hard floor).  A
+    chain that cannot continue backs up two units; one that keeps failing is
+    removed and started again elsewhere."""
+    box = pk.box
+    lo = 0.0 if lo is None else lo
+    hi = box[2] if hi is None else hi
+    chains = [_Chain(c) for c in range(n_chains)]
+
+    def others(ch, p, k):
+        idx = pk.near(p)
+        if len(idx):
+            idx = idx[~((pk.chain[idx] == ch.cid) & (pk.pos[idx] >= k - 2))]
+        return idx
+
+    def seed(ch):
+        for _ in range(5000):
+            c0 = rng.uniform([0, 0, lo], [box[0], box[1], hi])
+            c1 = c0 + _random_rotation(rng) @ np.array([CC, 0.0, 0.0])
+            ok, sc = pk.score(np.array([[c0, c1]]), np.array([0, 0]), pk.near(c0))
+            if ok[0] and sc[0] > 1.0:
+                ch.bb = [c0, c1]
+                ch.cidx = [pk.add(c0, 0, ch.cid, 0), pk.add(c1, 0, ch.cid, 1)]
+                ch.hidx = [[], []]
+                return
+        raise RuntimeError("could not seed a chain")
+
+    def back(ch):
+        k = len(ch.bb)
+        pk.remove(ch.cidx.pop())
+        ch.bb.pop()
+        ch.hidx.pop()
+        for h in ch.hidx[k - 2]:
+            pk.remove(h)
+        ch.hidx[k - 2] = []
+
+    def restart(ch):
+        for lst in ch.hidx:
+            for h in lst:
+                pk.remove(h)
+        for c in ch.cidx:
+            pk.remove(c)
+        ch.fails = 0
+        seed(ch)
+
+    def step(ch):
+        bb, k = ch.bb, len(ch.bb)
+        if k < nC:
+            if k == 2:
+                a = _unit(bb[0] - bb[1])
+                perp = np.cross(a, rng.normal(size=(K, 3)))
+                perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+                cand = bb[1] + CC * (math.cos(TETRA) * a + math.sin(TETRA) * perp)
+                h3 = np.stack([np.array(_ch3_hydrogens(q, bb[1], bb[0])) for q in cand])
+                hs = np.concatenate([h3, _ch2_h_batch(bb[0], bb[1], cand)], axis=1)
+            else:
+                cand = _nerf_batch(bb[k - 3], bb[k - 2], bb[k - 1], CC, TETRA, rng.uniform(-math.pi, math.pi, K))
+                hs = _ch2_h_batch(bb[k - 2], bb[k - 1], cand)
+            T = np.concatenate([hs, cand[:, None, :]], axis=1)
+        else:
+            rot = rng.uniform(-math.pi, math.pi, K)
+            T = np.array([[_nerf(bb[-3], bb[-2], bb[-1], CH, TETRA, r0 + t)
+                           for t in (0.0, 2 * math.pi / 3, -2 * math.pi / 3)] for r0 in rot])
+        sp = np.array([1] * (T.shape[1] - 1) + [1 if k == nC else 0])
+        ok, sc = pk.score(T, sp, others(ch, bb[-1], k))
+        if not ok.any():
+            return False
+        atoms = T[int(np.argmax(np.where(ok, sc, -1e9)))]
+        if k == nC:
+            ch.hidx[nC - 1] = [pk.add(h, 1, ch.cid, nC - 1) for h in atoms]
+            ch.done = True
+            return True
+        if k == 2:
+            ch.hidx[0] = [pk.add(h, 1, ch.cid, 0) for h in atoms[:3]]
+            ch.hidx[1] = [pk.add(h, 1, ch.cid, 1) for h in atoms[3:5]]
+        else:
+            ch.hidx[k - 1] = [pk.add(h, 1, ch.cid, k - 1) for h in atoms[:2]]
+        ch.cidx.append(pk.add(atoms[-1], 0, ch.cid, k))
+        ch.bb.append(atoms[-1])
+        ch.hidx.append([])
+        return True
+
+    for ch in chains:
+        seed(ch)
+    sweeps = 0
+    while not all(ch.done for ch in chains):
+        sweeps += 1
+        if sweeps > 20 * nC:
+            raise RuntimeError("chain growth did not converge")
+        for c in rng.permutation(n_chains):
+            ch = chains[c]
+            if ch.done:
+                continue
+            if step(ch):
+                continue
+            ch.fails += 1
+            if ch.fails > 25 or len(ch.bb) <= 4:
+                restart(ch)
+                continue
+            for _ in range(min(2, len(ch.bb) - 3)):
+                back(ch)
+
+
+def _chain_topology(chain, pos, s):
+    """Bonds and bond-angle (1-3) pairs of grown alkane chains from their labels."""
+    n = len(s)
+    key = {}
+    hyd = {}
+    for i in range(n):
+        if s[i] == 0:
+            key[(int(chain[i]), int(pos[i]))] = i
+        else:
+            hyd.setdefault((int(chain[i]), int(pos[i])), []).append(i)
+    nb = [[] for _ in range(n)]
+    bonds = []
+    for (c, k), i in key.items():
+        j = key.get((c, k + 1))
+        if j is not None:
+            bonds.append((i, j)); nb[i].append(j); nb[j].append(i)
+        for h in hyd.get((c, k), []):
+            bonds.append((i, h)); nb[i].append(h); nb[h].append(i)
+    ang = set()
+    for i in range(n):
+        for a in range(len(nb[i])):
+            for b in range(a + 1, len(nb[i])):
+                p, q = sorted((nb[i][a], nb[i][b]))
+                ang.add((p, q))
+    return np.array(bonds, dtype=np.int64), np.array(sorted(ang), dtype=np.int64)
+
+
+def _relax(x, s, box, bonds, angles, zwall=None, iters=3000, log=None):
+    """Push non-bonded atoms apart while springs hold bond lengths and bond
+    angles (as 1-3 distances) at their grown values: plain capped-step
+    gradient descent on a quadratic penalty.  Geometry only."""
+    from scipy.spatial import cKDTree
+    box = np.asarray(box, float)
+    x = np.mod(x, box)
+
+    def disp(a, b):
+        d = x[b] - x[a]
+        return d - box * np.round(d / box)
+
+    r0b = np.linalg.norm(disp(bonds[:, 0], bonds[:, 1]), axis=1)
+    r0a = np.linalg.norm(disp(angles[:, 0], angles[:, 1]), axis=1)
+    excl = set(map(tuple, bonds.tolist())) | set(map(tuple, angles.tolist()))
+    excl_code = np.array(sorted(a * len(s) + b for a, b in excl), dtype=np.int64)
+    hard = _HARD[s[:, None], s[None, :]] if len(s) < 2 else None
+    pairs = None
+    for it in range(iters):
+        if it % 10 == 0:
+            tree = cKDTree(np.mod(x, box), boxsize=box)
+            pairs = tree.query_pairs(2.7, output_type="ndarray")
+            pairs.sort(axis=1)
+            code = pairs[:, 0] * len(s) + pairs[:, 1]
+            pairs = pairs[~np.isin(code, excl_code)]
+        g = np.zeros_like(x)
+        d = disp(pairs[:, 0], pairs[:, 1])
+        r = np.linalg.norm(d, axis=1)
+        tgt = _RELAX[s[pairs[:, 0]], s[pairs[:, 1]]]
+        viol = r < tgt
+        f = np.where(viol, (r - tgt) / np.maximum(r, 1e-9), 0.0)[:, None] * d
+        np.add.at(g, pairs[:, 0], f)
+        np.add.at(g, pairs[:, 1], -f)
+        for lst, r0, k in ((bonds, r0b, 4.0), (angles, r0a, 1.0)):
+            d2 = disp(lst[:, 0], lst[:, 1])
+            r2 = np.linalg.norm(d2, axis=1)
+            f2 = (k * (r2 - r0) / r2)[:, None] * d2
+            np.add.at(g, lst[:, 0], f2)
+            np.add.at(g, lst[:, 1], -f2)
+        step = 0.5 * g
+        m = np.linalg.norm(step, axis=1)
+        step *= np.minimum(1.0, 0.05 / np.maximum(m, 1e-12))[:, None]
+        x = x + step
+        if zwall is not None:
+            x[:, 2] = np.clip(x[:, 2], zwall[0], zwall[1])
+        hard_viol = (r < _HARD[s[pairs[:, 0]], s[pairs[:, 1]]]).sum()
+        if log and it % 100 == 0:
+            log(it, int(viol.sum()), int(hard_viol), float(r.min()) if len(r) else 0.0)
+        if it % 10 == 9 and hard_viol == 0 and not viol.any():
+            break
+    return np.mod(x, box)
+
+
+def polyethylene(n_chains, n_carbon, box, seed, T=300.0, jitter=0.0, zwall=None, relax=None, log=None):
+    """n_chains CnH(2n+2) chains grown with uniform random torsions in a periodic box.
+
+    At melt density (relax=True) the chains are grown with a low overlap floor
+    and then relaxed so that every non-bonded pair clears the bonding range."""
+    rng = np.random.default_rng(seed)
+    per_chain = 3 * n_carbon + 2
+    if relax is None:
+        relax = n_chains * per_chain / float(np.prod(box)) > 0.05
+    pk = _Packer(box, n_chains * per_chain + 64, zwall=zwall, floor=_GROW_FLOOR if relax else None)
+    lo, hi = (zwall[0] + 1.0, zwall[1] - 1.0) if zwall is not None else (None, None)
+    _grow_all(pk, n_chains, n_carbon, rng, lo=lo, hi=hi)
+    meta = dict(kind="polyethylene", n_chains=n_chains, n_carbon=n_carbon, seed=seed)
+    if relax:
+        keep = np.where(pk.alive[:pk.n])[0]
+        order = keep[np.lexsort((pk.s[keep], pk.pos[keep], pk.chain[keep]))]
+        x, s_, ch, ps = pk.x[order], pk.s[order], pk.chain[order], pk.pos[order]
+        bonds, angles = _chain_topology(ch, ps, s_)
+        x = _relax(x, s_, box, bonds, angles, zwall=zwall, log=log)
+        out = dict(x=x, species=s_.copy(), box=np.asarray(box, float), periodic=np.ones(3, np.int32), meta=meta)
+        if T is not None:
+            out["v"] = maxwell_velocities(s_, T, rng)
+        return out
+    return _finish(pk, box, (1, 1, 1), rng, T, meta, jitter)
+
+
+def _finish(pk, box, periodic, rng, T, meta, jitter=0.0):
+    x, s = pk.compact()
+    if jitter > 0:
+        x += rng.normal(scale=jitter, size=x.shape)
+    for c in range(3):
+        if periodic[c]:
+            x[:, c] %= box[c]
+    out = dict(x=x, species=s, box=np.asarray(box, float), periodic=np.asarray(periodic, np.int32), meta=meta)
+    if T is not None:
+        out["v"] = maxwell_velocities(s, T, rng)
+    return out
+
+
+def pe_small(seed=SEED0 + 0, T=300.0):
+    """4 x C20H42 in a 20 A periodic cube, Gaussian jitter 0.05 A (248 atoms)."""
+    return polyethylene(4, 20, (20.0, 20.0, 20.0), seed, T=T, jitter=0.05)
+
+
+def melt_box_side(n_atoms_per_chain, n_chains, density_gcc=0.85):
+    mass = n_chains * (n_atoms_per_chain // 3 * MASS[0] + (n_atoms_per_chain - n_atoms_per_chain // 3) * MASS[1])
+    return (mass * 1.66053906660 / density_gcc) ** (1.0 / 3.0)
+
+
+def pe_melt(n_chains=106, n_carbon=100, density_gcc=0.85, seed=SEED0 + 1, T=300.0):
+    """C100H202 melt at 0.85 g/cm^3 (106 chains = 32,012 atoms, cube 66.26 A)."""
+    per = 3 * n_carbon + 2
+    mass = n_chains * (n_carbon * MASS[0] + (2 * n_carbon + 2) * MASS[1])
+    L = (mass * 1.66053906660 / density_gcc) ** (1.0 / 3.0)
+    out = polyethylene(n_chains, n_carbon, (L, L, L), seed, T=T)
+    out["meta"].update(kind="pe_melt", density_gcc=density_gcc, atoms_per_chain=per)
+    return out
+
+
+def tile(sysd, reps):
+    """Periodic replica reps = (a, b, c) of a periodic system."""
+    x, s, box = sysd["x"], sysd["species"], np.asarray(sysd["box"])
+    shifts = np.array([[a, b, c] for a in range(reps[0]) for b in range(reps[1]) for c in range(reps[2])], float)
+    X = (x[None, :, :] + (shifts * box)[:, None, :]).reshape(-1, 3)
+    S = np.tile(s, len(shifts))
+    out = dict(x=X, species=S, box=box * np.asarray(reps), periodic=np.asarray(sysd["periodic"]),
+               meta=dict(sysd["meta"], tiled=list(reps)))
+    if "v" in sysd:
+        out["v"] = np.tile(sysd["v"], (len(shifts), 1))
+    return out
+
+
+def isolated(x, species, pad=20.0):
+    """A molecule in a non-periodic box (box lengths only bound the coordinates)."""
+    x = np.asarray(x, float)
+    lo = x.min(0)
+    x = x - lo + pad / 2
+    box = x.max(0) + pad / 2
+    return dict(x=x, species=np.asarray(species, np.int32), box=box, periodic=np.zeros(3, np.int32),
+                meta=dict(kind="isolated"))
+
+
+# ---------------------------------------------------------------------------
+# Small molecules (tests)
+# ---------------------------------------------------------------------------
+def alkane(n_carbon, torsions=None, rng=None):
+    """CnH(2n+2) with given backbone torsions (radians; default all-trans)."""
+    if n_carbon == 1:
+        c = np.zeros(3)
+        d = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float) / math.sqrt(3)
+        return np.vstack([c, c + CH * d]), np.array([0, 1, 1, 1, 1], np.int32)
+    bb = [np.zeros(3), np.array([CC, 0, 0])]
+    if n_carbon > 2:
+        bb.append(bb[1] + np.array([-CC * math.cos(TETRA), CC * math.sin(TETRA), 0]))
+    for k in range(3, n_carbon):
+        t = math.pi if torsions is None else torsions[k - 3]
+        bb.append(_nerf(bb[k - 3], bb[k - 2], bb[k - 1], CC, TETRA, t))
+    xs, ss = list(bb), [0] * n_carbon
+    if n_carbon == 2:
+        ref = np.array([0, 1.0, 0])
+        for h in _ch3_hydrogens(ref + bb[1], bb[1], bb[0]):
+            xs.append(h); ss.append(1)
+        for h in _ch3_hydrogens(ref + bb[0], bb[0], bb[1]):
+            xs.append(h); ss.append(1)
+        return np.array(xs), np.array(ss, np.int32)
+    for h in _ch3_hydrogens(bb[2], bb[1], bb[0]):
+        xs.append(h); ss.append(1)
+    for k in range(1, n_carbon - 1):
+        for h in _ch2_hydrogens(bb[k - 1], bb[k], bb[k + 1]):
+            xs.append(h); ss.append(1)
+    for h in _ch3_hydrogens(bb[-3], bb[-2], bb[-1]):
+        xs.append(h); ss.append(1)
+    return np.array(xs), np.array(ss, np.int32)
+
+
+def ethane(phi):
+    """Ethane with the H-C-C-H dihedral set by rotating one methyl group by phi (radians)."""
+    c0, c1 = np.zeros(3), np.array([CC, 0, 0])
+    ref = np.array([0.0, 1.0, 0.0])
+    h0 = [_nerf(ref + c1, c1, c0, CH, TETRA, t) for t in (0, 2 * math.pi / 3, -2 * math.pi / 3)]
+    h1 = [_nerf(ref, c0, c1, CH, TETRA, phi + t) for t in (0, 2 * math.pi / 3, -2 * math.pi / 3)]
+    return np.vstack([c0, c1] + h0 + h1), np.array([0, 0, 1, 1, 1, 1, 1, 1], np.int32)
+
+
+def ring_aromatic(n_rings=1, cc=1.40):
+    """Benzene (1), naphthalene (2), anthracene (3): planar, C-H 1.09 A."""
+    centres = [np.array([k * cc * math.sqrt(3), 0.0, 0.0]) for k in range(n_rings)]
+    pts = []
+    for c in centres:
+        for m in range(6):
+            a = math.pi / 6 + m * math.pi / 3
+            p = c + cc * np.array([math.cos(a), math.sin(a), 0.0])
+            if not any(np.linalg.norm(p - q) < 0.1 for q in pts):
+                pts.append(p)
+    C = np.array(pts)
+    xs, ss = [*C], [0] * len(C)
+    for i, p in enumerate(C):
+        nb = [q for q in C if 0.1 < np.linalg.norm(q - p) < cc * 1.1]
+        if len(nb) == 2:
+            d = _unit(2 * p - nb[0] - nb[1])
+            xs.append(p + CH * d); ss.append(1)
+    return np.array(xs), np.array(ss, np.int32)
+
+
+def ethylene(cc=1.33):
+    """Planar C2H4 with exact 120 degree angles."""
+    c0, c1 = np.zeros(3), np.array([cc, 0, 0])
+    hs = []
+    for c, sgn in ((c0, -1), (c1, 1)):
+        for a in (math.pi / 3, -math.pi / 3):
+            hs.append(c + CH * np.array([sgn * math.cos(a), math.sin(a), 0.0]))
+    return np.vstack([c0, c1] + hs), np.array([0, 0, 1, 1, 1, 1], np.int32)
+
+
+def graphene_flake(nx, ny, cc=1.42):
+    """Rectangular graphene patch with H on every two-fold carbon."""
+    a1 = np.array([cc * math.sqrt(3), 0, 0])
+    a2 = np.array([cc * math.sqrt(3) / 2, cc * 1.5, 0])
+    pts = []
+    for i in range(nx):
+        for j in range(ny):
+            o = i * a1 + j * a2 - (j // 2) * a1
+            pts.append(o)
+            pts.append(o + np.array([0, cc, 0]))
+    C = np.array(pts)
+    d = np.linalg.norm(C[:, None] - C[None], axis=2)
+    deg = ((d > 0.1) & (d < cc * 1.1)).sum(1)
+    keep = deg >= 2
+    C = C[keep]
+    d = np.linalg.norm(C[:, None] - C[None], axis=2)
+    xs, ss = [*C], [0] * len(C)
+    for i in range(len(C)):
+        nb = np.where((d[i] > 0.1) & (d[i] < cc * 1.1))[0]
+        if len(nb) == 2:
+            v = _unit(2 * C[i] - C[nb[0]] - C[nb[1]])
+            xs.append(C[i] + CH * v); ss.append(1)
+    return np.array(xs), np.array(ss, np.int32)
