@@ -1,0 +1,120 @@
+/*
+ * airebo.h -- C ABI of the MI355X (gfx950) AIREBO library.
+ *
+ * The library evaluates the AIREBO hydrocarbon potential: total and per-term
+ * energy, per-atom forces and the virial of a periodic (or isolated) system
+ * of carbon and hydrogen atoms, and integrates it in time with velocity
+ * Verlet.  The method is the one whose optimisation Hoehnerbach & Bientinesi
+ * describe in "Optimizing AIREBO" (Sec. 2.1): the REBO bond-order term
+ * (Sec. 2.1.1, Alg. 1 and Sec. 2.1.3), the explicit torsion term (Alg. 2) and
+ * the Lennard-Jones term with its C_ij connectivity and bond-order switch
+ * (Sec. 2.1.2, Alg. 3); the only input of the potential is the atom
+ * positions (Sec. 1) and forces are the negative gradient (Sec. 2).
+ *
+ * Conventions shared by every call:
+ *   - Units are LAMMPS "metal": A, eV, fs, amu.  Species code 0 = C, 1 = H.
+ *   - Arrays marked "device" are GPU pointers (e.g. from torch tensors on
+ *     the same device as the context); "host" arrays are CPU pointers.
+ *     Positions, velocities and forces are [n][3] row-major FP64.
+ *   - Calls are ordered on the HIP stream passed in (NULL = default stream);
+ *     device outputs are valid after that stream is synchronised.  Calls
+ *     that return device-side status (airebo_compute, airebo_nve) synchronise
+ *     the stream before returning so that errors can be reported.
+ *   - Every call returns 0 on success or a negative AIREBO_E_* code; the
+ *     message of the last error of the calling thread is airebo_last_error().
+ *     Outputs are unspecified after an error.  No exception crosses the ABI.
+ *   - The caller owns every array it passes; the library never frees or
+ *     keeps a caller pointer beyond the call.  A context owns its parameter
+ *     copy and all scratch memory.  A context is not thread safe.
+ */
+#ifndef AIREBO_H
+#define AIREBO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AIREBO_OK = 0,
+  AIREBO_E_ARG = -1,       /* null pointer, n < 0, bad option value            */
+  AIREBO_E_PARAMS = -2,    /* parameter file missing, malformed or inconsistent */
+  AIREBO_E_SPECIES = -3,   /* a species code other than 0 or 1                 */
+  AIREBO_E_BOX = -4,       /* a periodic side below max(12 A, LJ cutoff)       */
+  AIREBO_E_NONFINITE = -5, /* a non-finite position or result                  */
+  AIREBO_E_CAPACITY = -6,  /* a neighbour or work capacity limit was exceeded  */
+  AIREBO_E_DEVICE = -7     /* a HIP runtime error (message carries the code)   */
+};
+
+enum { AIREBO_FP64 = 0, AIREBO_MIXED = 1 };
+enum { AIREBO_TERM_REBO = 1, AIREBO_TERM_LJ = 2, AIREBO_TERM_TORSION = 4, AIREBO_TERM_ALL = 7 };
+
+typedef struct airebo_ctx* airebo_ctx_t;
+
+/* Run-time options.  Zero-initialise, then set what differs from the
+ * defaults; airebo_options_default() fills the defaults. */
+typedef struct {
+  int32_t precision;   /* AIREBO_FP64 (default) or AIREBO_MIXED                       */
+  int32_t term_mask;   /* AIREBO_TERM_* bits; default AIREBO_TERM_ALL                  */
+  double skin;         /* neighbour-list skin in A (default 1.0)                      */
+  int32_t lj_cap;      /* LJ list entries per atom; 0 = automatic (grows on demand)   */
+  int32_t device;      /* HIP device ordinal (default 0)                              */
+  int32_t reserved[8];
+} airebo_options;
+
+void airebo_options_default(airebo_options* opt);
+
+/* Create a context from a parameter file (format documented in the file
+ * itself: scalars, angular-spline knots, bicubic and tricubic knot tables).
+ * The parameters are validated (cutoffs ordered, knots increasing, symmetric
+ * tables symmetric) and copied; spline coefficients are built on the host and
+ * uploaded.  Errors: AIREBO_E_ARG, AIREBO_E_PARAMS, AIREBO_E_DEVICE. */
+int airebo_ctx_create(const char* param_path, const airebo_options* opt, airebo_ctx_t* out);
+void airebo_ctx_free(airebo_ctx_t ctx);
+
+/* Energy, forces and virial of one configuration (Sec. 2.1, Alg. 1-3).
+ *   n        number of atoms (>= 0)
+ *   pos      device [n][3] positions in A; any values (wrapped internally)
+ *   species  device [n] int32, 0 = C, 1 = H
+ *   box      host [3] orthorhombic box lengths in A (origin 0)
+ *   periodic host [3] int32 flags; a periodic side must be >= max(12 A, LJ cutoff)
+ *   energy   device [4] out: total, REBO, LJ, torsion (eV)
+ *   forces   device [n][3] out: eV/A, in input order
+ *   virial   device [6] out: xx yy zz xy xz yz of sum_a x_a (x) F_a (eV);
+ *            positive for repulsion
+ *   stream   hipStream_t or NULL
+ * Neighbour lists are rebuilt on every call.  Errors: AIREBO_E_ARG,
+ * AIREBO_E_SPECIES, AIREBO_E_BOX, AIREBO_E_NONFINITE, AIREBO_E_CAPACITY,
+ * AIREBO_E_DEVICE. */
+int airebo_compute(airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species, const double* box,
+                   const int32_t* periodic, double* energy, double* forces, double* virial, void* stream);
+
+/* Velocity-Verlet NVE (Sec. 2): nsteps steps of length dt_fs, updating pos
+ * and vel (device [n][3], A and A/fs) in place; positions are wrapped into the
+ * box whenever the neighbour lists are rebuilt (when an atom has moved more
+ * than half the skin since the last build).  mass: host [2] amu of C and H.
+ * thermo: device [(nsteps / thermo_every) + 1][6] rows of
+ * {step, PE, KE, Etot, T, rebuilds}, written for step 0 and every
+ * thermo_every steps (thermo may be NULL when thermo_every <= 0).  The step
+ * sequence is captured once into a HIP graph and replayed.  Errors as for
+ * airebo_compute. */
+int airebo_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int32_t* species, const double* box,
+               const int32_t* periodic, const double* mass, double dt_fs, int64_t nsteps, int64_t thermo_every,
+               double* thermo, void* stream);
+
+/* Counters of the last airebo_compute / airebo_nve call (host [16] int64):
+ *   0 LJ pairs inside the cutoff (each pair once)   1 pairs with C_ij = 0
+ *   2 pairs queued for the modified bond order b*   3 b* pairs with dS_b != 0
+ *   4 bonds                                          5 neighbour-list rebuilds
+ *   6 max short neighbours of one atom               7 max path-map entries of one atom
+ *   8 max LJ entries of one atom                     9-15 reserved */
+int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* airebo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIREBO_H */

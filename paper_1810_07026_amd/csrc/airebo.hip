@@ -1,0 +1,1526 @@
+// AIREBO energy / force / virial on MI355X (gfx950): kernels and the C ABI.
+//
+// Method: "Optimizing AIREBO" (Hoehnerbach & Bientinesi), Sec. 2.1:
+//   REBO pair term with bond order b_ij (Alg. 1, Sec. 2.1.3), explicit torsion
+//   (Alg. 2), Lennard-Jones with the C_ij connectivity switch and the modified
+//   bond order b*_ij inside S_b (Alg. 3, Sec. 2.1.2); forces are the negative
+//   gradient (Sec. 2), obtained here by a hand-written forward pass followed by
+//   a reverse (chain-rule) pass per bond, the "AD without a tape" pattern the
+//   paper describes for sums inside functions (Sec. 2).
+//
+// GPU design (one process, one device; everything stays in HBM):
+//   rebuild (when any atom moved more than half the skin):
+//     k_bin / k_scan / k_fill   counting sort of atoms into cells >= LJ cutoff + skin
+//     k_build                    one wavefront per atom: full LJ list (with image
+//                                shift codes) and the intermediate REBO list
+//                                (R2 + skin), both filled by wave-ballot compaction
+//                                (the vectorised list insertion of Sec. 4.1)
+//   every step:
+//     k_short                    exact short list from the intermediate list,
+//                                w, dw/dr, coordination N^C, N^H; species-bucketed
+//                                bond list (CC / CH / HH batches, Sec. 4.2)
+//     k_pathmap                  per atom, every atom reachable over <= 3 short
+//                                bonds with its largest weight product and the
+//                                path that realises it (the reversed C_ij search
+//                                of Sec. 4.3)
+//     k_bond                     one lane per bond: bond order, REBO pair term and
+//                                torsion merged (Sec. 4.2), forward then reverse
+//     k_lj                       one wavefront per atom over its full LJ list:
+//                                far pairs (r >= 3 max R2) are plain LJ; near pairs
+//                                look up C_ij in the path map; pairs inside the S_r
+//                                range are deferred to a queue (Sec. 4.3)
+//     k_bstar                    one lane per queued pair: b*, S_b, full gradient
+//   Forces are accumulated with hardware FP64 atomics; energies and the virial by
+//   block reduction followed by one atomic per block.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/airebo.h"
+#include "params.h"
+
+namespace airebo {
+
+constexpr int SCAP = 8;    // short (REBO) neighbours per atom
+constexpr int ICAP = 48;   // intermediate-list entries per atom
+constexpr int PCAP = 48;   // path-map entries per atom
+constexpr int WAVE = 64;
+
+// flag bits
+enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16, F_OV_BOND = 32, F_OV_QUEUE = 64,
+       F_NONFINITE = 128, F_BADSPEC = 256 };
+// accumulator slots
+enum { A_EREBO = 0, A_ELJ = 1, A_ETORS = 2, A_VIR = 3, A_KE = 9, A_N = 10 };
+// statistics slots (unsigned long long)
+enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
+       S_MAXLJ = 8, S_N = 16 };
+
+struct Dev {
+  int n;
+  double L[3], invL[3];
+  int per[3];
+  int nc[3];
+  double skin, rlist2[3], rint2[3];
+  double4* x;        // positions (w = species) since the last build
+  double4* xref;     // positions at the last build
+  int* cell_of;
+  int* cell_count;
+  int* cell_start;
+  int* cell_cursor;
+  int* cell_atoms;
+  int lj_cap;
+  int* lj_n;
+  unsigned* lj_e;    // j | shift code << 27
+  int* in_n;
+  int* in_e;
+  int* sn;
+  int* sj;
+  double4* sd;       // displacement to neighbour and its length
+  double2* sw;       // w, dw/dr
+  double* NCt;
+  double* NHt;
+  int bcap;
+  int* bcount;       // [3]
+  int2* bonds;       // [3][bcap]: (i, slot)
+  int* pm_n;
+  int* pm_atom;
+  double* pm_prod;
+  int* pm_code;
+  int qcap;
+  int* qcount;
+  int4* q;           // (i, j, shift code, path code)
+  double* F;         // forces [n][3]
+  double* acc;       // A_N accumulators
+  unsigned long long* stats;
+  int* flags;
+  int* step;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename R> struct V3 { R x, y, z; };
+template <typename R> __device__ __forceinline__ V3<R> mk(R a, R b, R c) { return {a, b, c}; }
+template <typename R> __device__ __forceinline__ V3<R> operator+(V3<R> a, V3<R> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename R> __device__ __forceinline__ V3<R> operator-(V3<R> a, V3<R> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename R> __device__ __forceinline__ V3<R> operator-(V3<R> a) { return {-a.x, -a.y, -a.z}; }
+template <typename R> __device__ __forceinline__ V3<R> operator*(R s, V3<R> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <typename R> __device__ __forceinline__ R dot(V3<R> a, V3<R> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename R> __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+__device__ __forceinline__ double xsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float xsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double xexp(double a) { return exp(a); }
+__device__ __forceinline__ float xexp(float a) { return expf(a); }
+__device__ __forceinline__ void xsincospi(double a, double* s, double* c) { sincospi(a, s, c); }
+__device__ __forceinline__ void xsincospi(float a, float* s, float* c) { sincospif(a, s, c); }
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// REBO bond weight w(r) and dw/dr: 1 below R1, 0 above R2, half cosine between.
+template <typename R>
+__device__ __forceinline__ R cutw(const DevParams& P, int p, R r, R& dw) {
+  if (r <= (R)P.R1[p]) { dw = 0; return 1; }
+  if (r >= (R)P.R2[p]) { dw = 0; return 0; }
+  R t = (r - (R)P.R1[p]) * (R)P.inv_dR[p];
+  R s, c;
+  xsincospi(t, &s, &c);
+  dw = (R)(-0.5 * M_PI) * (R)P.inv_dR[p] * s;
+  return (R)0.5 * ((R)1 + c);
+}
+// Cubic switch S(t) = 1 - t^2 (3 - 2t) on [0,1] and dS/dt.
+template <typename R>
+__device__ __forceinline__ R Sw(R t, R& d) {
+  if (t <= (R)0) { d = 0; return 1; }
+  if (t >= (R)1) { d = 0; return 0; }
+  d = (R)-6 * t * ((R)1 - t);
+  return (R)1 - t * t * ((R)3 - (R)2 * t);
+}
+// Half-cosine step from 1 (x <= lo) to 0 (x >= hi).
+template <typename R>
+__device__ __forceinline__ R cosstep(R x, double lo, double hi, R& d) {
+  if (x <= (R)lo) { d = 0; return 1; }
+  if (x >= (R)hi) { d = 0; return 0; }
+  R inv = (R)(1.0 / (hi - lo));
+  R s, c;
+  xsincospi((x - (R)lo) * inv, &s, &c);
+  d = (R)(-0.5 * M_PI) * inv * s;
+  return (R)0.5 * ((R)1 + c);
+}
+// Collinearity guard of dihedral terms as a function of cos theta.
+template <typename R>
+__device__ __forceinline__ R guard(const DevParams& P, R c, R& d) {
+  R a = c < (R)0 ? -c : c;
+  R inv = (R)(1.0 / (P.guard_off - P.guard_on));
+  R ds;
+  R s = Sw((a - (R)P.guard_on) * inv, ds);
+  d = ds * inv * (c < (R)0 ? (R)-1 : (R)1);
+  return s;
+}
+
+// Quintic angular spline: value and d/dx.
+template <typename R>
+__device__ __forceinline__ R gspl(const GSpline& g, R x, R& d) {
+  bool clamped = false;
+  if (x <= (R)g.x[0]) { x = (R)g.x[0]; clamped = true; }
+  if (x >= (R)g.x[g.n - 1]) { x = (R)g.x[g.n - 1]; clamped = true; }
+  int m = 0;
+  while (m + 2 < g.n && x > (R)g.x[m + 1]) ++m;
+  R t = (x - (R)g.x[m]) * (R)g.inv_h[m];
+  const double* c = g.c[m];
+  R v = (R)c[5], dv = (R)0;
+  for (int p = 4; p >= 0; --p) { dv = dv * t + v; v = v * t + (R)c[p]; }
+  d = clamped ? (R)0 : dv * (R)g.inv_h[m];
+  return v;
+}
+// g_i(cos theta) of the centre species; carbon blends gamma_C in over N_ij.
+template <typename R>
+__device__ __forceinline__ R gfun(const DevParams& P, int sc, R c, R N, R& dc, R& dN) {
+  dN = 0;
+  if (sc == 1) return gspl(P.gH, c, dc);
+  R dG;
+  R G = gspl(P.gC, c, dG);
+  dc = dG;
+  if (c <= (R)P.gammaC.x[0]) return G;
+  R dQ;
+  R Qn = cosstep(N, P.gC_lo, P.gC_hi, dQ);
+  if (Qn == (R)0 && dQ == (R)0) return G;
+  R dgam;
+  R gam = gspl(P.gammaC, c, dgam);
+  dc = dG + Qn * (dgam - dG);
+  dN = dQ * (gam - G);
+  return G + Qn * (gam - G);
+}
+// Bicubic P_{C s_j}(N^C, N^H) with partials.
+template <typename R>
+__device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx, R& dy) {
+  bool kx = x < (R)0 || x > (R)4, ky = y < (R)0 || y > (R)4;
+  x = x < (R)0 ? (R)0 : (x > (R)4 ? (R)4 : x);
+  y = y < (R)0 ? (R)0 : (y > (R)4 ? (R)4 : y);
+  int cx = min((int)x, 3), cy = min((int)y, 3);
+  R tx = x - (R)cx, ty = y - (R)cy;
+  const double* c = Pc[cx][cy];
+  R v = 0, vx = 0, vy = 0;
+  for (int a = 3; a >= 0; --a) {
+    R b0 = (R)c[a * 4 + 3], b1 = 0;
+    for (int b = 2; b >= 0; --b) { b1 = b1 * ty + b0; b0 = b0 * ty + (R)c[a * 4 + b]; }
+    vx = vx * tx + v;
+    v = v * tx + b0;
+    vy = vy * tx + b1;
+  }
+  dx = kx ? (R)0 : vx;
+  dy = ky ? (R)0 : vy;
+  return v;
+}
+// Tricubic table t at (x, y, z) with partials.
+template <typename R>
+__device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, R& dx, R& dy, R& dz) {
+  bool kx = x < (R)0 || x > (R)4, ky = y < (R)0 || y > (R)4, kz = z < (R)1 || z > (R)9;
+  x = x < (R)0 ? (R)0 : (x > (R)4 ? (R)4 : x);
+  y = y < (R)0 ? (R)0 : (y > (R)4 ? (R)4 : y);
+  z = z < (R)1 ? (R)1 : (z > (R)9 ? (R)9 : z);
+  int cx = min((int)x, 3), cy = min((int)y, 3), cz = min((int)z - 1, 7);
+  int cell = (cx * 4 + cy) * 8 + cz;
+  dx = dy = dz = 0;
+  if (!P.tri_nz[t][cell]) return 0;
+  R tx = x - (R)cx, ty = y - (R)cy, tz = z - (R)(cz + 1);
+  const double* c = P.tri + ((size_t)t * kTriCells + cell) * kTriCoef;
+  R v = 0, vx = 0, vy = 0, vz = 0;
+  for (int a = 3; a >= 0; --a) {
+    R u = 0, uy = 0, uz = 0;
+    for (int b = 3; b >= 0; --b) {
+      const double* cc = c + (a * 4 + b) * 4;
+      R w = (R)cc[3], wz = 0;
+      for (int k = 2; k >= 0; --k) { wz = wz * tz + w; w = w * tz + (R)cc[k]; }
+      uy = uy * ty + u;
+      u = u * ty + w;
+      uz = uz * ty + wz;
+    }
+    vx = vx * tx + v;
+    v = v * tx + u;
+    vy = vy * tx + uy;
+    vz = vz * tx + uz;
+  }
+  dx = kx ? (R)0 : vx;
+  dy = ky ? (R)0 : vy;
+  dz = kz ? (R)0 : vz;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Force / virial accumulation of one lane.  A gradient g = dE/dr_ab on the
+// relative vector r_ab = x_b - x_a gives F_a += g, F_b -= g and
+// W -= r_ab (x) g; the two atoms the lane owns are kept in registers.
+// ---------------------------------------------------------------------------
+struct Acc {
+  int i, j;
+  double fi[3], fj[3];
+  double W[6];
+  double* F;
+  __device__ void init(double* F_, int i_, int j_) {
+    F = F_; i = i_; j = j_;
+    for (int c = 0; c < 3; ++c) fi[c] = fj[c] = 0;
+    for (int c = 0; c < 6; ++c) W[c] = 0;
+  }
+  __device__ void force(int a, double gx, double gy, double gz) {
+    if (a == i) { fi[0] += gx; fi[1] += gy; fi[2] += gz; }
+    else if (a == j) { fj[0] += gx; fj[1] += gy; fj[2] += gz; }
+    else { atomic_add(&F[3 * a], gx); atomic_add(&F[3 * a + 1], gy); atomic_add(&F[3 * a + 2], gz); }
+  }
+  template <typename R>
+  __device__ void vec(int a, int b, V3<R> r, V3<R> g, double scale = 1.0) {
+    double gx = scale * (double)g.x, gy = scale * (double)g.y, gz = scale * (double)g.z;
+    force(a, gx, gy, gz);
+    force(b, -gx, -gy, -gz);
+    double rx = r.x, ry = r.y, rz = r.z;
+    W[0] -= rx * gx; W[1] -= ry * gy; W[2] -= rz * gz;
+    W[3] -= rx * gy; W[4] -= rx * gz; W[5] -= ry * gz;
+  }
+  __device__ void flush() {
+    if (i >= 0) for (int c = 0; c < 3; ++c) if (fi[c] != 0) atomic_add(&F[3 * i + c], fi[c]);
+    if (j >= 0) for (int c = 0; c < 3; ++c) if (fj[c] != 0) atomic_add(&F[3 * j + c], fj[c]);
+  }
+};
+
+// Block reduction of `nv` doubles per thread into global accumulators.
+template <int NV>
+__device__ void block_reduce_add(double (&v)[NV], double* out) {
+  __shared__ double red[NV][16];
+  int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  for (int q = 0; q < NV; ++q) {
+    double s = v[q];
+    for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[q][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0;
+    int nw = (blockDim.x + WAVE - 1) / WAVE;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    if (s != 0) atomic_add(&out[threadIdx.x], s);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ V3<R> nbr_vec(const Dev& D, int a, int q, R& r) {
+  double4 d = D.sd[a * SCAP + q];
+  r = (R)d.w;
+  return {(R)d.x, (R)d.y, (R)d.z};
+}
+
+// ---------------------------------------------------------------------------
+// Bond order b_ij (Sec. 2.1.3).  One end at a time: centre c with partner o
+// along r_co.  With bstar, r_ij is replaced by R1_ij where a bond length i-j
+// enters (the lambda exponent); directions are kept.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct EndF {
+  R NC, NH, N, S, P, dPC, dPH, p, conj, SdN;
+};
+
+template <typename R>
+__device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, int so, V3<R> rco, R rlen, R rlam,
+                        EndF<R>& e) {
+  int n = D.sn[c];
+  R NC = 0, NH = 0;
+  for (int q = 0; q < n; ++q) {
+    int k = D.sj[c * SCAP + q];
+    if (k == o) continue;
+    R w = (R)D.sw[c * SCAP + q].x;
+    if (__double2int_rn(D.x[k].w) == 0) NC += w; else NH += w;
+  }
+  R N = NC + NH;
+  R S = 0, conj = 0, SdN = 0;
+  for (int q = 0; q < n; ++q) {
+    int k = D.sj[c * SCAP + q];
+    if (k == o) continue;
+    int sk = __double2int_rn(D.x[k].w);
+    R r;
+    V3<R> d = nbr_vec<R>(D, c, q, r);
+    R w = (R)D.sw[c * SCAP + q].x;
+    R cth = dot(rco, d) / (rlen * r);
+    R dgc, dgN;
+    R g = gfun(P, sc, cth, N, dgc, dgN);
+    R el = 1;
+    if (sc == 1) el = xexp((R)P.lambda_pref * (((R)P.rho[sk] - r) - ((R)P.rho[so] - rlam)));
+    S += w * g * el;
+    SdN += w * el * dgN;
+    if (sk == 0) {
+      R xk = (R)(D.NCt[k] + D.NHt[k]) - w;
+      R dF;
+      conj += w * cosstep(xk, P.conj_lo, P.conj_hi, dF);
+    }
+  }
+  R Pv = 0, dPC = 0, dPH = 0;
+  if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH);
+  e.NC = NC; e.NH = NH; e.N = N; e.S = S; e.P = Pv; e.dPC = dPC; e.dPH = dPH;
+  e.p = (R)1 / xsqrt((R)1 + S + Pv);
+  e.conj = conj;
+  e.SdN = SdN;
+}
+
+// Reverse pass of one end.  Gp = dE/dp, GN = dE/dN_co from outside the end,
+// Gconj = dE/d(conjugation sum of this end).  Returns dE/dr_co in gco.
+template <typename R>
+__device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, int so, V3<R> rco, R rlen, R rlam,
+                        bool bstar, const EndF<R>& e, R Gp, R GN, R Gconj, V3<R>& gco, Acc& acc) {
+  int n = D.sn[c];
+  R GS = (R)-0.5 * e.p * e.p * e.p * Gp;
+  R GNt = GN + GS * e.SdN;
+  R GNC = GS * e.dPC + GNt, GNH = GS * e.dPH + GNt;
+  R Grlen = 0;
+  for (int q = 0; q < n; ++q) {
+    int k = D.sj[c * SCAP + q];
+    if (k == o) continue;
+    int sk = __double2int_rn(D.x[k].w);
+    R r;
+    V3<R> d = nbr_vec<R>(D, c, q, r);
+    double2 wd = D.sw[c * SCAP + q];
+    R w = (R)wd.x, dw = (R)wd.y;
+    R inv = (R)1 / (rlen * r);
+    R cth = dot(rco, d) * inv;
+    R dgc, dgN;
+    R g = gfun(P, sc, cth, e.N, dgc, dgN);
+    R el = 1;
+    R Gr = 0;
+    if (sc == 1) {
+      el = xexp((R)P.lambda_pref * (((R)P.rho[sk] - r) - ((R)P.rho[so] - rlam)));
+      R Gl = GS * w * g * el * (R)P.lambda_pref;
+      Gr -= Gl;
+      if (!bstar) Grlen += Gl;
+    }
+    R Gw = GS * g * el + (sk == 0 ? GNC : GNH);
+    R Gcos = GS * w * el * dgc;
+    if (sk == 0) {
+      R xk = (R)(D.NCt[k] + D.NHt[k]) - w;
+      R dF;
+      R Fv = cosstep(xk, P.conj_lo, P.conj_hi, dF);
+      Gw += Gconj * Fv;
+      R Gx = Gconj * w * dF;
+      if (Gx != (R)0) {
+        int nk = D.sn[k];
+        for (int u = 0; u < nk; ++u) {
+          int m = D.sj[k * SCAP + u];
+          if (m == c) continue;
+          R rm;
+          V3<R> dm = nbr_vec<R>(D, k, u, rm);
+          R dwm = (R)D.sw[k * SCAP + u].y;
+          if (dwm != (R)0) acc.vec(k, m, dm, (Gx * dwm / rm) * dm);
+        }
+      }
+    }
+    Gr += Gw * dw;
+    V3<R> gk = (Gr / r) * d + Gcos * (inv * rco - (cth / (r * r)) * d);
+    gco = gco + Gcos * (inv * d - (cth / (rlen * rlen)) * rco);
+    acc.vec(c, k, d, gk);
+  }
+  gco = gco + (Grlen / rlen) * rco;
+}
+
+// Dihedral loop over k in N(i)\{j}, l in N(j)\{i,k} of a C-C bond: forward
+// sums of the pi^dh term (1 - cos^2) w_ik w_jl s_i s_j and of the torsion
+// energy w_ik w_ij w_jl s_i s_j V(omega); with rev, the reverse pass given
+// GSdh = dE/d(sum) and the torsion's own derivatives.
+template <typename R>
+__device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, R wij, bool tors, bool rev,
+                         R GSdh, R& Sdh, R& Et, V3<R>& gij, R& Gwij, Acc& acc) {
+  int ni = D.sn[i], nj = D.sn[j];
+  V3<R> rji = -rij;
+  for (int q = 0; q < ni; ++q) {
+    int k = D.sj[i * SCAP + q];
+    if (k == j) continue;
+    R rik_l;
+    V3<R> rik = nbr_vec<R>(D, i, q, rik_l);
+    double2 wdk = D.sw[i * SCAP + q];
+    R wik = (R)wdk.x, dwik = (R)wdk.y;
+    R ci = dot(rij, rik) / (r * rik_l);
+    R dgi;
+    R gi = guard(P, ci, dgi);
+    if (gi == (R)0) continue;
+    V3<R> a = cross(rij, rik);
+    R na2 = dot(a, a);
+    int sk = __double2int_rn(D.x[k].w);
+    for (int u = 0; u < nj; ++u) {
+      int l = D.sj[j * SCAP + u];
+      if (l == i || l == k) continue;
+      R rjl_l;
+      V3<R> rjl = nbr_vec<R>(D, j, u, rjl_l);
+      double2 wdl = D.sw[j * SCAP + u];
+      R wjl = (R)wdl.x, dwjl = (R)wdl.y;
+      R cj = dot(rji, rjl) / (r * rjl_l);
+      R dgj;
+      R gj = guard(P, cj, dgj);
+      if (gj == (R)0) continue;
+      V3<R> b = cross(rij, rjl);
+      R nb2 = dot(b, b);
+      R inab = (R)1 / xsqrt(na2 * nb2);
+      R cw = dot(a, b) * inab;
+      R ww = wik * wjl * gi * gj;
+      Sdh += ((R)1 - cw * cw) * ww;
+      R V = 0, dV = 0;
+      if (tors) {
+        int sl = __double2int_rn(D.x[l].w);
+        R eps = (R)P.tors_eps[sk + sl];
+        R h = (R)0.5 * ((R)1 + cw);
+        R h2 = h * h, h4 = h2 * h2;
+        V = eps * ((R)(256.0 / 405.0) * h4 * h - (R)0.1);
+        dV = eps * (R)(256.0 / 405.0 * 2.5) * h4;
+        Et += wij * ww * V;
+      }
+      if (!rev) continue;
+      R Gc = GSdh * (R)-2 * cw * ww + wij * ww * dV;
+      R Gww = GSdh * ((R)1 - cw * cw) + wij * V;
+      Gwij += ww * V;
+      R Gwik = Gww * wjl * gi * gj, Gwjl = Gww * wik * gi * gj;
+      R Gci = Gww * wik * wjl * gj * dgi, Gcj = Gww * wik * wjl * gi * dgj;
+      V3<R> Ga = Gc * (inab * b - (cw / na2) * a);
+      V3<R> Gb = Gc * (inab * a - (cw / nb2) * b);
+      R iik = (R)1 / (r * rik_l), ijl = (R)1 / (r * rjl_l);
+      V3<R> gik = cross(Ga, rij) + (Gwik * dwik / rik_l) * rik + Gci * (iik * rij - (ci / (rik_l * rik_l)) * rik);
+      V3<R> gjl = cross(Gb, rij) + (Gwjl * dwjl / rjl_l) * rjl + Gcj * (ijl * rji - (cj / (rjl_l * rjl_l)) * rjl);
+      gij = gij + cross(rik, Ga) + cross(rjl, Gb) + Gci * (iik * rik - (ci / (r * r)) * rij);
+      gij = gij - Gcj * (ijl * rjl - (cj / (r * r)) * rji);
+      acc.vec(i, k, rik, gik);
+      acc.vec(j, l, rjl, gjl);
+    }
+  }
+}
+
+// Complete bond order (value and, with rev, its reverse pass for dE/db = Gb).
+template <typename R>
+__device__ R bond_order(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar, bool rev, R Gb,
+                        V3<R>& gij, Acc& acc) {
+  int si = __double2int_rn(D.x[i].w), sj = __double2int_rn(D.x[j].w);
+  int p = si + sj;
+  R rlam = (bstar && P.bstar_use_R1) ? (R)P.R1[p] : r;
+  EndF<R> ei, ej;
+  V3<R> rji = -rij;
+  end_fwd(P, D, i, si, j, sj, rij, r, rlam, ei);
+  end_fwd(P, D, j, sj, i, si, rji, r, rlam, ej);
+  R Nconj = (R)1 + ei.conj * ei.conj + ej.conj * ej.conj;
+  R dFa, dFb, dFc;
+  R pirc;
+  bool swap = (p == 1 && si == 1);   // C-H table takes the carbon side first
+  int tF = p == 0 ? TRI_FCC : (p == 1 ? TRI_FCH : TRI_FHH);
+  R Fij, Fji;
+  if (!swap) { pirc = tricubic(P, tF, ei.N, ej.N, Nconj, dFa, dFb, dFc); Fij = dFa; Fji = dFb; }
+  else { pirc = tricubic(P, tF, ej.N, ei.N, Nconj, dFa, dFb, dFc); Fij = dFb; Fji = dFa; }
+  R Tv = 0, dTa = 0, dTb = 0, dTc = 0, Sdh = 0, Et = 0, Gwij = 0;
+  bool dh = false;
+  if (p == 0) {
+    Tv = tricubic(P, TRI_TCC, ei.N, ej.N, Nconj, dTa, dTb, dTc);
+    dh = Tv != (R)0 || dTa != (R)0 || dTb != (R)0 || dTc != (R)0;
+    if (dh) { V3<R> dummy = {0, 0, 0}; dihedral(P, D, i, j, rij, r, (R)0, false, false, (R)0, Sdh, Et, dummy, Gwij, acc); }
+  }
+  R b = (R)0.5 * (ei.p + ej.p) + pirc + Tv * Sdh;
+  if (!rev) return b;
+  R GNij = Gb * (Fij + Sdh * dTa), GNji = Gb * (Fji + Sdh * dTb), GNc = Gb * (dFc + Sdh * dTc);
+  if (dh) {
+    R s2 = 0;
+    dihedral(P, D, i, j, rij, r, (R)0, false, true, Gb * Tv, s2, Et, gij, Gwij, acc);
+  }
+  V3<R> gi = {0, 0, 0}, gj = {0, 0, 0};
+  end_rev(P, D, i, si, j, sj, rij, r, rlam, bstar, ei, (R)0.5 * Gb, GNij, GNc * (R)2 * ei.conj, gi, acc);
+  end_rev(P, D, j, sj, i, si, rji, r, rlam, bstar, ej, (R)0.5 * Gb, GNji, GNc * (R)2 * ej.conj, gj, acc);
+  gij = gij + gi - gj;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: neighbour lists
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int cell_coord(double x, double invL, int nc) {
+  int c = (int)floor(x * invL * nc);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+// Load positions (wrapping periodic dims), reset cell counters.
+__global__ void k_load(Dev D, const double* __restrict__ pos, const int* __restrict__ spec, int wrap_only) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double4 x;
+  if (wrap_only) {
+    x = D.x[i];
+  } else {
+    x = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], (double)spec[i]);
+    if (spec[i] != 0 && spec[i] != 1) atomicOr(D.flags, F_BADSPEC);
+  }
+  double* xc = &x.x;
+  for (int c = 0; c < 3; ++c) {
+    if (!isfinite(xc[c])) atomicOr(D.flags, F_NONFINITE);
+    if (D.per[c]) {
+      xc[c] -= D.L[c] * floor(xc[c] * D.invL[c]);
+      if (xc[c] >= D.L[c]) xc[c] -= D.L[c];
+      if (xc[c] < 0) xc[c] = 0;
+    }
+  }
+  D.x[i] = x;
+}
+
+__global__ void k_bin(Dev D) {
+  if (!(*D.flags & F_REBUILD)) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double4 x = D.x[i];
+  double* xc = &x.x;
+  for (int c = 0; c < 3; ++c) {
+    if (D.per[c]) {
+      xc[c] -= D.L[c] * floor(xc[c] * D.invL[c]);
+      if (xc[c] >= D.L[c]) xc[c] -= D.L[c];
+      if (xc[c] < 0) xc[c] = 0;
+    }
+  }
+  D.x[i] = x;
+  D.xref[i] = x;
+  int c = (cell_coord(x.x, D.invL[0], D.nc[0]) * D.nc[1] + cell_coord(x.y, D.invL[1], D.nc[1])) * D.nc[2] +
+          cell_coord(x.z, D.invL[2], D.nc[2]);
+  D.cell_of[i] = c;
+  atomicAdd(&D.cell_count[c], 1);
+}
+
+// Exclusive scan of cell counts (one block); resets the counts for the next build.
+__global__ void k_scan(Dev D, int ncell) {
+  if (!(*D.flags & F_REBUILD)) return;
+  __shared__ int part[1024];
+  int t = threadIdx.x, nt = blockDim.x;
+  int per = (ncell + nt - 1) / nt;
+  int lo = t * per, hi = min(ncell, lo + per);
+  int s = 0;
+  for (int c = lo; c < hi; ++c) s += D.cell_count[c];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int q = 0; q < nt; ++q) { int v = part[q]; part[q] = run; run += v; }
+  }
+  __syncthreads();
+  int run = part[t];
+  for (int c = lo; c < hi; ++c) {
+    D.cell_start[c] = run;
+    D.cell_cursor[c] = run;
+    run += D.cell_count[c];
+    D.cell_count[c] = 0;
+  }
+  if (t == 0) D.cell_start[ncell] = D.n;
+}
+
+__global__ void k_fill(Dev D) {
+  if (!(*D.flags & F_REBUILD)) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  int slot = atomicAdd(&D.cell_cursor[D.cell_of[i]], 1);
+  D.cell_atoms[slot] = i;
+}
+
+// One wavefront per atom: full LJ list (cutoff + skin, with image shift code)
+// and intermediate REBO list (R2 + skin), compacted with wave ballots.
+__global__ void k_build(Dev D, const DevParams* __restrict__ Pp) {
+  if (!(*D.flags & F_REBUILD)) return;
+  int lane = threadIdx.x & (WAVE - 1);
+  int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  if (i >= D.n) return;
+  double4 xi = D.x[i];
+  int si = __double2int_rn(xi.w);
+  int ci[3] = {cell_coord(xi.x, D.invL[0], D.nc[0]), cell_coord(xi.y, D.invL[1], D.nc[1]),
+               cell_coord(xi.z, D.invL[2], D.nc[2])};
+  int nlj = 0, nin = 0;
+  unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+  for (int o = 0; o < 27; ++o) {
+    int off[3] = {o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1};
+    int cc[3], sh[3];
+    bool skip = false;
+    for (int c = 0; c < 3; ++c) {
+      int t = ci[c] + off[c];
+      if (D.per[c]) {
+        sh[c] = t < 0 ? -1 : (t >= D.nc[c] ? 1 : 0);
+        cc[c] = t - sh[c] * D.nc[c];
+        if (cc[c] < 0 || cc[c] >= D.nc[c]) skip = true;   // nc == 1 wraps once only
+      } else {
+        sh[c] = 0;
+        cc[c] = t;
+        if (t < 0 || t >= D.nc[c]) skip = true;
+      }
+    }
+    if (skip) continue;
+    int cell = (cc[0] * D.nc[1] + cc[1]) * D.nc[2] + cc[2];
+    int start = D.cell_start[cell], cnt = D.cell_start[cell + 1] - start;
+    unsigned code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
+    double shx = sh[0] * D.L[0], shy = sh[1] * D.L[1], shz = sh[2] * D.L[2];
+    for (int base = 0; base < cnt; base += WAVE) {
+      int idx = base + lane;
+      bool ok_lj = false, ok_in = false;
+      int j = -1;
+      if (idx < cnt) {
+        j = D.cell_atoms[start + idx];
+        double4 xj = D.x[j];
+        double dx = xj.x + shx - xi.x, dy = xj.y + shy - xi.y, dz = xj.z + shz - xi.z;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        int p = si + __double2int_rn(xj.w);
+        bool self = (j == i) && code == 13;
+        ok_lj = !self && r2 < D.rlist2[p];
+        ok_in = !self && r2 < D.rint2[p];
+      }
+      unsigned long long m = __ballot(ok_lj);
+      if (ok_lj) {
+        int pos = nlj + __popcll(m & below);
+        if (pos < D.lj_cap) D.lj_e[(size_t)i * D.lj_cap + pos] = (unsigned)j | (code << 27);
+      }
+      nlj += __popcll(m);
+      m = __ballot(ok_in);
+      if (ok_in) {
+        int pos = nin + __popcll(m & below);
+        if (pos < ICAP) D.in_e[i * ICAP + pos] = j;
+      }
+      nin += __popcll(m);
+    }
+  }
+  if (lane == 0) {
+    D.lj_n[i] = min(nlj, D.lj_cap);
+    D.in_n[i] = min(nin, ICAP);
+    if (nlj > D.lj_cap) atomicOr(D.flags, F_OV_LJ);
+    if (nin > ICAP) atomicOr(D.flags, F_OV_INT);
+    atomicMax(&D.stats[S_MAXLJ], (unsigned long long)nlj);
+  }
+}
+
+__global__ void k_build_done(Dev D) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && (*D.flags & F_REBUILD)) {
+    atomicAnd(D.flags, ~F_REBUILD);
+    D.stats[S_REBUILD] += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: per-step force evaluation
+// ---------------------------------------------------------------------------
+__global__ void k_zero(Dev D) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = t; k < 3 * D.n; k += gridDim.x * blockDim.x) D.F[k] = 0;
+  if (t < A_N) D.acc[t] = 0;
+  if (t < 3) D.bcount[t] = 0;
+  if (t == 0) *D.qcount = 0;
+}
+
+__device__ __forceinline__ void minimg(const Dev& D, double& dx, double& dy, double& dz) {
+  if (D.per[0]) dx -= D.L[0] * rint(dx * D.invL[0]);
+  if (D.per[1]) dy -= D.L[1] * rint(dy * D.invL[1]);
+  if (D.per[2]) dz -= D.L[2] * rint(dz * D.invL[2]);
+}
+
+// Exact short list, weights and coordination; species-bucketed bond list.
+__global__ void k_short(Dev D, const DevParams* __restrict__ Pp) {
+  const DevParams& P = *Pp;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double4 xi = D.x[i];
+  int si = __double2int_rn(xi.w);
+  int m = D.in_n[i], cnt = 0;
+  double NC = 0, NH = 0;
+  for (int e = 0; e < m; ++e) {
+    int j = D.in_e[i * ICAP + e];
+    double4 xj = D.x[j];
+    double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    minimg(D, dx, dy, dz);
+    double r2 = dx * dx + dy * dy + dz * dz;
+    int sj = __double2int_rn(xj.w);
+    int p = si + sj;
+    if (r2 >= P.R2[p] * P.R2[p]) continue;
+    double r = sqrt(r2), dw;
+    double w = cutw<double>(P, p, r, dw);
+    if (sj == 0) NC += w; else NH += w;
+    if (cnt < SCAP) {
+      D.sj[i * SCAP + cnt] = j;
+      D.sd[i * SCAP + cnt] = make_double4(dx, dy, dz, r);
+      D.sw[i * SCAP + cnt] = make_double2(w, dw);
+      if (j > i) {
+        int b = atomicAdd(&D.bcount[p], 1);
+        if (b < D.bcap) D.bonds[p * D.bcap + b] = make_int2(i, cnt);
+        else atomicOr(D.flags, F_OV_BOND);
+      }
+    }
+    ++cnt;
+  }
+  if (cnt > SCAP) atomicOr(D.flags, F_OV_SHORT);
+  D.sn[i] = min(cnt, SCAP);
+  D.NCt[i] = NC;
+  D.NHt[i] = NH;
+  atomicMax(&D.stats[S_MAXSHORT], (unsigned long long)cnt);
+}
+
+// Path map of each atom: every atom reachable over at most three short bonds
+// (no atom repeated), keeping the largest weight product and its path.
+__global__ void k_pathmap(Dev D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  int cnt = 0;
+  bool over = false;
+  int* A = D.pm_atom + (size_t)i * PCAP;
+  double* W = D.pm_prod + (size_t)i * PCAP;
+  int* C = D.pm_code + (size_t)i * PCAP;
+  auto insert = [&](int a, double w, int code) {
+    if (w <= 0.0) return;
+    for (int e = 0; e < cnt; ++e)
+      if (A[e] == a) {
+        if (w > W[e]) { W[e] = w; C[e] = code; }
+        return;
+      }
+    if (cnt < PCAP) { A[cnt] = a; W[cnt] = w; C[cnt] = code; ++cnt; }
+    else over = true;
+  };
+  int n1 = D.sn[i];
+  for (int q1 = 0; q1 < n1; ++q1) {
+    int k = D.sj[i * SCAP + q1];
+    double w1 = D.sw[i * SCAP + q1].x;
+    insert(k, w1, 1 | (q1 << 2));
+    int n2 = D.sn[k];
+    for (int q2 = 0; q2 < n2; ++q2) {
+      int m = D.sj[k * SCAP + q2];
+      if (m == i) continue;
+      double w2 = w1 * D.sw[k * SCAP + q2].x;
+      insert(m, w2, 2 | (q1 << 2) | (q2 << 5));
+      int n3 = D.sn[m];
+      for (int q3 = 0; q3 < n3; ++q3) {
+        int t = D.sj[m * SCAP + q3];
+        if (t == i || t == k) continue;
+        insert(t, w2 * D.sw[m * SCAP + q3].x, 3 | (q1 << 2) | (q2 << 5) | (q3 << 8));
+      }
+    }
+  }
+  D.pm_n[i] = cnt;
+  if (over) atomicOr(D.flags, F_OV_PATH);
+  atomicMax(&D.stats[S_MAXPATH], (unsigned long long)cnt);
+}
+
+// Atoms and bond slots along a path code starting at atom i.
+struct PathInfo { int len; int at[4]; int slot[3]; };
+__device__ __forceinline__ PathInfo decode_path(const Dev& D, int i, int code) {
+  PathInfo pi;
+  pi.len = code & 3;
+  pi.at[0] = i;
+  int a = i;
+  for (int b = 0; b < pi.len; ++b) {
+    int s = (code >> (2 + 3 * b)) & 7;
+    pi.slot[b] = s;
+    a = D.sj[a * SCAP + s];
+    pi.at[b + 1] = a;
+  }
+  return pi;
+}
+
+// Gradient of E with respect to the path bonds, given dE/dprod.  `half`
+// halves the contribution to every atom except the path start (full-list LJ
+// visits each pair from both ends).
+template <typename R>
+__device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_all, double scale_start, Acc& acc) {
+  R w[3], dw[3], rl[3];
+  V3<R> rv[3];
+  for (int b = 0; b < pi.len; ++b) {
+    int a = pi.at[b], s = pi.slot[b];
+    rv[b] = nbr_vec<R>(D, a, s, rl[b]);
+    double2 wd = D.sw[a * SCAP + s];
+    w[b] = (R)wd.x;
+    dw[b] = (R)wd.y;
+  }
+  for (int b = 0; b < pi.len; ++b) {
+    if (dw[b] == (R)0) continue;
+    R others = 1;
+    for (int c = 0; c < pi.len; ++c) if (c != b) others *= w[c];
+    V3<R> g = (GP * others * dw[b] / rl[b]) * rv[b];
+    double gx = g.x, gy = g.y, gz = g.z;
+    int a = pi.at[b], c = pi.at[b + 1];
+    double sa = (b == 0) ? scale_start : scale_all;
+    acc.force(a, sa * gx, sa * gy, sa * gz);
+    if (b + 1 < pi.len || scale_all == 1.0) acc.force(c, -scale_all * gx, -scale_all * gy, -scale_all * gz);
+    double rx = rv[b].x, ry = rv[b].y, rz = rv[b].z;
+    acc.W[0] -= scale_all * rx * gx; acc.W[1] -= scale_all * ry * gy; acc.W[2] -= scale_all * rz * gz;
+    acc.W[3] -= scale_all * rx * gy; acc.W[4] -= scale_all * rx * gz; acc.W[5] -= scale_all * ry * gz;
+  }
+}
+
+// REBO pair + bond order + torsion, one lane per bond (Alg. 1 and 2 merged).
+template <typename R>
+__global__ void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
+  const DevParams& P = *Pp;
+  int n0 = D.bcount[0], n1 = D.bcount[1], n2 = D.bcount[2];
+  n0 = min(n0, D.bcap); n1 = min(n1, D.bcap); n2 = min(n2, D.bcap);
+  int total = n0 + n1 + n2;
+  double er = 0, et = 0;
+  Acc acc;
+  acc.init(D.F, -1, -1);
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+    int seg = g < n0 ? 0 : (g < n0 + n1 ? 1 : 2);
+    int off = g - (seg == 0 ? 0 : (seg == 1 ? n0 : n0 + n1));
+    int2 bq = D.bonds[seg * D.bcap + off];
+    int i = bq.x, slot = bq.y;
+    int j = D.sj[i * SCAP + slot];
+    R r;
+    V3<R> rij = nbr_vec<R>(D, i, slot, r);
+    double2 wd = D.sw[i * SCAP + slot];
+    R wij = (R)wd.x, dwij = (R)wd.y;
+    int p = seg;
+    acc.i = i; acc.j = j;
+    for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
+    V3<R> gij = {0, 0, 0};
+    R Gr = 0;
+    if (mask & AIREBO_TERM_REBO) {
+      R ea = (R)P.alpha[p];
+      R eR = xexp(-ea * r) * (R)P.A[p];
+      R VR = ((R)1 + (R)P.Q[p] / r) * eR;
+      R dVR = -((R)P.Q[p] / (r * r)) * eR - ea * VR;
+      R VA = 0, dVA = 0;
+      for (int m = 0; m < 3; ++m) {
+        if (P.B[p][m] == 0.0) continue;
+        R t = (R)P.B[p][m] * xexp(-(R)P.beta[p][m] * r);
+        VA += t;
+        dVA -= (R)P.beta[p][m] * t;
+      }
+      R Gb = -wij * VA;
+      R b = bond_order(P, D, i, j, rij, r, false, true, Gb, gij, acc);
+      er += (double)(wij * (VR - b * VA));
+      Gr += dwij * (VR - b * VA) + wij * (dVR - b * dVA);
+    }
+    if ((mask & AIREBO_TERM_TORSION) && p == 0) {
+      R Sdh = 0, Et = 0, Gwij = 0;
+      dihedral(P, D, i, j, rij, r, wij, true, true, (R)0, Sdh, Et, gij, Gwij, acc);
+      et += (double)Et;
+      Gr += Gwij * dwij;
+    }
+    gij = gij + (Gr / r) * rij;
+    acc.vec(i, j, rij, gij);
+    acc.flush();
+  }
+  double v[8] = {er, et, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
+  double v1[1] = {v[0]};
+  block_reduce_add<1>(v1, D.acc + A_EREBO);
+  __syncthreads();
+  double v2[1] = {v[1]};
+  block_reduce_add<1>(v2, D.acc + A_ETORS);
+  __syncthreads();
+  double v6[6] = {v[2], v[3], v[4], v[5], v[6], v[7]};
+  block_reduce_add<6>(v6, D.acc + A_VIR);
+}
+
+__device__ __forceinline__ void lj_pair(const DevParams& P, int p, double r, double& V, double& dV) {
+  double s = P.sigma[p] / r;
+  double s2 = s * s, s6 = s2 * s2 * s2;
+  double e4 = 4.0 * P.eps[p];
+  double v = e4 * (s6 * s6 - s6);
+  double dv = e4 * (-12.0 * s6 * s6 + 6.0 * s6) / r;
+  double t = (r - (P.rc[p] - P.lj_sw)) / P.lj_sw, dS;
+  double S = Sw(t, dS);
+  V = v * S;
+  dV = dv * S + v * dS / P.lj_sw;
+}
+
+// LJ term (Alg. 3), one wavefront per atom over its full list.  Each pair is
+// seen from both ends: each end adds half the energy and virial, the full
+// force on its own atom and half the force on intermediate path atoms.
+__global__ void k_lj(Dev D, const DevParams* __restrict__ Pp) {
+  const DevParams& P = *Pp;
+  int lane = threadIdx.x & (WAVE - 1);
+  int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  double e = 0;
+  Acc acc;
+  acc.init(D.F, i < D.n ? i : -1, -1);
+  unsigned long long n_in = 0, n_c0 = 0;
+  if (i < D.n) {
+    double4 xi = D.x[i];
+    int si = __double2int_rn(xi.w);
+    int npm = D.pm_n[i];
+    const int* PA = D.pm_atom + (size_t)i * PCAP;
+    int nl = D.lj_n[i];
+    for (int e0 = lane; e0 < nl; e0 += WAVE) {
+      unsigned ent = D.lj_e[(size_t)i * D.lj_cap + e0];
+      int j = (int)(ent & 0x7FFFFFFu);
+      int code = (int)(ent >> 27);
+      double4 xj = D.x[j];
+      double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
+      double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * D.L[1];
+      double dz = xj.z - xi.z + (code % 3 - 1) * D.L[2];
+      double r2 = dx * dx + dy * dy + dz * dz;
+      int p = si + __double2int_rn(xj.w);
+      if (r2 >= P.rc2[p]) continue;
+      double r = sqrt(r2);
+      if (i < j) ++n_in;
+      double V, dV;
+      lj_pair(P, p, r, V, dV);
+      double C = 1.0;
+      int pcode = 0;
+      if (r < P.r_conn) {
+        double prod = 0.0;
+        for (int m = 0; m < npm; ++m)
+          if (PA[m] == j) { prod = D.pm_prod[(size_t)i * PCAP + m]; pcode = D.pm_code[(size_t)i * PCAP + m]; break; }
+        if (prod >= 1.0) { if (i < j) ++n_c0; continue; }
+        C = 1.0 - prod;
+        if (r < P.rljmax[p]) {
+          if (i < j) {
+            int slot = atomicAdd(D.qcount, 1);
+            if (slot < D.qcap) D.q[slot] = make_int4(i, j, code, pcode);
+            else atomicOr(D.flags, F_OV_QUEUE);
+          }
+          continue;
+        }
+        if (prod > 0.0) {
+          PathInfo pi = decode_path(D, i, pcode);
+          path_grad<double>(D, pi, -V, 0.5, 1.0, acc);
+        }
+      }
+      e += 0.5 * C * V;
+      double g = C * dV / r;    // dE/dr_ij vector = g * d
+      acc.fi[0] += g * dx; acc.fi[1] += g * dy; acc.fi[2] += g * dz;
+      acc.W[0] -= 0.5 * g * dx * dx; acc.W[1] -= 0.5 * g * dy * dy; acc.W[2] -= 0.5 * g * dz * dz;
+      acc.W[3] -= 0.5 * g * dx * dy; acc.W[4] -= 0.5 * g * dx * dz; acc.W[5] -= 0.5 * g * dy * dz;
+    }
+  }
+  // reduce the force on atom i across the wavefront
+  for (int c = 0; c < 3; ++c) {
+    double s = acc.fi[c];
+    for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && i < D.n && s != 0) atomic_add(&D.F[3 * i + c], s);
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    n_in += __shfl_xor(n_in, o);
+    n_c0 += __shfl_xor(n_c0, o);
+  }
+  if (lane == 0 && n_in) atomicAdd(&D.stats[S_INCUT], n_in);
+  if (lane == 0 && n_c0) atomicAdd(&D.stats[S_CIJ0], n_c0);
+  double v1[1] = {e};
+  block_reduce_add<1>(v1, D.acc + A_ELJ);
+  __syncthreads();
+  double v6[6] = {acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
+  block_reduce_add<6>(v6, D.acc + A_VIR);
+}
+
+// Deferred LJ pairs inside the S_r range: b*, S_b and the full gradient.
+template <typename R>
+__global__ void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
+  const DevParams& P = *Pp;
+  int nq = min(*D.qcount, D.qcap);
+  double e = 0;
+  Acc acc;
+  acc.init(D.F, -1, -1);
+  unsigned long long ndsb = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += gridDim.x * blockDim.x) {
+    int4 qe = D.q[t];
+    int i = qe.x, j = qe.y, code = qe.z, pcode = qe.w;
+    double4 xi = D.x[i], xj = D.x[j];
+    double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
+    double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * D.L[1];
+    double dz = xj.z - xi.z + (code % 3 - 1) * D.L[2];
+    int p = __double2int_rn(xi.w) + __double2int_rn(xj.w);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    acc.i = i; acc.j = j;
+    for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
+    double V, dV;
+    lj_pair(P, p, r, V, dV);
+    double prod = 0;
+    PathInfo pi;
+    pi.len = 0;
+    if (pcode) {
+      pi = decode_path(D, i, pcode);
+      prod = 1;
+      for (int b = 0; b < pi.len; ++b) prod *= D.sw[pi.at[b] * SCAP + pi.slot[b]].x;
+    }
+    double C = 1.0 - prod;
+    double dSr;
+    double Sr = Sw((r - P.sigma[p]) * P.inv_rlj[p], dSr);
+    dSr *= P.inv_rlj[p];
+    V3<R> rij = {(R)dx, (R)dy, (R)dz};
+    V3<R> gij = {0, 0, 0};
+    R bs = bond_order(P, D, i, j, rij, (R)r, true, false, (R)0, gij, acc);
+    double inv_b = 1.0 / (P.bmax[p] - P.bmin[p]);
+    double dSb;
+    double Sb = Sw(((double)bs - P.bmin[p]) * inv_b, dSb);
+    dSb *= inv_b;
+    double Qf = Sr * Sb + 1.0 - Sr;
+    e += Qf * C * V;
+    double Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
+    if (dSb != 0.0) {
+      ++ndsb;
+      R Gb = (R)(Sr * dSb * C * V);
+      bond_order(P, D, i, j, rij, (R)r, true, true, Gb, gij, acc);
+    }
+    if (prod > 0.0) path_grad<double>(D, pi, -Qf * V, 1.0, 1.0, acc);
+    gij = gij + (R)(Gr / r) * rij;
+    acc.vec(i, j, rij, gij);
+    acc.flush();
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) ndsb += __shfl_xor(ndsb, o);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && ndsb) atomicAdd(&D.stats[S_DSB], ndsb);
+  double v1[1] = {e};
+  block_reduce_add<1>(v1, D.acc + A_ELJ);
+  __syncthreads();
+  double v6[6] = {acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
+  block_reduce_add<6>(v6, D.acc + A_VIR);
+}
+
+__global__ void k_finish(Dev D, double* energy, double* virial) {
+  int t = threadIdx.x;
+  if (t == 0) {
+    energy[1] = D.acc[A_EREBO];
+    energy[2] = D.acc[A_ELJ];
+    energy[3] = D.acc[A_ETORS];
+    energy[0] = D.acc[A_EREBO] + D.acc[A_ELJ] + D.acc[A_ETORS];
+    D.stats[S_BSTAR] = (unsigned long long)min(*D.qcount, D.qcap);
+    D.stats[S_BONDS] = (unsigned long long)(D.bcount[0] + D.bcount[1] + D.bcount[2]);
+    if (!isfinite(energy[0])) atomicOr(D.flags, F_NONFINITE);
+  }
+  if (t < 6) virial[t] = D.acc[A_VIR + t];
+}
+
+// ---------------------------------------------------------------------------
+// Velocity Verlet
+// ---------------------------------------------------------------------------
+constexpr double FTM = 1.0 / 103.642691;   // eV / (A amu) -> A / fs^2
+constexpr double KB = 8.617333262e-5;
+
+__global__ void k_kick_drift(Dev D, double* vel, double m0, double m1, double dt, double half_skin2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double4 x = D.x[i];
+  double im = FTM / (__double2int_rn(x.w) == 0 ? m0 : m1);
+  double v[3];
+  for (int c = 0; c < 3; ++c) v[c] = vel[3 * i + c] + 0.5 * dt * D.F[3 * i + c] * im;
+  x.x += dt * v[0]; x.y += dt * v[1]; x.z += dt * v[2];
+  for (int c = 0; c < 3; ++c) vel[3 * i + c] = v[c];
+  D.x[i] = x;
+  double4 xr = D.xref[i];
+  double ddx = x.x - xr.x, ddy = x.y - xr.y, ddz = x.z - xr.z;
+  if (ddx * ddx + ddy * ddy + ddz * ddz > half_skin2) atomicOr(D.flags, F_REBUILD);
+}
+
+__global__ void k_kick(Dev D, double* vel, double m0, double m1, double dt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double ke = 0;
+  if (i < D.n) {
+    double m = __double2int_rn(D.x[i].w) == 0 ? m0 : m1;
+    double im = FTM / m;
+    for (int c = 0; c < 3; ++c) {
+      double v = vel[3 * i + c] + 0.5 * dt * D.F[3 * i + c] * im;
+      vel[3 * i + c] = v;
+      ke += 0.5 * m * v * v / FTM;
+    }
+  }
+  double v1[1] = {ke};
+  block_reduce_add<1>(v1, D.acc + A_KE);
+}
+
+__global__ void k_thermo(Dev D, double* thermo, int every, int nrows) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int s = *D.step;
+  if (thermo && every > 0 && s % every == 0 && s / every < nrows) {
+    double* row = thermo + 6 * (s / every);
+    double pe = D.acc[A_EREBO] + D.acc[A_ELJ] + D.acc[A_ETORS];
+    double ke = D.acc[A_KE];
+    row[0] = s;
+    row[1] = pe;
+    row[2] = ke;
+    row[3] = pe + ke;
+    row[4] = D.n > 1 ? 2.0 * ke / ((3.0 * D.n - 3.0) * KB) : 0.0;
+    row[5] = (double)D.stats[S_REBUILD];
+  }
+  *D.step = s + 1;
+}
+
+__global__ void k_store(Dev D, double* pos) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double4 x = D.x[i];
+  pos[3 * i] = x.x; pos[3 * i + 1] = x.y; pos[3 * i + 2] = x.z;
+}
+
+__global__ void k_set_flags(Dev D, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *D.flags = v;
+}
+
+}  // namespace airebo
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+using namespace airebo;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(AIREBO_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_) + " (" + \
+                                       std::to_string((int)e_) + ")");                         \
+  } while (0)
+
+template <typename T>
+int grow(T*& p, size_t& cap, size_t need) {
+  if (need <= cap && p) return 0;
+  if (p) hipFree(p);
+  p = nullptr;
+  size_t c = std::max<size_t>(need, 1);
+  hipError_t e = hipMalloc((void**)&p, c * sizeof(T));
+  if (e != hipSuccess) { cap = 0; return fail(AIREBO_E_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+  cap = c;
+  return 0;
+}
+}  // namespace
+
+struct airebo_ctx {
+  airebo_options opt;
+  DevParams P;
+  DevParams* dP = nullptr;
+  double* dtri = nullptr;
+  Dev D;
+  int64_t n = 0;
+  int lj_cap = 0;
+  // buffers and capacities
+  double4 *x = nullptr, *xref = nullptr;
+  size_t cx = 0, cxr = 0;
+  int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr, *cell_atoms = nullptr;
+  size_t c_of = 0, c_cc = 0, c_cs = 0, c_cu = 0, c_ca = 0;
+  int* lj_n = nullptr;
+  size_t c_ljn = 0;
+  unsigned* lj_e = nullptr;
+  size_t c_lje = 0;
+  int *in_n = nullptr, *in_e = nullptr, *sn = nullptr, *sj = nullptr;
+  size_t c_inn = 0, c_ine = 0, c_sn = 0, c_sj = 0;
+  double4* sd = nullptr;
+  size_t c_sd = 0;
+  double2* sw = nullptr;
+  size_t c_sw = 0;
+  double *NCt = nullptr, *NHt = nullptr;
+  size_t c_nc = 0, c_nh = 0;
+  int* bcount = nullptr;
+  size_t c_bc = 0;
+  int2* bonds = nullptr;
+  size_t c_b = 0;
+  int *pm_n = nullptr, *pm_atom = nullptr, *pm_code = nullptr;
+  size_t c_pmn = 0, c_pma = 0, c_pmc = 0;
+  double* pm_prod = nullptr;
+  size_t c_pmp = 0;
+  int* qcount = nullptr;
+  size_t c_qc = 0;
+  int4* q = nullptr;
+  size_t c_q = 0;
+  double* F = nullptr;
+  size_t c_F = 0;
+  double* acc = nullptr;
+  size_t c_acc = 0;
+  unsigned long long* stats = nullptr;
+  size_t c_st = 0;
+  int* flags = nullptr;
+  size_t c_fl = 0;
+  int* step = nullptr;
+  size_t c_stp = 0;
+  unsigned long long host_stats[S_N] = {};
+};
+
+extern "C" {
+
+const char* airebo_last_error(void) { return g_err.c_str(); }
+
+void airebo_options_default(airebo_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof *opt);
+  opt->precision = AIREBO_FP64;
+  opt->term_mask = AIREBO_TERM_ALL;
+  opt->skin = 1.0;
+  opt->lj_cap = 0;
+  opt->device = 0;
+}
+
+int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t* out) {
+  if (!path || !out) return fail(AIREBO_E_ARG, "null argument");
+  airebo_options o;
+  if (opt) o = *opt; else airebo_options_default(&o);
+  if (!(o.skin > 0.0 && o.skin < 5.0)) return fail(AIREBO_E_ARG, "skin must be in (0, 5) A");
+  if (o.precision != AIREBO_FP64 && o.precision != AIREBO_MIXED) return fail(AIREBO_E_ARG, "unknown precision");
+  if (o.term_mask < 0 || o.term_mask > 7) return fail(AIREBO_E_ARG, "bad term mask");
+  if (o.lj_cap < 0) return fail(AIREBO_E_ARG, "bad lj_cap");
+  airebo_ctx* c = new airebo_ctx();
+  c->opt = o;
+  std::vector<double> tri((size_t)TRI_N * kTriCells * kTriCoef);
+  std::string err;
+  if (!build_params(path, c->P, tri.data(), err)) { delete c; return fail(AIREBO_E_PARAMS, err); }
+  hipError_t e = hipSetDevice(o.device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->dtri, tri.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(c->dtri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
+  c->P.tri = c->dtri;
+  if (e == hipSuccess) e = hipMalloc((void**)&c->dP, sizeof(DevParams));
+  if (e == hipSuccess) e = hipMemcpy(c->dP, &c->P, sizeof(DevParams), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    std::string m = hipGetErrorString(e);
+    airebo_ctx_free(c);
+    return fail(AIREBO_E_DEVICE, "context setup: " + m);
+  }
+  *out = c;
+  return 0;
+}
+
+void airebo_ctx_free(airebo_ctx_t c) {
+  if (!c) return;
+  void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
+                  c->cell_atoms, c->lj_n, c->lj_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
+                  c->bcount, c->bonds, c->pm_n, c->pm_atom, c->pm_code, c->pm_prod, c->qcount, c->q, c->F, c->acc,
+                  c->stats, c->flags, c->step};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  delete c;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Size buffers for n atoms and the given box; fill the Dev descriptor.
+int setup(airebo_ctx* c, int64_t n, const double* box, const int32_t* per) {
+  if (n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
+  if (!box || !per) return fail(AIREBO_E_ARG, "null box or periodic");
+  const DevParams& P = c->P;
+  double rlist = P.rc_max + c->opt.skin;
+  Dev& D = c->D;
+  std::memset(&D, 0, sizeof D);
+  D.n = (int)n;
+  D.skin = c->opt.skin;
+  size_t ncell = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (!(box[d] > 0) || !std::isfinite(box[d])) return fail(AIREBO_E_BOX, "box lengths must be positive");
+    D.L[d] = box[d];
+    D.invL[d] = 1.0 / box[d];
+    D.per[d] = per[d] ? 1 : 0;
+    if (D.per[d] && box[d] < std::max({12.0, P.rc_max + c->opt.skin}))
+      return fail(AIREBO_E_BOX, "periodic box side must be at least max(12 A, LJ cutoff + skin)");
+    D.nc[d] = std::max(1, (int)std::floor(box[d] / rlist));
+    D.nc[d] = std::min(D.nc[d], 1024);
+    ncell *= D.nc[d];
+  }
+  for (int p = 0; p < 3; ++p) {
+    D.rlist2[p] = (P.rc[p] + c->opt.skin) * (P.rc[p] + c->opt.skin);
+    D.rint2[p] = (P.R2[p] + c->opt.skin) * (P.R2[p] + c->opt.skin);
+  }
+  if (c->lj_cap == 0) c->lj_cap = c->opt.lj_cap > 0 ? c->opt.lj_cap : 256;
+  size_t N = (size_t)std::max<int64_t>(n, 1);
+  int rc = 0;
+  rc |= grow(c->x, c->cx, N);
+  rc |= grow(c->xref, c->cxr, N);
+  rc |= grow(c->cell_of, c->c_of, N);
+  rc |= grow(c->cell_count, c->c_cc, ncell);
+  rc |= grow(c->cell_start, c->c_cs, ncell + 1);
+  rc |= grow(c->cell_cursor, c->c_cu, ncell);
+  rc |= grow(c->cell_atoms, c->c_ca, N);
+  rc |= grow(c->lj_n, c->c_ljn, N);
+  rc |= grow(c->lj_e, c->c_lje, N * (size_t)c->lj_cap);
+  rc |= grow(c->in_n, c->c_inn, N);
+  rc |= grow(c->in_e, c->c_ine, N * ICAP);
+  rc |= grow(c->sn, c->c_sn, N);
+  rc |= grow(c->sj, c->c_sj, N * SCAP);
+  rc |= grow(c->sd, c->c_sd, N * SCAP);
+  rc |= grow(c->sw, c->c_sw, N * SCAP);
+  rc |= grow(c->NCt, c->c_nc, N);
+  rc |= grow(c->NHt, c->c_nh, N);
+  rc |= grow(c->bcount, c->c_bc, 4);
+  size_t bcap = N * SCAP / 2 + 64;
+  rc |= grow(c->bonds, c->c_b, 3 * bcap);
+  rc |= grow(c->pm_n, c->c_pmn, N);
+  rc |= grow(c->pm_atom, c->c_pma, N * PCAP);
+  rc |= grow(c->pm_code, c->c_pmc, N * PCAP);
+  rc |= grow(c->pm_prod, c->c_pmp, N * PCAP);
+  rc |= grow(c->qcount, c->c_qc, 4);
+  size_t qcap = 4 * N + 1024;
+  rc |= grow(c->q, c->c_q, qcap);
+  rc |= grow(c->F, c->c_F, 3 * N);
+  rc |= grow(c->acc, c->c_acc, A_N + 6);
+  rc |= grow(c->stats, c->c_st, S_N);
+  rc |= grow(c->flags, c->c_fl, 4);
+  rc |= grow(c->step, c->c_stp, 4);
+  if (rc) return AIREBO_E_DEVICE;
+  D.x = c->x; D.xref = c->xref; D.cell_of = c->cell_of; D.cell_count = c->cell_count; D.cell_start = c->cell_start;
+  D.cell_cursor = c->cell_cursor; D.cell_atoms = c->cell_atoms; D.lj_cap = c->lj_cap; D.lj_n = c->lj_n;
+  D.lj_e = c->lj_e; D.in_n = c->in_n; D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
+  D.NCt = c->NCt; D.NHt = c->NHt; D.bcap = (int)bcap; D.bcount = c->bcount; D.bonds = c->bonds; D.pm_n = c->pm_n;
+  D.pm_atom = c->pm_atom; D.pm_prod = c->pm_prod; D.pm_code = c->pm_code; D.qcap = (int)qcap; D.qcount = c->qcount;
+  D.q = c->q; D.F = c->F; D.acc = c->acc; D.stats = c->stats; D.flags = c->flags; D.step = c->step;
+  return 0;
+}
+
+inline int blocks(int64_t n, int t) { return (int)std::max<int64_t>(1, (n + t - 1) / t); }
+
+// Launch the rebuild chain (kernels check the rebuild flag on the device).
+void launch_rebuild(airebo_ctx* c, hipStream_t s) {
+  Dev& D = c->D;
+  int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+  hipLaunchKernelGGL(k_bin, dim3(blocks(D.n, 256)), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, D, ncell);
+  hipLaunchKernelGGL(k_fill, dim3(blocks(D.n, 256)), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_build, dim3(blocks((int64_t)D.n * WAVE, 256)), dim3(256), 0, s, D, (const DevParams*)c->dP);
+  hipLaunchKernelGGL(k_build_done, dim3(1), dim3(64), 0, s, D);
+}
+
+// Launch one force evaluation on the current positions.
+void launch_forces(airebo_ctx* c, hipStream_t s) {
+  Dev& D = c->D;
+  const DevParams* P = c->dP;
+  int mask = c->opt.term_mask;
+  hipLaunchKernelGGL(k_zero, dim3(std::min(blocks(3 * (int64_t)D.n, 256), 4096)), dim3(256), 0, s, D);
+  hipLaunchKernelGGL(k_short, dim3(blocks(D.n, 128)), dim3(128), 0, s, D, P);
+  if (mask & (AIREBO_TERM_LJ)) hipLaunchKernelGGL(k_pathmap, dim3(blocks(D.n, 128)), dim3(128), 0, s, D);
+  int nb = std::min(blocks((int64_t)D.n * 2, 128), 8192);
+  if (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION))
+    hipLaunchKernelGGL(k_bond<double>, dim3(nb), dim3(128), 0, s, D, P, mask);
+  if (mask & AIREBO_TERM_LJ) {
+    hipLaunchKernelGGL(k_lj, dim3(blocks((int64_t)D.n * WAVE, 256)), dim3(256), 0, s, D, P);
+    hipLaunchKernelGGL(k_bstar<double>, dim3(std::min(blocks(D.n, 128), 2048)), dim3(128), 0, s, D, P);
+  }
+}
+
+int check_flags(airebo_ctx* c, int flags) {
+  if (flags & F_BADSPEC) return fail(AIREBO_E_SPECIES, "species codes must be 0 (C) or 1 (H)");
+  if (flags & F_NONFINITE) return fail(AIREBO_E_NONFINITE, "non-finite position or energy");
+  if (flags & F_OV_SHORT) return fail(AIREBO_E_CAPACITY, "an atom has more than 8 REBO neighbours");
+  if (flags & F_OV_INT) return fail(AIREBO_E_CAPACITY, "intermediate REBO list capacity exceeded");
+  if (flags & F_OV_PATH) return fail(AIREBO_E_CAPACITY, "path map capacity exceeded");
+  if (flags & F_OV_BOND) return fail(AIREBO_E_CAPACITY, "bond list capacity exceeded");
+  if (flags & F_OV_QUEUE) return fail(AIREBO_E_CAPACITY, "b* queue capacity exceeded");
+  return 0;
+}
+
+// One evaluation; forces == nullptr evaluates into the context's own buffer.
+int compute_impl(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
+                 const int32_t* periodic, double* energy, double* forces, double* virial, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->opt.device));
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    int rc = setup(c, n, box, periodic);
+    if (rc) return rc;
+    Dev& D = c->D;
+    D.F = forces ? forces : c->F;
+    HIPCHK(hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
+    HIPCHK(hipMemsetAsync(c->cell_count, 0, sizeof(int) * D.nc[0] * D.nc[1] * D.nc[2], s));
+    if (n > 0) {
+      hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
+      launch_rebuild(c, s);
+      launch_forces(c, s);
+    } else {
+      hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, D);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, D, energy, virial);
+    HIPCHK(hipGetLastError());
+    int flags = 0;
+    HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flags & F_OV_LJ) {   // grow the LJ list and evaluate again
+      c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + 64, 1u << 16);
+      continue;
+    }
+    return check_flags(c, flags);
+  }
+  return fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established");
+}
+
+}  // namespace
+
+extern "C" {
+
+int airebo_compute(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
+                   const int32_t* periodic, double* energy, double* forces, double* virial, void* stream) {
+  if (!c || (n > 0 && (!pos || !species || !forces)) || !energy || !virial) return fail(AIREBO_E_ARG, "null argument");
+  return compute_impl(c, n, pos, species, box, periodic, energy, forces, virial, stream);
+}
+
+int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species, const double* box,
+               const int32_t* periodic, const double* mass, double dt, int64_t nsteps, int64_t every,
+               double* thermo, void* stream) {
+  if (!c || (n > 0 && (!pos || !vel || !species)) || !mass) return fail(AIREBO_E_ARG, "null argument");
+  if (nsteps < 0 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0)) return fail(AIREBO_E_ARG, "bad step count, dt or mass");
+  if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(c->opt.device));
+  if (n == 0) return 0;
+  // establish list capacity with a plain evaluation first
+  double *e4 = nullptr, *w6 = nullptr;
+  HIPCHK(hipMalloc((void**)&e4, 16 * sizeof(double)));
+  w6 = e4 + 8;
+  int rc = compute_impl(c, n, pos, species, box, periodic, e4, nullptr, w6, stream);
+  if (rc) { hipFree(e4); return rc; }
+  // headroom for list growth between rebuilds
+  c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32, 1u << 16);
+  rc = setup(c, n, box, periodic);
+  if (rc) { hipFree(e4); return rc; }
+  Dev& D = c->D;
+  D.F = c->F;
+  int nrows = every > 0 ? (int)(nsteps / every) + 1 : 0;
+  double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
+  int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+  hipError_t err = hipSuccess;
+  auto body = [&](bool first) {
+    if (first) {
+      hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
+      hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s);
+      hipMemsetAsync(c->cell_count, 0, sizeof(int) * ncell, s);
+      hipMemsetAsync(c->step, 0, sizeof(int), s);
+      hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
+      launch_rebuild(c, s);
+      launch_forces(c, s);
+      // kinetic energy of the initial state (zero-length kick)
+      hipLaunchKernelGGL(k_kick, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], 0.0);
+      hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
+      return;
+    }
+    hipLaunchKernelGGL(k_kick_drift, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], dt, half_skin2);
+    launch_rebuild(c, s);
+    launch_forces(c, s);
+    hipLaunchKernelGGL(k_kick, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], dt);
+    hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
+  };
+  body(true);
+  // capture one step into a graph and replay it
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;
+  err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (err == hipSuccess) {
+    hipStream_t keep = s;
+    s = cs;
+    body(false);
+    s = keep;
+    err = hipStreamEndCapture(cs, &graph);
+  }
+  if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) err = hipGraphLaunch(exec, cs);
+  if (err == hipSuccess) err = hipStreamSynchronize(cs);
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (cs) hipStreamDestroy(cs);
+  if (err != hipSuccess) { hipFree(e4); return fail(AIREBO_E_DEVICE, std::string("nve: ") + hipGetErrorString(err)); }
+  hipLaunchKernelGGL(k_store, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos);
+  int flags = 0;
+  HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  hipFree(e4);
+  if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded during NVE");
+  return check_flags(c, flags);
+}
+
+int airebo_stats(airebo_ctx_t c, int64_t* out) {
+  if (!c || !out) return fail(AIREBO_E_ARG, "null argument");
+  for (int k = 0; k < 16; ++k) out[k] = (int64_t)c->host_stats[k];
+  return 0;
+}
+
+}  // extern "C"

@@ -358,7 +358,7 @@ def _relax(x, s, box, bonds, angles, zwall=None, iters=3000, log=None):
         r = np.linalg.norm(d, axis=1)
         tgt = _RELAX[s[pairs[:, 0]], s[pairs[:, 1]]]
         viol = r < tgt
-        f = np.where(viol, (r - tgt) / np.maximum(r, 1e-9), 0.0)[:, None] * d
+        f = np.where(viol, 20.0 * (r - tgt) / np.maximum(r, 1e-9), 0.0)[:, None] * d
         np.add.at(g, pairs[:, 0], f)
         np.add.at(g, pairs[:, 1], -f)
         for lst, r0, k in ((bonds, r0b, 4.0), (angles, r0a, 1.0)):
@@ -367,7 +367,7 @@ def _relax(x, s, box, bonds, angles, zwall=None, iters=3000, log=None):
             f2 = (k * (r2 - r0) / r2)[:, None] * d2
             np.add.at(g, lst[:, 0], f2)
             np.add.at(g, lst[:, 1], -f2)
-        step = 0.5 * g
+        step = 0.05 * g
         m = np.linalg.norm(step, axis=1)
         step *= np.minimum(1.0, 0.05 / np.maximum(m, 1e-12))[:, None]
         x = x + step

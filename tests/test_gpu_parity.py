@@ -1,0 +1,180 @@
+"""GPU (HIP, gfx950) AIREBO against the FP64 CPU oracle, through the C ABI.
+
+Bar (FP64 path): |dE|/|E| <= 1e-12 per term (absolute 1e-12 eV for terms
+that vanish), max_a |F_a - F^or_a| / RMS_a |F^or_a| <= 1e-10 and
+|dW| / |W| <= 1e-10.  Both sides evaluate the same definition in FP64; the
+remaining differences are summation order (atomics) and last-bit differences
+of exp / cos / sqrt between the device and host math libraries.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1810_07026_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_E, TOL_F, TOL_W = 1e-12, 1e-10, 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    from paper_1810_07026_amd import airebo
+    out = {m: airebo.Context(term_mask=m) for m in (1, 2, 4, 7)}
+    yield out
+    for c in out.values():
+        c.close()
+
+
+def run_gpu(ctx, d):
+    e, f, w = ctx.compute(d["x"], d["species"], d["box"], d["periodic"])
+    return e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
+
+
+def compare(gpu, ref, label=""):
+    e, f, w = gpu
+    eo, fo, wo = ref
+    scale_e = max(abs(eo[0]), 1.0)
+    for t in range(4):
+        assert abs(e[t] - eo[t]) <= TOL_E * max(abs(eo[t]), scale_e * 1e-3, 1.0), (label, t, e, eo)
+    if len(fo):
+        rms = math.sqrt((fo ** 2).sum(1).mean()) + 1e-300
+        err = np.abs(f - fo).max() / rms
+        assert err <= TOL_F, (label, err)
+    wn = np.linalg.norm(wo) + 1e-300
+    assert np.linalg.norm(w - wo) / wn <= TOL_W or np.linalg.norm(w - wo) < 1e-12, (label, w, wo)
+
+
+def reactive_cluster(seed, n=24, lo=1.05, span=6.0):
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(0, span, 3)
+        if all(np.linalg.norm(p - q) > lo for q in pts):
+            pts.append(p)
+    x = np.array(pts) + 7.0
+    s = rng.integers(0, 2, n).astype(np.int32)
+    return dict(x=x, species=s, box=np.array([40.0, 40, 40]), periodic=np.zeros(3, np.int32))
+
+
+@pytest.mark.parametrize("mask", [1, 2, 4, 7])
+def test_pe_small_terms(ctxs, oracle, mask):
+    d = synth.pe_small()
+    compare(run_gpu(ctxs[mask], d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"], mask=mask),
+            f"pe_small mask={mask}")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_reactive_clusters(ctxs, oracle, seed):
+    d = reactive_cluster(seed, n=28)
+    compare(run_gpu(ctxs[7], d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"]), f"cluster {seed}")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dense_periodic_small_box(ctxs, oracle, seed):
+    """Periodic 12.5 A box: several images of one atom interact."""
+    rng = np.random.default_rng(100 + seed)
+    pts = []
+    while len(pts) < 60:
+        p = rng.uniform(0, 12.5, 3)
+        if all(np.linalg.norm(p - q) > 1.1 for q in pts):
+            pts.append(p)
+    d = dict(x=np.array(pts), species=rng.integers(0, 2, 60).astype(np.int32), box=np.array([12.5, 12.5, 12.5]),
+             periodic=np.ones(3, np.int32))
+    ref = oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
+    compare(run_gpu(ctxs[7], d), ref, "small box")
+
+
+@pytest.mark.parametrize("mol", ["benzene", "naphthalene", "flake", "ethylene_twist", "butane"])
+def test_molecules(ctxs, oracle, mol):
+    if mol == "benzene":
+        x, s = synth.ring_aromatic(1)
+    elif mol == "naphthalene":
+        x, s = synth.ring_aromatic(2)
+    elif mol == "flake":
+        x, s = synth.graphene_flake(3, 3)
+    elif mol == "ethylene_twist":
+        x, s = synth.ethylene(1.33)
+        R = np.array([[1, 0, 0], [0, math.cos(0.7), -math.sin(0.7)], [0, math.sin(0.7), math.cos(0.7)]])
+        x[4:6] = (x[4:6] - x[1]) @ R.T + x[1]
+    else:
+        x, s = synth.alkane(4, torsions=[1.0])
+    x = x + np.random.default_rng(5).normal(scale=0.03, size=x.shape)
+    d = synth.isolated(x, s)
+    compare(run_gpu(ctxs[7], d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"]), mol)
+
+
+def test_tiled_medium(ctxs, oracle):
+    """2x2x2 replica of the 248-atom system: many wavefronts and a ragged tail."""
+    d = synth.tile(synth.pe_small(seed=synth.SEED0 + 17), (2, 2, 1))
+    d["x"] = d["x"] + np.random.default_rng(3).normal(scale=0.05, size=d["x"].shape)
+    compare(run_gpu(ctxs[7], d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"]), "tiled")
+
+
+def test_edge_cases(ctxs, oracle):
+    from paper_1810_07026_amd import airebo
+    c = ctxs[7]
+    # empty system
+    e, f, w = c.compute(np.zeros((0, 3)), np.zeros(0, np.int32), [20, 20, 20])
+    assert np.all(e.cpu().numpy() == 0) and f.shape == (0, 3)
+    # one atom
+    e, f, w = c.compute([[1.0, 2.0, 3.0]], [0], [20, 20, 20])
+    assert np.all(e.cpu().numpy() == 0) and np.all(f.cpu().numpy() == 0)
+    # errors
+    with pytest.raises(airebo.AireboError) as ex:
+        c.compute([[1.0, 2, 3], [2, 2, 3]], [0, 2], [20, 20, 20])
+    assert ex.value.code == -3
+    with pytest.raises(airebo.AireboError) as ex:
+        c.compute([[1.0, 2, 3], [2, 2, 3]], [0, 1], [8, 20, 20])
+    assert ex.value.code == -4
+    with pytest.raises(airebo.AireboError) as ex:
+        c.compute([[1.0, 2, 3], [float("nan"), 2, 3]], [0, 1], [20, 20, 20])
+    assert ex.value.code == -5
+    # context still usable after errors
+    d = synth.pe_small()
+    compare(run_gpu(c, d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"]), "after errors")
+
+
+def test_stats_match_oracle(ctxs, oracle):
+    """Bond, LJ-pair, C_ij = 0 and b* counts are integers both sides must agree on."""
+    d = synth.pe_small()
+    run_gpu(ctxs[7], d)
+    st = ctxs[7].stats()
+    _, _, _, so = oracle.compute(d["x"], d["species"], d["box"], d["periodic"], stats=True)
+    assert st["bonds"] == so["bonds"]
+    assert st["lj_in_cut"] == so["lj_in_cut"]
+    assert st["cij_zero"] == so["cij_zero"]
+    assert st["bstar_queued"] == so["bstar_needed"]
+    assert st["dsb_nonzero"] == so["dsb_nonzero"]
+
+
+def test_nve_matches_oracle(oracle):
+    """20 velocity-Verlet steps: GPU trajectory and thermo follow the oracle's."""
+    import torch
+    from paper_1810_07026_amd import airebo
+    d = synth.pe_small(seed=synth.SEED0 + 3)
+    ctx = airebo.Context()
+    x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+    th = ctx.nve(x, v, d["species"], d["box"], dt=0.5, nsteps=20, thermo_every=5).cpu().numpy()
+    xo, vo, tho = oracle.nve(d["x"], d["v"], d["species"], d["box"], dt=0.5, nsteps=20, thermo_every=5)
+    L = d["box"]
+    dx = x.cpu().numpy() - xo
+    dx -= L * np.round(dx / L)
+    assert np.abs(dx).max() < 1e-9
+    assert np.abs(v.cpu().numpy() - vo).max() < 1e-9
+    assert np.allclose(th[:, :4], tho[:, :4], rtol=1e-10, atol=1e-9)
+
+
+def test_nve_energy_conservation():
+    import torch
+    from paper_1810_07026_amd import airebo
+    d = synth.pe_small(seed=synth.SEED0 + 4)
+    ctx = airebo.Context()
+    x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+    th = ctx.nve(x, v, d["species"], d["box"], dt=0.25, nsteps=400, thermo_every=10).cpu().numpy()
+    drift = np.abs(th[:, 3] - th[0, 3]).max() / len(d["species"])
+    assert drift < 2e-4, drift      # eV/atom over 100 fs
+    assert th[-1, 5] >= 1           # lists were rebuilt at least once

@@ -1,0 +1,32 @@
+"""The C-ABI library loads and exports every symbol include/airebo.h declares (CPU only)."""
+import os
+import re
+
+from paper_1810_07026_amd import airebo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "airebo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(airebo_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_functions() == sorted(airebo.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = airebo.load_library()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_options_default_on_cpu():
+    import ctypes
+    L = airebo.load_library()
+    o = airebo.Options()
+    L.airebo_options_default(ctypes.byref(o))
+    assert o.precision == 0 and o.term_mask == 7 and abs(o.skin - 1.0) < 1e-15
+    assert L.airebo_last_error() is not None
