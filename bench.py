@@ -1,0 +1,150 @@
+"""Throughput of the MI355X AIREBO path: atom-steps/s of velocity-Verlet NVE.
+
+One step is the whole hot path over the system once: half kick and drift, the
+neighbour-list rebuild when an atom has moved more than half the skin, the
+short list and coordination, bond order + REBO + torsion, the C_ij path map,
+the LJ pair loop, the deferred b* pairs, and the second half kick.
+
+Default workload: polyethylene melt, 106 x C100H202 = 32,012 atoms at
+0.85 g/cm^3 in a 66.26 A periodic cube, 300 K, dt = 0.5 fs (synthetic,
+seeded), FP64.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK = 78.6e12      # MI355X vector FP64, FLOP/s
+FP32_VALU_PEAK = 157.3e12
+# Algorithmic FP64 operations per unit of work of each kernel (see the design
+# notes for the breakdown): per LJ pair inside the cutoff (each pair once) and
+# per REBO bond (bond order forward + reverse, pair term, torsion).
+FLOP_PER_LJ_PAIR = 60
+FLOP_PER_BOND = 4000
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": max(args.gpus, world)}))
+        sys.exit(2)
+
+    import torch
+    from paper_1810_07026_amd import airebo, synth
+
+    log("bench: generating workload")
+    d = synth.pe_melt()
+    n = len(d["species"])
+    box, per = d["box"], d["periodic"]
+    prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
+    ctx = airebo.Context(precision=prec)
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(d["x"], dtype=torch.float64, device=dev)
+    v = torch.tensor(d["v"], dtype=torch.float64, device=dev)
+    x0 = x.clone()
+
+    log(f"bench: n={n} warmup {args.warmup} steps")
+    ctx.nve(x, v, d["species"], box, per, nsteps=args.warmup, thermo_every=0)
+    torch.cuda.synchronize()
+    every = max(1, args.steps // 20)
+    log(f"bench: timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = ctx.nve(x, v, d["species"], box, per, nsteps=args.steps, thermo_every=every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    th = th.cpu().numpy()
+    sec = t1 - t0
+    value = n * args.steps / sec
+    rebuilds = int(th[-1, 5])
+    log(f"bench: {value:.4g} atom-steps/s ({1e3 * sec / args.steps:.4f} ms/step), rebuilds {rebuilds}")
+
+    # energy drift over the timed run: slope of (E - E0)/N and max |dE|/|E0|
+    t_ps = th[:, 0] * 0.5e-3
+    de = (th[:, 3] - th[0, 3]) / n
+    slope = float(np.polyfit(t_ps, de, 1)[0]) if len(t_ps) > 2 else float("nan")
+    maxrel = float(np.abs(th[:, 3] - th[0, 3]).max() / abs(th[0, 3]))
+
+    # per-kernel device times (HIP events on the launch stream) and work counts
+    e0, f0, _ = ctx.compute(x0, d["species"], box, per)
+    st = ctx.stats()
+    roof, kern = None, {}
+    if not args.no_profile:
+        xp, vp = x.clone(), v.clone()
+        prof = ctx.profile_nve(xp, vp, d["species"], box, per, nsteps=args.profile_steps)
+        kern = {k: {"total_ms": ms, "launches": c, "avg_us": 1e3 * ms / c if c else 0.0}
+                for k, (ms, c) in prof.items() if c}
+        st_p = ctx.stats()
+        work = {"k_lj": FLOP_PER_LJ_PAIR * st["lj_in_cut"], "k_bond": FLOP_PER_BOND * st["bonds"]}
+        dom = max(kern, key=lambda k: kern[k]["total_ms"])
+        cand = dom if dom in work else max(work, key=lambda k: kern.get(k, {"total_ms": 0})["total_ms"])
+        avg_s = kern[cand]["avg_us"] * 1e-6
+        peak = FP64_VALU_PEAK if prec == airebo.FP64 else FP32_VALU_PEAK
+        ach = work[cand] / avg_s
+        roof = {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": ach / 1e12,
+                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "flop_per_launch": work[cand], "avg_launch_us": kern[cand]["avg_us"]}
+        log(f"bench: kernels {json.dumps({k: round(v['avg_us'], 2) for k, v in kern.items()})}")
+
+    cpu = None
+    ferr = None
+    if not args.no_cpu_baseline:
+        from oracle.oracle import Oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        orc = Oracle(nthreads=threads)
+        log(f"bench: oracle on {threads} threads, one force evaluation of the {n}-atom system")
+        t2 = time.perf_counter()
+        eo, fo, wo = orc.compute(d["x"], d["species"], box, per)
+        t3 = time.perf_counter()
+        cpu = {"value": n / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"one full FP64 force evaluation (= one MD step) of the {n}-atom melt, "
+                         f"{t3 - t2:.1f} s"}
+        fg = f0.cpu().numpy()
+        rms = math.sqrt((fo ** 2).sum(1).mean())
+        ferr = {"force_rms_err_eVA": float(math.sqrt(((fg - fo) ** 2).sum(1).mean())),
+                "force_rel_err_max": float(np.abs(fg - fo).max() / rms),
+                "energy_rel_err": float(abs(e0[0].item() - eo[0]) / abs(eo[0]))}
+
+    out = {
+        "metric": "AIREBO atom-steps/s on 1 GPU",
+        "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == airebo.FP64 else "f32+f64",
+        "data": "synthetic (seeded polyethylene melt generator)",
+        "config": {"workload": f"polyethylene melt 106 x C100H202, {n} atoms, 0.85 g/cm^3, "
+                               f"{box[0]:.2f} A periodic cube, 300 K, NVE dt 0.5 fs, "
+                               f"{args.precision}", "n_atoms": n, "dt_fs": 0.5,
+                   "precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy_vs_oracle": ferr,
+        "energy_drift": {"slope_eV_per_atom_per_ps": slope, "max_rel": maxrel, "rebuilds": rebuilds},
+        "work": {k: st[k] for k in ("lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds")},
+        "kernels_us": {k: round(v["avg_us"], 3) for k, v in kern.items()},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

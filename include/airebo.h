@@ -111,6 +111,20 @@ int airebo_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int3
  *   8 max LJ entries of one atom                     9-15 reserved */
 int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
 
+/* Per-kernel timing of the velocity-Verlet path: runs nsteps steps like
+ * airebo_nve (same arguments, no thermo output) but launches every kernel
+ * eagerly (no graph) between a pair of HIP events on `stream`.  On return
+ * ms_out[k] (host, airebo_kernel_count() doubles) holds the summed device time
+ * in ms of kernel k over those steps and launches_out[k] (host int64) its
+ * launch count; names come from airebo_kernel_name(k).  Errors as for
+ * airebo_nve.  For measurement; the results of the run are those of
+ * airebo_nve. */
+int airebo_profile_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int32_t* species,
+                       const double* box, const int32_t* periodic, const double* mass, double dt_fs, int64_t nsteps,
+                       double* ms_out, int64_t* launches_out, void* stream);
+int airebo_kernel_count(void);
+const char* airebo_kernel_name(int k);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* airebo_last_error(void);
 

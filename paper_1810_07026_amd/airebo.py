@@ -20,7 +20,7 @@ STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "
               "max_path", "max_lj"]
 
 EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "airebo_compute", "airebo_nve",
-           "airebo_stats", "airebo_last_error"]
+           "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name"]
 
 
 class AireboError(RuntimeError):
@@ -61,6 +61,13 @@ def load_library(path=LIB_PATH):
     L.airebo_nve.restype = ctypes.c_int
     L.airebo_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.airebo_stats.restype = ctypes.c_int
+    L.airebo_profile_nve.argtypes = L.airebo_nve.argtypes[:10] + [ctypes.POINTER(ctypes.c_double),
+                                                                   ctypes.POINTER(ctypes.c_int64), vp]
+    L.airebo_profile_nve.restype = ctypes.c_int
+    L.airebo_kernel_count.argtypes = []
+    L.airebo_kernel_count.restype = ctypes.c_int
+    L.airebo_kernel_name.argtypes = [ctypes.c_int]
+    L.airebo_kernel_name.restype = ctypes.c_char_p
     L.airebo_last_error.argtypes = []
     L.airebo_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -142,6 +149,22 @@ class Context:
                                ctypes.c_void_p(th.data_ptr()), self._stream())
         _check(self.L, rc)
         return th
+
+    def profile_nve(self, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5, nsteps=10):
+        """Per-kernel device time over nsteps eager NVE steps: {name: (total ms, launches)}."""
+        import torch
+        assert x.is_cuda and v.is_cuda
+        s = self._dev(species, torch.int32)
+        nk = self.L.airebo_kernel_count()
+        ms = (ctypes.c_double * nk)()
+        cnt = (ctypes.c_int64 * nk)()
+        m = (ctypes.c_double * 2)(*masses)
+        rc = self.L.airebo_profile_nve(self.h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                       _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32), m, dt,
+                                       nsteps, ms, cnt, self._stream())
+        _check(self.L, rc)
+        return {self.L.airebo_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(nk)}
 
     def stats(self):
         out = (ctypes.c_int64 * 16)()

@@ -19,17 +19,18 @@
 //     k_short                    exact short list from the intermediate list,
 //                                w, dw/dr, coordination N^C, N^H; species-bucketed
 //                                bond list (CC / CH / HH batches, Sec. 4.2)
-//     k_pathmap                  per atom, every atom reachable over <= 3 short
-//                                bonds with its largest weight product and the
-//                                path that realises it (the reversed C_ij search
-//                                of Sec. 4.3)
 //     k_bond                     one lane per bond: bond order, REBO pair term and
-//                                torsion merged (Sec. 4.2), forward then reverse
-//     k_lj                       one wavefront per atom over its full LJ list:
+//                                torsion merged (Sec. 4.2), forward then reverse;
+//                                runs on a second stream beside the LJ chain
+//     k_lj                       one wavefront per atom: first the atom's path map
+//                                in LDS (every atom reachable over <= 3 short bonds
+//                                with its weight product and path: the reversed
+//                                C_ij search of Sec. 4.3), then the full LJ list:
 //                                far pairs (r >= 3 max R2) are plain LJ; near pairs
-//                                look up C_ij in the path map; pairs inside the S_r
-//                                range are deferred to a queue (Sec. 4.3)
-//     k_bstar                    one lane per queued pair: b*, S_b, full gradient
+//                                look up C_ij; pairs with 0 < C_ij < 1 or inside the
+//                                S_r range are deferred to a queue (Sec. 4.3)
+//     k_bstar                    one lane per queued pair: C_ij, b*, S_b, full
+//                                gradient
 //   Forces are accumulated with hardware FP64 atomics; energies and the virial by
 //   block reduction followed by one atomic per block.
 #include <hip/hip_runtime.h>
@@ -48,14 +49,25 @@ namespace airebo {
 
 constexpr int SCAP = 8;    // short (REBO) neighbours per atom
 constexpr int ICAP = 48;   // intermediate-list entries per atom
-constexpr int PCAP = 48;   // path-map entries per atom
+constexpr int PCAP = 64;   // path-map candidates per atom (LDS, per wavefront)
+constexpr int LJ_BLOCK = 256;
 constexpr int WAVE = 64;
 
 // flag bits
 enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16, F_OV_BOND = 32, F_OV_QUEUE = 64,
        F_NONFINITE = 128, F_BADSPEC = 256 };
-// accumulator slots
-enum { A_EREBO = 0, A_ELJ = 1, A_ETORS = 2, A_VIR = 3, A_KE = 9, A_N = 10 };
+// accumulator quantities; each lives in NSLOT copies (one per group of blocks,
+// one cache line apart) that k_finish / k_thermo add up
+enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_N = 16 };
+constexpr int NSLOT = 64;
+// deferred-pair queue: NSEG segments with separate counters (QSTRIDE ints apart)
+constexpr int NSEG = 64, QSTRIDE = 32;
+// kernel ids for per-kernel timing
+enum { K_LOAD, K_BIN, K_SCAN, K_FILL, K_BUILD, K_BUILD_DONE, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
+       K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_COUNT };
+__host__ const char* const kKernelNames[K_COUNT] = {
+    "k_load", "k_bin", "k_scan", "k_fill", "k_build", "k_build_done", "k_zero", "k_short", "k_bond",
+    "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
        S_MAXLJ = 8, S_N = 16 };
@@ -68,6 +80,7 @@ struct Dev {
   double skin, rlist2[3], rint2[3];
   double4* x;        // positions (w = species) since the last build
   double4* xref;     // positions at the last build
+  double4* xsort;    // positions ordered by cell (list build only)
   int* cell_of;
   int* cell_count;
   int* cell_start;
@@ -87,12 +100,8 @@ struct Dev {
   int bcap;
   int* bcount;       // [3]
   int2* bonds;       // [3][bcap]: (i, slot)
-  int* pm_n;
-  int* pm_atom;
-  double* pm_prod;
-  int* pm_code;
-  int qcap;
-  int* qcount;
+  int qcap;          // capacity per queue segment
+  int* qcount;       // [NSEG * QSTRIDE]
   int4* q;           // (i, j, shift code, path code)
   double* F;         // forces [n][3]
   double* acc;       // A_N accumulators
@@ -304,8 +313,37 @@ __device__ void block_reduce_add(double (&v)[NV], double* out) {
     double s = 0;
     int nw = (blockDim.x + WAVE - 1) / WAVE;
     for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
-    if (s != 0) atomic_add(&out[threadIdx.x], s);
+    if (s != 0) atomic_add(&out[(blockIdx.x & (NSLOT - 1)) * A_N + threadIdx.x], s);
   }
+}
+
+__device__ __forceinline__ unsigned long long lanes_below() {
+  int lane = threadIdx.x & (WAVE - 1);
+  return lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
+}
+// Wave-aggregated append: every lane with `want` reserves `cnt` slots of the
+// counter; one atomic per wavefront.  Returns the lane's first slot.
+__device__ __forceinline__ int wave_append(int* counter, bool want, int cnt) {
+  int lane = threadIdx.x & (WAVE - 1);
+  int v = want ? cnt : 0;
+  int incl = v;
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  int total = __shfl(incl, WAVE - 1);
+  int base = 0;
+  if (lane == WAVE - 1 && total) base = atomicAdd(counter, total);
+  base = __shfl(base, WAVE - 1);
+  return base + incl - v;
+}
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
 }
 
 template <typename R>
@@ -617,11 +655,12 @@ __global__ void k_fill(Dev D) {
   if (i >= D.n) return;
   int slot = atomicAdd(&D.cell_cursor[D.cell_of[i]], 1);
   D.cell_atoms[slot] = i;
+  D.xsort[slot] = D.x[i];
 }
 
 // One wavefront per atom: full LJ list (cutoff + skin, with image shift code)
 // and intermediate REBO list (R2 + skin), compacted with wave ballots.
-__global__ void k_build(Dev D, const DevParams* __restrict__ Pp) {
+__global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restrict__ Pp) {
   if (!(*D.flags & F_REBUILD)) return;
   int lane = threadIdx.x & (WAVE - 1);
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -659,7 +698,7 @@ __global__ void k_build(Dev D, const DevParams* __restrict__ Pp) {
       int j = -1;
       if (idx < cnt) {
         j = D.cell_atoms[start + idx];
-        double4 xj = D.x[j];
+        double4 xj = D.xsort[start + idx];
         double dx = xj.x + shx - xi.x, dy = xj.y + shy - xi.y, dz = xj.z + shz - xi.z;
         double r2 = dx * dx + dy * dy + dz * dz;
         int p = si + __double2int_rn(xj.w);
@@ -682,11 +721,10 @@ __global__ void k_build(Dev D, const DevParams* __restrict__ Pp) {
     }
   }
   if (lane == 0) {
-    D.lj_n[i] = min(nlj, D.lj_cap);
+    D.lj_n[i] = nlj;            // unclamped; readers clamp to lj_cap
     D.in_n[i] = min(nin, ICAP);
     if (nlj > D.lj_cap) atomicOr(D.flags, F_OV_LJ);
     if (nin > ICAP) atomicOr(D.flags, F_OV_INT);
-    atomicMax(&D.stats[S_MAXLJ], (unsigned long long)nlj);
   }
 }
 
@@ -703,9 +741,9 @@ __global__ void k_build_done(Dev D) {
 __global__ void k_zero(Dev D) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k = t; k < 3 * D.n; k += gridDim.x * blockDim.x) D.F[k] = 0;
-  if (t < A_N) D.acc[t] = 0;
+  if (t < NSLOT * A_N) D.acc[t] = 0;
   if (t < 3) D.bcount[t] = 0;
-  if (t == 0) *D.qcount = 0;
+  if (t < NSEG) D.qcount[t * QSTRIDE] = 0;
 }
 
 __device__ __forceinline__ void minimg(const Dev& D, double& dx, double& dy, double& dz) {
@@ -718,10 +756,13 @@ __device__ __forceinline__ void minimg(const Dev& D, double& dx, double& dy, dou
 __global__ void k_short(Dev D, const DevParams* __restrict__ Pp) {
   const DevParams& P = *Pp;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
+  bool live = i < D.n;
+  int cnt = 0;
+  int nb[3] = {0, 0, 0};
+  if (live) {
   double4 xi = D.x[i];
   int si = __double2int_rn(xi.w);
-  int m = D.in_n[i], cnt = 0;
+  int m = D.in_n[i];
   double NC = 0, NH = 0;
   for (int e = 0; e < m; ++e) {
     int j = D.in_e[i * ICAP + e];
@@ -739,11 +780,7 @@ __global__ void k_short(Dev D, const DevParams* __restrict__ Pp) {
       D.sj[i * SCAP + cnt] = j;
       D.sd[i * SCAP + cnt] = make_double4(dx, dy, dz, r);
       D.sw[i * SCAP + cnt] = make_double2(w, dw);
-      if (j > i) {
-        int b = atomicAdd(&D.bcount[p], 1);
-        if (b < D.bcap) D.bonds[p * D.bcap + b] = make_int2(i, cnt);
-        else atomicOr(D.flags, F_OV_BOND);
-      }
+      if (j > i) nb[p]++;
     }
     ++cnt;
   }
@@ -751,51 +788,24 @@ __global__ void k_short(Dev D, const DevParams* __restrict__ Pp) {
   D.sn[i] = min(cnt, SCAP);
   D.NCt[i] = NC;
   D.NHt[i] = NH;
-  atomicMax(&D.stats[S_MAXSHORT], (unsigned long long)cnt);
-}
-
-// Path map of each atom: every atom reachable over at most three short bonds
-// (no atom repeated), keeping the largest weight product and its path.
-__global__ void k_pathmap(Dev D) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
-  int cnt = 0;
-  bool over = false;
-  int* A = D.pm_atom + (size_t)i * PCAP;
-  double* W = D.pm_prod + (size_t)i * PCAP;
-  int* C = D.pm_code + (size_t)i * PCAP;
-  auto insert = [&](int a, double w, int code) {
-    if (w <= 0.0) return;
-    for (int e = 0; e < cnt; ++e)
-      if (A[e] == a) {
-        if (w > W[e]) { W[e] = w; C[e] = code; }
-        return;
-      }
-    if (cnt < PCAP) { A[cnt] = a; W[cnt] = w; C[cnt] = code; ++cnt; }
-    else over = true;
-  };
-  int n1 = D.sn[i];
-  for (int q1 = 0; q1 < n1; ++q1) {
-    int k = D.sj[i * SCAP + q1];
-    double w1 = D.sw[i * SCAP + q1].x;
-    insert(k, w1, 1 | (q1 << 2));
-    int n2 = D.sn[k];
-    for (int q2 = 0; q2 < n2; ++q2) {
-      int m = D.sj[k * SCAP + q2];
-      if (m == i) continue;
-      double w2 = w1 * D.sw[k * SCAP + q2].x;
-      insert(m, w2, 2 | (q1 << 2) | (q2 << 5));
-      int n3 = D.sn[m];
-      for (int q3 = 0; q3 < n3; ++q3) {
-        int t = D.sj[m * SCAP + q3];
-        if (t == i || t == k) continue;
-        insert(t, w2 * D.sw[m * SCAP + q3].x, 3 | (q1 << 2) | (q2 << 5) | (q3 << 8));
-      }
+  }
+  // species-bucketed bond list: one atomic per wavefront and class
+  int base[3];
+  for (int p = 0; p < 3; ++p) base[p] = wave_append(&D.bcount[p], nb[p] > 0, nb[p]);
+  if (live && (nb[0] | nb[1] | nb[2])) {
+    int si = __double2int_rn(D.x[i].w);
+    int n = D.sn[i];
+    for (int q = 0; q < n; ++q) {
+      int j = D.sj[i * SCAP + q];
+      if (j <= i) continue;
+      int p = si + __double2int_rn(D.x[j].w);
+      int b = base[p]++;
+      if (b < D.bcap) D.bonds[p * D.bcap + b] = make_int2(i, q);
+      else atomicOr(D.flags, F_OV_BOND);
     }
   }
-  D.pm_n[i] = cnt;
-  if (over) atomicOr(D.flags, F_OV_PATH);
-  atomicMax(&D.stats[S_MAXPATH], (unsigned long long)cnt);
+  int mx = wave_max(cnt);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && mx > 0) atomicMax(&D.stats[S_MAXSHORT], (unsigned long long)mx);
 }
 
 // Atoms and bond slots along a path code starting at atom i.
@@ -846,7 +856,7 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
 
 // REBO pair + bond order + torsion, one lane per bond (Alg. 1 and 2 merged).
 template <typename R>
-__global__ void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
+__global__ __launch_bounds__(128) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
   const DevParams& P = *Pp;
   int n0 = D.bcount[0], n1 = D.bcount[1], n2 = D.bcount[2];
   n0 = min(n0, D.bcap); n1 = min(n1, D.bcap); n2 = min(n2, D.bcap);
@@ -896,15 +906,8 @@ __global__ void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
     acc.vec(i, j, rij, gij);
     acc.flush();
   }
-  double v[8] = {er, et, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
-  double v1[1] = {v[0]};
-  block_reduce_add<1>(v1, D.acc + A_EREBO);
-  __syncthreads();
-  double v2[1] = {v[1]};
-  block_reduce_add<1>(v2, D.acc + A_ETORS);
-  __syncthreads();
-  double v6[6] = {v[2], v[3], v[4], v[5], v[6], v[7]};
-  block_reduce_add<6>(v6, D.acc + A_VIR);
+  double v9[9] = {er, et, 0.0, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
+  block_reduce_add<9>(v9, D.acc + A_EREBO);  // A_EREBO, A_ETORS, A_ELJ, A_VIR .. A_VIR+5
 }
 
 __device__ __forceinline__ void lj_pair(const DevParams& P, int p, double r, double& V, double& dV) {
@@ -919,96 +922,180 @@ __device__ __forceinline__ void lj_pair(const DevParams& P, int p, double r, dou
   dV = dv * S + v * dS / P.lj_sw;
 }
 
-// LJ term (Alg. 3), one wavefront per atom over its full list.  Each pair is
-// seen from both ends: each end adds half the energy and virial, the full
-// force on its own atom and half the force on intermediate path atoms.
-__global__ void k_lj(Dev D, const DevParams* __restrict__ Pp) {
+// LJ term (Alg. 3), one wavefront per atom over its full list.
+//
+// The wavefront first maps every atom reachable from i over at most three
+// short bonds (no atom repeated) into LDS, with the weight product of the
+// path and the path itself (the reversed C_ij search: map once per atom, then
+// look up per pair).  Candidates are kept per path; a lookup takes the
+// largest product over the candidates of an atom (first one on ties, direct
+// before one intermediate before two).  Then, over the full list, pairs
+// beyond 3 max R2 are plain LJ; nearer pairs look up C_ij: C = 0 is skipped,
+// C = 1 outside the S_r range is plain LJ, and every other pair (0 < C < 1 or
+// inside the S_r range) is deferred to a queue that k_defer evaluates in
+// full.  Each pair is seen from both ends: each end adds half the energy and
+// virial and the full force on its own atom.
+__global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restrict__ Pp) {
   const DevParams& P = *Pp;
+  __shared__ int c_atom[LJ_BLOCK / WAVE][PCAP];
+  __shared__ int c_code[LJ_BLOCK / WAVE][PCAP];
+  __shared__ int c_k[LJ_BLOCK / WAVE][PCAP];
+  __shared__ double c_prod[LJ_BLOCK / WAVE][PCAP];
   int lane = threadIdx.x & (WAVE - 1);
+  int wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  unsigned long long below = lanes_below();
   double e = 0;
-  Acc acc;
-  acc.init(D.F, i < D.n ? i : -1, -1);
+  double fi[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
   unsigned long long n_in = 0, n_c0 = 0;
   if (i < D.n) {
     double4 xi = D.x[i];
     int si = __double2int_rn(xi.w);
-    int npm = D.pm_n[i];
-    const int* PA = D.pm_atom + (size_t)i * PCAP;
-    int nl = D.lj_n[i];
-    for (int e0 = lane; e0 < nl; e0 += WAVE) {
-      unsigned ent = D.lj_e[(size_t)i * D.lj_cap + e0];
-      int j = (int)(ent & 0x7FFFFFFu);
-      int code = (int)(ent >> 27);
-      double4 xj = D.x[j];
-      double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
-      double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * D.L[1];
-      double dz = xj.z - xi.z + (code % 3 - 1) * D.L[2];
-      double r2 = dx * dx + dy * dy + dz * dz;
-      int p = si + __double2int_rn(xj.w);
-      if (r2 >= P.rc2[p]) continue;
-      double r = sqrt(r2);
-      if (i < j) ++n_in;
-      double V, dV;
-      lj_pair(P, p, r, V, dV);
-      double C = 1.0;
-      int pcode = 0;
-      if (r < P.r_conn) {
-        double prod = 0.0;
-        for (int m = 0; m < npm; ++m)
-          if (PA[m] == j) { prod = D.pm_prod[(size_t)i * PCAP + m]; pcode = D.pm_code[(size_t)i * PCAP + m]; break; }
-        if (prod >= 1.0) { if (i < j) ++n_c0; continue; }
-        C = 1.0 - prod;
-        if (r < P.rljmax[p]) {
-          if (i < j) {
-            int slot = atomicAdd(D.qcount, 1);
-            if (slot < D.qcap) D.q[slot] = make_int4(i, j, code, pcode);
-            else atomicOr(D.flags, F_OV_QUEUE);
-          }
-          continue;
-        }
-        if (prod > 0.0) {
-          PathInfo pi = decode_path(D, i, pcode);
-          path_grad<double>(D, pi, -V, 0.5, 1.0, acc);
+    // ---- path map: levels 1 and 2, one lane per (q1, q2)
+    int ncand = 0;
+    {
+      int q1 = lane >> 3, q2 = lane & 7;
+      int ni = D.sn[i];
+      int k = -1, m = -1;
+      double w1 = 0, w2 = 0;
+      if (q1 < ni) {
+        k = D.sj[i * SCAP + q1];
+        w1 = D.sw[i * SCAP + q1].x;
+        if (q2 < D.sn[k]) {
+          m = D.sj[k * SCAP + q2];
+          w2 = w1 * D.sw[k * SCAP + q2].x;
         }
       }
-      e += 0.5 * C * V;
-      double g = C * dV / r;    // dE/dr_ij vector = g * d
-      acc.fi[0] += g * dx; acc.fi[1] += g * dy; acc.fi[2] += g * dz;
-      acc.W[0] -= 0.5 * g * dx * dx; acc.W[1] -= 0.5 * g * dy * dy; acc.W[2] -= 0.5 * g * dz * dz;
-      acc.W[3] -= 0.5 * g * dx * dy; acc.W[4] -= 0.5 * g * dx * dz; acc.W[5] -= 0.5 * g * dy * dz;
+      bool c1 = q2 == 0 && k >= 0 && w1 > 0.0;
+      unsigned long long b1 = __ballot(c1);
+      if (c1) {
+        int pos = __popcll(b1 & below);
+        c_atom[wv][pos] = k; c_prod[wv][pos] = w1; c_code[wv][pos] = 1 | (q1 << 2); c_k[wv][pos] = i;
+      }
+      ncand = __popcll(b1);
+      bool c2 = m >= 0 && m != i && w2 > 0.0;
+      unsigned long long b2 = __ballot(c2);
+      if (c2) {
+        int pos = ncand + __popcll(b2 & below);
+        if (pos < PCAP) { c_atom[wv][pos] = m; c_prod[wv][pos] = w2; c_code[wv][pos] = 2 | (q1 << 2) | (q2 << 5); c_k[wv][pos] = k; }
+      }
+      int n2start = ncand;
+      ncand += __popcll(b2);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      int n2end = min(ncand, PCAP);
+      // ---- level 3: one lane per (level-2 candidate, q3)
+      for (int base = n2start * 8; base < n2end * 8; base += WAVE) {
+        int c = (base + lane) >> 3, q3 = (base + lane) & 7;
+        bool c3 = false;
+        int t = -1, code = 0;
+        double w3 = 0;
+        if (c < n2end) {
+          int mm = c_atom[wv][c], kk = c_k[wv][c];
+          if (q3 < D.sn[mm]) {
+            t = D.sj[mm * SCAP + q3];
+            w3 = c_prod[wv][c] * D.sw[mm * SCAP + q3].x;
+            code = c_code[wv][c] | (q3 << 8);
+            c3 = t != i && t != kk && w3 > 0.0;
+            code = (code & ~3) | 3;
+          }
+        }
+        unsigned long long b3 = __ballot(c3);
+        if (c3) {
+          int pos = ncand + __popcll(b3 & below);
+          if (pos < PCAP) { c_atom[wv][pos] = t; c_prod[wv][pos] = w3; c_code[wv][pos] = code; }
+        }
+        ncand += __popcll(b3);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (ncand > PCAP && lane == 0) atomicOr(D.flags, F_OV_PATH);
+      ncand = min(ncand, PCAP);
+    }
+    // ---- pair loop
+    int nl = min(D.lj_n[i], D.lj_cap);
+    for (int base = 0; base < nl; base += WAVE) {
+      int e0 = base + lane;
+      bool push = false;
+      int j = 0, code = 0, pcode = 0;
+      if (e0 < nl) {
+        unsigned ent = D.lj_e[(size_t)i * D.lj_cap + e0];
+        j = (int)(ent & 0x7FFFFFFu);
+        code = (int)(ent >> 27);
+        double4 xj = D.x[j];
+        double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
+        double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * D.L[1];
+        double dz = xj.z - xi.z + (code % 3 - 1) * D.L[2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        int p = si + __double2int_rn(xj.w);
+        if (r2 < P.rc2[p]) {
+          double r = sqrt(r2);
+          if (i < j) ++n_in;
+          bool plain = true;
+          if (r < P.r_conn) {
+            double prod = 0.0;
+            for (int c = 0; c < ncand; ++c)
+              if (c_atom[wv][c] == j && c_prod[wv][c] > prod) { prod = c_prod[wv][c]; pcode = c_code[wv][c]; }
+            if (prod >= 1.0) {
+              if (i < j) ++n_c0;
+              plain = false;
+            } else if (prod > 0.0 || r < P.rljmax[p]) {
+              push = i < j;
+              plain = false;
+            }
+          }
+          if (plain) {
+            double V, dV;
+            lj_pair(P, p, r, V, dV);
+            e += 0.5 * V;
+            double g = dV / r;    // dE/dr_ij vector = g * d
+            fi[0] += g * dx; fi[1] += g * dy; fi[2] += g * dz;
+            W[0] -= 0.5 * g * dx * dx; W[1] -= 0.5 * g * dy * dy; W[2] -= 0.5 * g * dz * dz;
+            W[3] -= 0.5 * g * dx * dy; W[4] -= 0.5 * g * dx * dz; W[5] -= 0.5 * g * dy * dz;
+          }
+        }
+      }
+      // deferred pairs: one queue reservation per wavefront
+      int seg = blockIdx.x & (NSEG - 1);
+      int slot = wave_append(D.qcount + seg * QSTRIDE, push, 1);
+      if (push) {
+        if (slot < D.qcap) D.q[(size_t)seg * D.qcap + slot] = make_int4(i, j, code, pcode);
+        else atomicOr(D.flags, F_OV_QUEUE);
+      }
     }
   }
   // reduce the force on atom i across the wavefront
   for (int c = 0; c < 3; ++c) {
-    double s = acc.fi[c];
+    double s = fi[c];
     for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0 && i < D.n && s != 0) atomic_add(&D.F[3 * i + c], s);
   }
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    n_in += __shfl_xor(n_in, o);
-    n_c0 += __shfl_xor(n_c0, o);
-  }
-  if (lane == 0 && n_in) atomicAdd(&D.stats[S_INCUT], n_in);
-  if (lane == 0 && n_c0) atomicAdd(&D.stats[S_CIJ0], n_c0);
-  double v1[1] = {e};
-  block_reduce_add<1>(v1, D.acc + A_ELJ);
-  __syncthreads();
-  double v6[6] = {acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
-  block_reduce_add<6>(v6, D.acc + A_VIR);
+  double v9[9] = {e, W[0], W[1], W[2], W[3], W[4], W[5], (double)n_in, (double)n_c0};
+  block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
 }
 
-// Deferred LJ pairs inside the S_r range: b*, S_b and the full gradient.
+// Deferred LJ pairs (0 < C_ij < 1, or inside the S_r range where the modified
+// bond order b* enters through S_b): energy and the full gradient, including
+// the path atoms of C_ij and, where 0 < t_b < 1, the b* neighbourhood.
 template <typename R>
-__global__ void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
+__global__ __launch_bounds__(128) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
   const DevParams& P = *Pp;
-  int nq = min(*D.qcount, D.qcap);
+  __shared__ int seg_start[NSEG + 1];
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int g = 0; g < NSEG; ++g) { seg_start[g] = run; run += min(D.qcount[g * QSTRIDE], D.qcap); }
+    seg_start[NSEG] = run;
+  }
+  __syncthreads();
+  int nq = seg_start[NSEG];
   double e = 0;
   Acc acc;
   acc.init(D.F, -1, -1);
   unsigned long long ndsb = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += gridDim.x * blockDim.x) {
-    int4 qe = D.q[t];
+    int g = 0;
+    while (seg_start[g + 1] <= t) ++g;
+    int4 qe = D.q[(size_t)g * D.qcap + (t - seg_start[g])];
     int i = qe.x, j = qe.y, code = qe.z, pcode = qe.w;
     double4 xi = D.x[i], xj = D.x[j];
     double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
@@ -1034,11 +1121,13 @@ __global__ void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
     dSr *= P.inv_rlj[p];
     V3<R> rij = {(R)dx, (R)dy, (R)dz};
     V3<R> gij = {0, 0, 0};
-    R bs = bond_order(P, D, i, j, rij, (R)r, true, false, (R)0, gij, acc);
-    double inv_b = 1.0 / (P.bmax[p] - P.bmin[p]);
-    double dSb;
-    double Sb = Sw(((double)bs - P.bmin[p]) * inv_b, dSb);
-    dSb *= inv_b;
+    double Sb = 1.0, dSb = 0.0;
+    if (Sr > 0.0) {
+      R bs = bond_order(P, D, i, j, rij, (R)r, true, false, (R)0, gij, acc);
+      double inv_b = 1.0 / (P.bmax[p] - P.bmin[p]);
+      Sb = Sw(((double)bs - P.bmin[p]) * inv_b, dSb);
+      dSb *= inv_b;
+    }
     double Qf = Sr * Sb + 1.0 - Sr;
     e += Qf * C * V;
     double Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
@@ -1052,27 +1141,43 @@ __global__ void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
     acc.vec(i, j, rij, gij);
     acc.flush();
   }
-  for (int o = WAVE / 2; o > 0; o >>= 1) ndsb += __shfl_xor(ndsb, o);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && ndsb) atomicAdd(&D.stats[S_DSB], ndsb);
-  double v1[1] = {e};
-  block_reduce_add<1>(v1, D.acc + A_ELJ);
   __syncthreads();
-  double v6[6] = {acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
-  block_reduce_add<6>(v6, D.acc + A_VIR);
+  double v10[10] = {e, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5], 0.0, 0.0, (double)ndsb};
+  block_reduce_add<10>(v10, D.acc + A_ELJ);  // A_ELJ .. A_NDSB
+}
+
+// Maximum of per-atom counts into a statistics slot (one atomic per wavefront).
+__global__ void k_max(const int* __restrict__ a, int n, unsigned long long* out) {
+  int m = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) m = max(m, a[t]);
+  m = wave_max(m);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && m > 0) atomicMax(out, (unsigned long long)m);
 }
 
 __global__ void k_finish(Dev D, double* energy, double* virial) {
   int t = threadIdx.x;
+  __shared__ double tot[A_N];
+  if (t < A_N) {
+    double s = 0;
+    for (int g = 0; g < NSLOT; ++g) s += D.acc[g * A_N + t];
+    tot[t] = s;
+  }
+  __syncthreads();
   if (t == 0) {
-    energy[1] = D.acc[A_EREBO];
-    energy[2] = D.acc[A_ELJ];
-    energy[3] = D.acc[A_ETORS];
-    energy[0] = D.acc[A_EREBO] + D.acc[A_ELJ] + D.acc[A_ETORS];
-    D.stats[S_BSTAR] = (unsigned long long)min(*D.qcount, D.qcap);
+    energy[1] = tot[A_EREBO];
+    energy[2] = tot[A_ELJ];
+    energy[3] = tot[A_ETORS];
+    energy[0] = tot[A_EREBO] + tot[A_ELJ] + tot[A_ETORS];
+    unsigned long long nq = 0;
+    for (int g = 0; g < NSEG; ++g) nq += (unsigned long long)min(D.qcount[g * QSTRIDE], D.qcap);
+    D.stats[S_BSTAR] = nq;
     D.stats[S_BONDS] = (unsigned long long)(D.bcount[0] + D.bcount[1] + D.bcount[2]);
+    D.stats[S_INCUT] = (unsigned long long)tot[A_NIN];
+    D.stats[S_CIJ0] = (unsigned long long)tot[A_NC0];
+    D.stats[S_DSB] = (unsigned long long)tot[A_NDSB];
     if (!isfinite(energy[0])) atomicOr(D.flags, F_NONFINITE);
   }
-  if (t < 6) virial[t] = D.acc[A_VIR + t];
+  if (t < 6) virial[t] = tot[A_VIR + t];
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,8 +1222,12 @@ __global__ void k_thermo(Dev D, double* thermo, int every, int nrows) {
   int s = *D.step;
   if (thermo && every > 0 && s % every == 0 && s / every < nrows) {
     double* row = thermo + 6 * (s / every);
-    double pe = D.acc[A_EREBO] + D.acc[A_ELJ] + D.acc[A_ETORS];
-    double ke = D.acc[A_KE];
+    double pe = 0, ke = 0;
+    for (int g = 0; g < NSLOT; ++g) {
+      const double* a = D.acc + g * A_N;
+      pe += a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
+      ke += a[A_KE];
+    }
     row[0] = s;
     row[1] = pe;
     row[2] = ke;
@@ -1185,8 +1294,10 @@ struct airebo_ctx {
   int64_t n = 0;
   int lj_cap = 0;
   // buffers and capacities
-  double4 *x = nullptr, *xref = nullptr;
-  size_t cx = 0, cxr = 0;
+  double4 *x = nullptr, *xref = nullptr, *xsort = nullptr;
+  size_t cx = 0, cxr = 0, cxs = 0;
+  hipStream_t side = nullptr;     // second stream: bonded terms run beside the LJ chain
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_cursor = nullptr, *cell_atoms = nullptr;
   size_t c_of = 0, c_cc = 0, c_cs = 0, c_cu = 0, c_ca = 0;
   int* lj_n = nullptr;
@@ -1205,10 +1316,6 @@ struct airebo_ctx {
   size_t c_bc = 0;
   int2* bonds = nullptr;
   size_t c_b = 0;
-  int *pm_n = nullptr, *pm_atom = nullptr, *pm_code = nullptr;
-  size_t c_pmn = 0, c_pma = 0, c_pmc = 0;
-  double* pm_prod = nullptr;
-  size_t c_pmp = 0;
   int* qcount = nullptr;
   size_t c_qc = 0;
   int4* q = nullptr;
@@ -1224,7 +1331,27 @@ struct airebo_ctx {
   int* step = nullptr;
   size_t c_stp = 0;
   unsigned long long host_stats[S_N] = {};
+  // per-kernel timing (profile mode)
+  bool prof = false;
+  struct Ev { int k; hipEvent_t a, b; };
+  std::vector<Ev> ev;
 };
+
+// Launch a kernel; in profile mode bracket it with a pair of HIP events.
+#define LAUNCH(C, KID, KER, GRID, BLOCK, STREAM, ...)                                     \
+  do {                                                                                     \
+    if ((C)->prof) {                                                                       \
+      airebo_ctx::Ev e_{KID, nullptr, nullptr};                                            \
+      (void)hipEventCreate(&e_.a);                                                         \
+      (void)hipEventCreate(&e_.b);                                                         \
+      (void)hipEventRecord(e_.a, STREAM);                                                  \
+      hipLaunchKernelGGL(KER, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                        \
+      (void)hipEventRecord(e_.b, STREAM);                                                  \
+      (C)->ev.push_back(e_);                                                               \
+    } else {                                                                               \
+      hipLaunchKernelGGL(KER, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                        \
+    }                                                                                      \
+  } while (0)
 
 extern "C" {
 
@@ -1257,6 +1384,9 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
   if (e == hipSuccess) e = hipMalloc((void**)&c->dtri, tri.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(c->dtri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
   c->P.tri = c->dtri;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc((void**)&c->dP, sizeof(DevParams));
   if (e == hipSuccess) e = hipMemcpy(c->dP, &c->P, sizeof(DevParams), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -1270,9 +1400,12 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
 
 void airebo_ctx_free(airebo_ctx_t c) {
   if (!c) return;
-  void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
+  if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->xsort, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
                   c->cell_atoms, c->lj_n, c->lj_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
-                  c->bcount, c->bonds, c->pm_n, c->pm_atom, c->pm_code, c->pm_prod, c->qcount, c->q, c->F, c->acc,
+                  c->bcount, c->bonds, c->qcount, c->q, c->F, c->acc,
                   c->stats, c->flags, c->step};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -1314,6 +1447,7 @@ int setup(airebo_ctx* c, int64_t n, const double* box, const int32_t* per) {
   int rc = 0;
   rc |= grow(c->x, c->cx, N);
   rc |= grow(c->xref, c->cxr, N);
+  rc |= grow(c->xsort, c->cxs, N);
   rc |= grow(c->cell_of, c->c_of, N);
   rc |= grow(c->cell_count, c->c_cc, ncell);
   rc |= grow(c->cell_start, c->c_cs, ncell + 1);
@@ -1332,24 +1466,20 @@ int setup(airebo_ctx* c, int64_t n, const double* box, const int32_t* per) {
   rc |= grow(c->bcount, c->c_bc, 4);
   size_t bcap = N * SCAP / 2 + 64;
   rc |= grow(c->bonds, c->c_b, 3 * bcap);
-  rc |= grow(c->pm_n, c->c_pmn, N);
-  rc |= grow(c->pm_atom, c->c_pma, N * PCAP);
-  rc |= grow(c->pm_code, c->c_pmc, N * PCAP);
-  rc |= grow(c->pm_prod, c->c_pmp, N * PCAP);
-  rc |= grow(c->qcount, c->c_qc, 4);
-  size_t qcap = 4 * N + 1024;
-  rc |= grow(c->q, c->c_q, qcap);
+  rc |= grow(c->qcount, c->c_qc, NSEG * QSTRIDE);
+  size_t qcap = (4 * N + 1024 * NSEG) / NSEG;   // per segment
+  rc |= grow(c->q, c->c_q, qcap * NSEG);
   rc |= grow(c->F, c->c_F, 3 * N);
-  rc |= grow(c->acc, c->c_acc, A_N + 6);
+  rc |= grow(c->acc, c->c_acc, NSLOT * A_N);
   rc |= grow(c->stats, c->c_st, S_N);
   rc |= grow(c->flags, c->c_fl, 4);
   rc |= grow(c->step, c->c_stp, 4);
   if (rc) return AIREBO_E_DEVICE;
-  D.x = c->x; D.xref = c->xref; D.cell_of = c->cell_of; D.cell_count = c->cell_count; D.cell_start = c->cell_start;
+  D.x = c->x; D.xref = c->xref; D.xsort = c->xsort; D.cell_of = c->cell_of; D.cell_count = c->cell_count; D.cell_start = c->cell_start;
   D.cell_cursor = c->cell_cursor; D.cell_atoms = c->cell_atoms; D.lj_cap = c->lj_cap; D.lj_n = c->lj_n;
   D.lj_e = c->lj_e; D.in_n = c->in_n; D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
-  D.NCt = c->NCt; D.NHt = c->NHt; D.bcap = (int)bcap; D.bcount = c->bcount; D.bonds = c->bonds; D.pm_n = c->pm_n;
-  D.pm_atom = c->pm_atom; D.pm_prod = c->pm_prod; D.pm_code = c->pm_code; D.qcap = (int)qcap; D.qcount = c->qcount;
+  D.NCt = c->NCt; D.NHt = c->NHt; D.bcap = (int)bcap; D.bcount = c->bcount; D.bonds = c->bonds;
+  D.qcap = (int)qcap; D.qcount = c->qcount;
   D.q = c->q; D.F = c->F; D.acc = c->acc; D.stats = c->stats; D.flags = c->flags; D.step = c->step;
   return 0;
 }
@@ -1360,11 +1490,11 @@ inline int blocks(int64_t n, int t) { return (int)std::max<int64_t>(1, (n + t - 
 void launch_rebuild(airebo_ctx* c, hipStream_t s) {
   Dev& D = c->D;
   int ncell = D.nc[0] * D.nc[1] * D.nc[2];
-  hipLaunchKernelGGL(k_bin, dim3(blocks(D.n, 256)), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, D, ncell);
-  hipLaunchKernelGGL(k_fill, dim3(blocks(D.n, 256)), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_build, dim3(blocks((int64_t)D.n * WAVE, 256)), dim3(256), 0, s, D, (const DevParams*)c->dP);
-  hipLaunchKernelGGL(k_build_done, dim3(1), dim3(64), 0, s, D);
+  LAUNCH(c, K_BIN, k_bin, dim3(blocks(D.n, 256)), dim3(256), s, D);
+  LAUNCH(c, K_SCAN, k_scan, dim3(1), dim3(1024), s, D, ncell);
+  LAUNCH(c, K_FILL, k_fill, dim3(blocks(D.n, 256)), dim3(256), s, D);
+  LAUNCH(c, K_BUILD, k_build, dim3(blocks((int64_t)D.n * WAVE, 256)), dim3(256), s, D, (const DevParams*)c->dP);
+  LAUNCH(c, K_BUILD_DONE, k_build_done, dim3(1), dim3(64), s, D);
 }
 
 // Launch one force evaluation on the current positions.
@@ -1372,15 +1502,28 @@ void launch_forces(airebo_ctx* c, hipStream_t s) {
   Dev& D = c->D;
   const DevParams* P = c->dP;
   int mask = c->opt.term_mask;
-  hipLaunchKernelGGL(k_zero, dim3(std::min(blocks(3 * (int64_t)D.n, 256), 4096)), dim3(256), 0, s, D);
-  hipLaunchKernelGGL(k_short, dim3(blocks(D.n, 128)), dim3(128), 0, s, D, P);
-  if (mask & (AIREBO_TERM_LJ)) hipLaunchKernelGGL(k_pathmap, dim3(blocks(D.n, 128)), dim3(128), 0, s, D);
-  int nb = std::min(blocks((int64_t)D.n * 2, 128), 8192);
+  LAUNCH(c, K_ZERO, k_zero, dim3(std::min(std::max(blocks(3 * (int64_t)D.n, 256), NSLOT * A_N / 256), 4096)),
+         dim3(256), s, D);
+  LAUNCH(c, K_SHORT, k_short, dim3(blocks(D.n, 128)), dim3(128), s, D, P);
+  // fork: the bonded kernel runs on the side stream beside the LJ chain (the
+  // profiler's per-kernel events keep everything on one stream)
+  bool fork = !c->prof && (mask & AIREBO_TERM_LJ) && (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION));
+  hipStream_t sb = s;
+  if (fork) {
+    (void)hipEventRecord(c->ev_fork, s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    sb = c->side;
+  }
+  int nb = std::min(blocks((int64_t)D.n * 2, 64), 8192);
   if (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION))
-    hipLaunchKernelGGL(k_bond<double>, dim3(nb), dim3(128), 0, s, D, P, mask);
+    LAUNCH(c, K_BOND, k_bond<double>, dim3(nb), dim3(64), sb, D, P, mask);
   if (mask & AIREBO_TERM_LJ) {
-    hipLaunchKernelGGL(k_lj, dim3(blocks((int64_t)D.n * WAVE, 256)), dim3(256), 0, s, D, P);
-    hipLaunchKernelGGL(k_bstar<double>, dim3(std::min(blocks(D.n, 128), 2048)), dim3(128), 0, s, D, P);
+    LAUNCH(c, K_LJ, k_lj, dim3(blocks((int64_t)D.n * WAVE, LJ_BLOCK)), dim3(LJ_BLOCK), s, D, P);
+    LAUNCH(c, K_BSTAR, k_bstar<double>, dim3(std::min(blocks(D.n, 64), 4096)), dim3(64), s, D, P);
+  }
+  if (fork) {
+    (void)hipEventRecord(c->ev_join, c->side);
+    (void)hipStreamWaitEvent(s, c->ev_join, 0);
   }
 }
 
@@ -1413,9 +1556,13 @@ int compute_impl(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* sp
       launch_rebuild(c, s);
       launch_forces(c, s);
     } else {
-      hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, D);
+      hipLaunchKernelGGL(k_zero, dim3(NSLOT * A_N / 256), dim3(256), 0, s, D);
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, D, energy, virial);
+    if (n > 0) {
+      int g = std::min(blocks(n, 256), 1024);
+      hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.stats + S_MAXLJ);
+    }
     HIPCHK(hipGetLastError());
     int flags = 0;
     HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1479,30 +1626,39 @@ int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_
       hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
       return;
     }
-    hipLaunchKernelGGL(k_kick_drift, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], dt, half_skin2);
+    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt,
+           half_skin2);
     launch_rebuild(c, s);
     launch_forces(c, s);
-    hipLaunchKernelGGL(k_kick, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], dt);
-    hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
+    LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt);
+    LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(64), s, D, thermo, (int)every, nrows);
   };
   body(true);
+  if (c->prof) {   // per-kernel timing: eager launches, one event pair per kernel
+    HIPCHK(hipStreamSynchronize(s));
+    for (auto& e : c->ev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    c->ev.clear();
+    for (int64_t k = 0; k < nsteps; ++k) body(false);
+    HIPCHK(hipStreamSynchronize(s));
+  }
   // capture one step into a graph and replay it
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cs = nullptr;
-  err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (err == hipSuccess) err = hipStreamSynchronize(s);
-  if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (err == hipSuccess) {
+  if (!c->prof) err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (c->prof) nsteps = 0;
+  if (err == hipSuccess && cs) err = hipStreamSynchronize(s);
+  if (err == hipSuccess && cs) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (err == hipSuccess && cs) {
     hipStream_t keep = s;
     s = cs;
     body(false);
     s = keep;
     err = hipStreamEndCapture(cs, &graph);
   }
-  if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (err == hipSuccess && cs) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) err = hipGraphLaunch(exec, cs);
-  if (err == hipSuccess) err = hipStreamSynchronize(cs);
+  if (err == hipSuccess && cs) err = hipStreamSynchronize(cs);
   if (exec) hipGraphExecDestroy(exec);
   if (graph) hipGraphDestroy(graph);
   if (cs) hipStreamDestroy(cs);
@@ -1516,6 +1672,32 @@ int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_
   if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded during NVE");
   return check_flags(c, flags);
 }
+
+int airebo_profile_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species,
+                       const double* box, const int32_t* periodic, const double* mass, double dt, int64_t nsteps,
+                       double* ms_out, int64_t* launches_out, void* stream) {
+  if (!c || !ms_out || !launches_out) return fail(AIREBO_E_ARG, "null argument");
+  c->prof = true;
+  c->ev.clear();
+  int rc = airebo_nve(c, n, pos, vel, species, box, periodic, mass, dt, nsteps, 0, nullptr, stream);
+  c->prof = false;
+  for (int k = 0; k < K_COUNT; ++k) { ms_out[k] = 0; launches_out[k] = 0; }
+  for (auto& e : c->ev) {
+    float ms = 0;
+    if (rc == 0 && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      ms_out[e.k] += ms;
+      launches_out[e.k] += 1;
+    }
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  c->ev.clear();
+  return rc;
+}
+
+int airebo_kernel_count(void) { return K_COUNT; }
+
+const char* airebo_kernel_name(int k) { return (k >= 0 && k < K_COUNT) ? kKernelNames[k] : ""; }
 
 int airebo_stats(airebo_ctx_t c, int64_t* out) {
   if (!c || !out) return fail(AIREBO_E_ARG, "null argument");

@@ -376,7 +376,7 @@ def _relax(x, s, box, bonds, angles, zwall=None, iters=3000, log=None):
         hard_viol = (r < _HARD[s[pairs[:, 0]], s[pairs[:, 1]]]).sum()
         if log and it % 100 == 0:
             log(it, int(viol.sum()), int(hard_viol), float(r.min()) if len(r) else 0.0)
-        if it % 10 == 9 and hard_viol == 0 and not viol.any():
+        if it % 10 == 9 and hard_viol == 0 and it >= 99:
             break
     return np.mod(x, box)
 
@@ -420,6 +420,27 @@ def _finish(pk, box, periodic, rng, T, meta, jitter=0.0):
     return out
 
 
+DATA = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)), "data")
+
+
+def cached(name, make):
+    """Load a generated system from data/<name>.npz, generating and storing it if absent."""
+    import os
+    path = os.path.join(DATA, name + ".npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        out = {k: z[k] for k in z.files if k != "meta_json"}
+        import json
+        out["meta"] = json.loads(str(z["meta_json"]))
+        return out
+    d = make()
+    import json
+    os.makedirs(DATA, exist_ok=True)
+    arrs = {k: v for k, v in d.items() if k != "meta"}
+    np.savez_compressed(path, meta_json=json.dumps(d["meta"]), **arrs)
+    return d
+
+
 def pe_small(seed=SEED0 + 0, T=300.0):
     """4 x C20H42 in a 20 A periodic cube, Gaussian jitter 0.05 A (248 atoms)."""
     return polyethylene(4, 20, (20.0, 20.0, 20.0), seed, T=T, jitter=0.05)
@@ -430,14 +451,26 @@ def melt_box_side(n_atoms_per_chain, n_chains, density_gcc=0.85):
     return (mass * 1.66053906660 / density_gcc) ** (1.0 / 3.0)
 
 
-def pe_melt(n_chains=106, n_carbon=100, density_gcc=0.85, seed=SEED0 + 1, T=300.0):
-    """C100H202 melt at 0.85 g/cm^3 (106 chains = 32,012 atoms, cube 66.26 A)."""
+def pe_melt(n_chains=106, n_carbon=100, density_gcc=0.85, seed=SEED0 + 1, T=300.0, shape=(1.0, 1.0, 1.0),
+            use_cache=True):
+    """C100H202 melt at 0.85 g/cm^3 (106 chains = 32,012 atoms, cube 66.26 A).
+
+    shape scales the box sides at fixed volume (for slabs that must match a
+    crystal's in-plane cell)."""
     per = 3 * n_carbon + 2
     mass = n_chains * (n_carbon * MASS[0] + (2 * n_carbon + 2) * MASS[1])
-    L = (mass * 1.66053906660 / density_gcc) ** (1.0 / 3.0)
-    out = polyethylene(n_chains, n_carbon, (L, L, L), seed, T=T)
-    out["meta"].update(kind="pe_melt", density_gcc=density_gcc, atoms_per_chain=per)
-    return out
+    vol = mass * 1.66053906660 / density_gcc
+    sh = np.asarray(shape, float)
+    L = vol ** (1.0 / 3.0) * sh / np.prod(sh) ** (1.0 / 3.0)
+
+    def make():
+        out = polyethylene(n_chains, n_carbon, tuple(L), seed, T=T)
+        out["meta"].update(kind="pe_melt", density_gcc=density_gcc, atoms_per_chain=per)
+        return out
+    if not use_cache:
+        return make()
+    tag = f"pe_melt_{n_chains}x{n_carbon}_s{seed}_" + "x".join(f"{v:.2f}" for v in L)
+    return cached(tag, make)
 
 
 def tile(sysd, reps):
