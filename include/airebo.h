@@ -60,7 +60,12 @@ typedef struct {
   double skin;         /* neighbour-list skin in A (default 1.0)                      */
   int32_t lj_cap;      /* LJ list entries per atom; 0 = automatic (grows on demand)   */
   int32_t device;      /* HIP device ordinal (default 0)                              */
-  int32_t reserved[8];
+  /* launch shapes (0 = default); chosen by the autotuner for a workload class */
+  int32_t bond_block;  /* threads per block of the bonded kernel: 64, 128 or 256 (64)  */
+  int32_t bond_grid;   /* blocks of the bonded kernel's persistent grid (auto)        */
+  int32_t defer_block; /* threads per block of the deferred-pair kernel: 64..256 (64) */
+  int32_t short_block; /* threads per block of the short-list kernel: 64..256 (128)   */
+  int32_t reserved[4];
 } airebo_options;
 
 void airebo_options_default(airebo_options* opt);
@@ -103,12 +108,37 @@ int airebo_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int3
                const int32_t* periodic, const double* mass, double dt_fs, int64_t nsteps, int64_t thermo_every,
                double* thermo, void* stream);
 
+/* Batched form: nsys independent systems stored back to back, evaluated by
+ * the same kernel launches (one launch per stage over every system's atoms).
+ *   sys_off  host [nsys + 1] int64, atoms of system k are [sys_off[k], sys_off[k+1]),
+ *            sys_off[0] = 0
+ *   boxes    host [nsys][3] box lengths; periodic host [nsys][3] flags (each
+ *            periodic side >= max(12 A, LJ cutoff + skin))
+ *   pos, species, forces as for airebo_compute over all sys_off[nsys] atoms
+ *   energy   device [nsys][4] (total, REBO, LJ, torsion); virial device [nsys][6]
+ * Each system's results equal those of airebo_compute on that system alone
+ * (up to summation order).  Errors as for airebo_compute. */
+int airebo_batch_compute(airebo_ctx_t ctx, int32_t nsys, const int64_t* sys_off, const double* boxes,
+                         const int32_t* periodic, const double* pos, const int32_t* species, double* energy,
+                         double* forces, double* virial, void* stream);
+
+/* Batched velocity Verlet: as airebo_nve over every system of the batch, the
+ * whole step of all systems captured into one HIP graph.  thermo: device
+ * [(nsteps / thermo_every) + 1][nsys][6] rows {step, PE, KE, Etot, T, rebuilds}
+ * per system.  Neighbour lists of all systems are rebuilt together when any
+ * atom has moved more than half the skin. */
+int airebo_batch_nve(airebo_ctx_t ctx, int32_t nsys, const int64_t* sys_off, const double* boxes,
+                     const int32_t* periodic, double* pos, double* vel, const int32_t* species, const double* mass,
+                     double dt_fs, int64_t nsteps, int64_t thermo_every, double* thermo, void* stream);
+
 /* Counters of the last airebo_compute / airebo_nve call (host [16] int64):
  *   0 LJ pairs inside the cutoff (each pair once)   1 pairs with C_ij = 0
  *   2 pairs queued for the modified bond order b*   3 b* pairs with dS_b != 0
  *   4 bonds                                          5 neighbour-list rebuilds
- *   6 max short neighbours of one atom               7 max path-map entries of one atom
- *   8 max LJ entries of one atom                     9-15 reserved */
+ *   6 max short neighbours of one atom               7 reserved
+ *   8 max LJ entries of one atom                     9 spline evaluations
+ *  10 of those evaluated in FP64 near a knot (AIREBO_MIXED)   11-15 reserved
+ * Slots 0-4 and 9-10 refer to the last force evaluation (every step in NVE). */
 int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
 
 /* Per-kernel timing of the velocity-Verlet path: runs nsteps steps like

@@ -17,10 +17,11 @@ DEFAULT_PARAMS = os.path.join(HERE, "params", "airebo_ch.param")
 FP64, MIXED = 0, 1
 TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
-              "max_path", "max_lj"]
+              "reserved7", "max_lj", "spline_evals", "spline_evals_fp64"]
 
 EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "airebo_compute", "airebo_nve",
-           "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name"]
+           "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name",
+           "airebo_batch_compute", "airebo_batch_nve"]
 
 
 class AireboError(RuntimeError):
@@ -31,7 +32,11 @@ class AireboError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("term_mask", ctypes.c_int32), ("skin", ctypes.c_double),
-                ("lj_cap", ctypes.c_int32), ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("lj_cap", ctypes.c_int32), ("device", ctypes.c_int32), ("bond_block", ctypes.c_int32),
+                ("bond_grid", ctypes.c_int32), ("defer_block", ctypes.c_int32), ("short_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+    TUNABLES = ("bond_block", "bond_grid", "defer_block", "short_block")
 
 
 _lib = None
@@ -68,6 +73,14 @@ def load_library(path=LIB_PATH):
     L.airebo_kernel_count.restype = ctypes.c_int
     L.airebo_kernel_name.argtypes = [ctypes.c_int]
     L.airebo_kernel_name.restype = ctypes.c_char_p
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.airebo_batch_compute.argtypes = [vp, ctypes.c_int32, i64p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32), dp, ip, dp, dp, dp, vp]
+    L.airebo_batch_compute.restype = ctypes.c_int
+    L.airebo_batch_nve.argtypes = [vp, ctypes.c_int32, i64p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int32), dp, dp, ip, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_double, ctypes.c_int64, ctypes.c_int64, dp, vp]
+    L.airebo_batch_nve.restype = ctypes.c_int
     L.airebo_last_error.argtypes = []
     L.airebo_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -87,7 +100,8 @@ def _host3(a, ctype):
 class Context:
     """One AIREBO evaluation context on one GPU."""
 
-    def __init__(self, params=DEFAULT_PARAMS, precision=FP64, term_mask=TERM_ALL, skin=1.0, lj_cap=0, device=0):
+    def __init__(self, params=DEFAULT_PARAMS, precision=FP64, term_mask=TERM_ALL, skin=1.0, lj_cap=0, device=0,
+                 tune=None):
         import torch
         if not torch.cuda.is_available():
             raise AireboError(-7, "no GPU visible: the AIREBO library runs on the GPU only")
@@ -95,6 +109,11 @@ class Context:
         o = Options()
         self.L.airebo_options_default(ctypes.byref(o))
         o.precision, o.term_mask, o.skin, o.lj_cap, o.device = precision, term_mask, skin, lj_cap, device
+        for k, v in (tune or {}).items():
+            if k not in Options.TUNABLES:
+                raise AireboError(-1, f"unknown tunable {k}")
+            setattr(o, k, int(v))
+        self.tune = dict(tune or {})
         h = ctypes.c_void_p()
         _check(self.L, self.L.airebo_ctx_create(params.encode(), ctypes.byref(o), ctypes.byref(h)))
         self.h = h
@@ -165,6 +184,51 @@ class Context:
                                        nsteps, ms, cnt, self._stream())
         _check(self.L, rc)
         return {self.L.airebo_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(nk)}
+
+    @staticmethod
+    def _batch_host(sizes, boxes, periodic):
+        nsys = len(sizes)
+        off = np.zeros(nsys + 1, dtype=np.int64)
+        off[1:] = np.cumsum(sizes)
+        b = np.ascontiguousarray(boxes, dtype=np.float64).reshape(nsys, 3)
+        p = np.ascontiguousarray(periodic if periodic is not None else np.ones((nsys, 3)), dtype=np.int32)
+        p = np.ascontiguousarray(np.broadcast_to(p.reshape(-1, 3), (nsys, 3)), dtype=np.int32)
+        return nsys, off, b, p
+
+    def batch_compute(self, x, species, sizes, boxes, periodic=None):
+        """Batched evaluation: energy [nsys,4], forces [n,3], virial [nsys,6] (device tensors)."""
+        import torch
+        x = self._dev(x, torch.float64).reshape(-1, 3)
+        s = self._dev(species, torch.int32)
+        nsys, off, b, p = self._batch_host(sizes, boxes, periodic)
+        e = torch.empty((nsys, 4), dtype=torch.float64, device=self.device)
+        w = torch.empty((nsys, 6), dtype=torch.float64, device=self.device)
+        f = torch.empty((x.shape[0], 3), dtype=torch.float64, device=self.device)
+        rc = self.L.airebo_batch_compute(
+            self.h, nsys, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(e.data_ptr()),
+            ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(w.data_ptr()), self._stream())
+        _check(self.L, rc)
+        return e, f, w
+
+    def batch_nve(self, x, v, species, sizes, boxes, periodic=None, masses=(12.011, 1.008), dt=0.5, nsteps=10,
+                  thermo_every=1):
+        """Batched velocity Verlet in place; returns thermo [rows, nsys, 6] (device tensor)."""
+        import torch
+        assert x.is_cuda and v.is_cuda
+        s = self._dev(species, torch.int32)
+        nsys, off, b, p = self._batch_host(sizes, boxes, periodic)
+        rows = nsteps // thermo_every + 1 if thermo_every > 0 else 1
+        th = torch.zeros((rows, nsys, 6), dtype=torch.float64, device=self.device)
+        m = (ctypes.c_double * 2)(*masses)
+        rc = self.L.airebo_batch_nve(
+            self.h, nsys, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(s.data_ptr()), m, dt,
+            nsteps, thermo_every, ctypes.c_void_p(th.data_ptr()), self._stream())
+        _check(self.L, rc)
+        return th
 
     def stats(self):
         out = (ctypes.c_int64 * 16)()

@@ -37,6 +37,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -58,7 +59,10 @@ enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16,
        F_NONFINITE = 128, F_BADSPEC = 256 };
 // accumulator quantities; each lives in NSLOT copies (one per group of blocks,
 // one cache line apart) that k_finish / k_thermo add up
-enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_N = 16 };
+enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_SPL = 13,
+       A_SPL64 = 14, A_N = 16 };
+// mixed precision: a spline argument within this distance of a knot is evaluated in FP64
+constexpr double KNOT_DELTA = 1e-3;
 constexpr int NSLOT = 64;
 // deferred-pair queue: NSEG segments with separate counters (QSTRIDE ints apart)
 constexpr int NSEG = 64, QSTRIDE = 32;
@@ -70,13 +74,24 @@ __host__ const char* const kKernelNames[K_COUNT] = {
     "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
-       S_MAXLJ = 8, S_N = 16 };
+       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_N = 16 };
 
-struct Dev {
-  int n;
+// One system of a batch: its own periodic box and cell grid.  A single
+// configuration is a batch of one.
+struct SysBox {
   double L[3], invL[3];
   int per[3];
   int nc[3];
+  int cell_off;      // first cell of this system in the global cell arrays
+  int natoms;
+};
+
+struct Dev {
+  int n;
+  int nsys;
+  const SysBox* sys;       // [nsys]
+  const int* atom_sys;     // [n] system of each atom (nullptr when nsys == 1)
+  double* sys_acc;         // [nsys][A_N] per-system accumulators (nsys > 1)
   double skin, rlist2[3], rint2[3];
   double4* x;        // positions (w = species) since the last build
   double4* xref;     // positions at the last build
@@ -113,6 +128,8 @@ struct Dev {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int sys_of(const Dev& D, int i) { return D.atom_sys ? D.atom_sys[i] : 0; }
+__device__ __forceinline__ const SysBox& box_of(const Dev& D, int i) { return D.sys[sys_of(D, i)]; }
 template <typename R> struct V3 { R x, y, z; };
 template <typename R> __device__ __forceinline__ V3<R> mk(R a, R b, R c) { return {a, b, c}; }
 template <typename R> __device__ __forceinline__ V3<R> operator+(V3<R> a, V3<R> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
@@ -176,7 +193,18 @@ __device__ __forceinline__ R guard(const DevParams& P, R c, R& d) {
 
 // Quintic angular spline: value and d/dx.
 template <typename R>
-__device__ __forceinline__ R gspl(const GSpline& g, R x, R& d) {
+__device__ __forceinline__ R gspl(const GSpline& g, R x, R& d, int* st) {
+  st[0]++;
+  if constexpr (std::is_same<R, float>::value) {
+    for (int m = 1; m + 1 < g.n; ++m)
+      if (fabs((double)x - g.x[m]) < KNOT_DELTA) {
+        st[1]++;
+        double dd;
+        double v = gspl<double>(g, (double)x, dd, st + 2);
+        d = (float)dd;
+        return (float)v;
+      }
+  }
   bool clamped = false;
   if (x <= (R)g.x[0]) { x = (R)g.x[0]; clamped = true; }
   if (x >= (R)g.x[g.n - 1]) { x = (R)g.x[g.n - 1]; clamped = true; }
@@ -191,25 +219,36 @@ __device__ __forceinline__ R gspl(const GSpline& g, R x, R& d) {
 }
 // g_i(cos theta) of the centre species; carbon blends gamma_C in over N_ij.
 template <typename R>
-__device__ __forceinline__ R gfun(const DevParams& P, int sc, R c, R N, R& dc, R& dN) {
+__device__ __forceinline__ R gfun(const DevParams& P, int sc, R c, R N, R& dc, R& dN, int* st) {
   dN = 0;
-  if (sc == 1) return gspl(P.gH, c, dc);
+  if (sc == 1) return gspl(P.gH, c, dc, st);
   R dG;
-  R G = gspl(P.gC, c, dG);
+  R G = gspl(P.gC, c, dG, st);
   dc = dG;
   if (c <= (R)P.gammaC.x[0]) return G;
   R dQ;
   R Qn = cosstep(N, P.gC_lo, P.gC_hi, dQ);
   if (Qn == (R)0 && dQ == (R)0) return G;
   R dgam;
-  R gam = gspl(P.gammaC, c, dgam);
+  R gam = gspl(P.gammaC, c, dgam, st);
   dc = dG + Qn * (dgam - dG);
   dN = dQ * (gam - G);
   return G + Qn * (gam - G);
 }
 // Bicubic P_{C s_j}(N^C, N^H) with partials.
 template <typename R>
-__device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx, R& dy) {
+__device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx, R& dy, int* st) {
+  st[0]++;
+  if constexpr (std::is_same<R, float>::value) {
+    if (fabs((double)x - rint((double)x)) < KNOT_DELTA || fabs((double)y - rint((double)y)) < KNOT_DELTA) {
+      st[1]++;
+      double ddx, ddy;
+      double v = bicubic<double>(Pc, (double)x, (double)y, ddx, ddy, st + 2);
+      dx = (float)ddx;
+      dy = (float)ddy;
+      return (float)v;
+    }
+  }
   bool kx = x < (R)0 || x > (R)4, ky = y < (R)0 || y > (R)4;
   x = x < (R)0 ? (R)0 : (x > (R)4 ? (R)4 : x);
   y = y < (R)0 ? (R)0 : (y > (R)4 ? (R)4 : y);
@@ -230,7 +269,20 @@ __device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx,
 }
 // Tricubic table t at (x, y, z) with partials.
 template <typename R>
-__device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, R& dx, R& dy, R& dz) {
+__device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, R& dx, R& dy, R& dz, int* st) {
+  st[0]++;
+  if constexpr (std::is_same<R, float>::value) {
+    if (fabs((double)x - rint((double)x)) < KNOT_DELTA || fabs((double)y - rint((double)y)) < KNOT_DELTA ||
+        fabs((double)z - rint((double)z)) < KNOT_DELTA) {
+      st[1]++;
+      double ddx, ddy, ddz;
+      double v = tricubic<double>(P, t, (double)x, (double)y, (double)z, ddx, ddy, ddz, st + 2);
+      dx = (float)ddx;
+      dy = (float)ddy;
+      dz = (float)ddz;
+      return (float)v;
+    }
+  }
   bool kx = x < (R)0 || x > (R)4, ky = y < (R)0 || y > (R)4, kz = z < (R)1 || z > (R)9;
   x = x < (R)0 ? (R)0 : (x > (R)4 ? (R)4 : x);
   y = y < (R)0 ? (R)0 : (y > (R)4 ? (R)4 : y);
@@ -269,12 +321,14 @@ __device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, 
 // W -= r_ab (x) g; the two atoms the lane owns are kept in registers.
 // ---------------------------------------------------------------------------
 struct Acc {
+  int st[4];         // spline evaluations, of which in FP64 near a knot
   int i, j;
   double fi[3], fj[3];
   double W[6];
   double* F;
   __device__ void init(double* F_, int i_, int j_) {
     F = F_; i = i_; j = j_;
+    st[0] = st[1] = st[2] = st[3] = 0;
     for (int c = 0; c < 3; ++c) fi[c] = fj[c] = 0;
     for (int c = 0; c < 6; ++c) W[c] = 0;
   }
@@ -301,7 +355,7 @@ struct Acc {
 // Block reduction of `nv` doubles per thread into global accumulators.
 template <int NV>
 __device__ void block_reduce_add(double (&v)[NV], double* out) {
-  __shared__ double red[NV][16];
+  __shared__ double red[NV][4];
   int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
   for (int q = 0; q < NV; ++q) {
     double s = v[q];
@@ -314,6 +368,27 @@ __device__ void block_reduce_add(double (&v)[NV], double* out) {
     int nw = (blockDim.x + WAVE - 1) / WAVE;
     for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
     if (s != 0) atomic_add(&out[(blockIdx.x & (NSLOT - 1)) * A_N + threadIdx.x], s);
+  }
+}
+
+// Add a lane's contribution to its system's accumulators (batched mode only).
+// Wave-uniform systems are reduced first (one atomic per quantity).
+template <int NV>
+__device__ void sys_add(const Dev& D, int sysid, const double (&v)[NV], int base, bool active) {
+  if (D.nsys <= 1) return;
+  int lane = threadIdx.x & (WAVE - 1);
+  int s0 = __shfl(active ? sysid : -1, 0);
+  unsigned long long act = __ballot(active);
+  bool uniform = __all(!active || sysid == s0) && (act & 1ull);
+  if (uniform) {
+    for (int q = 0; q < NV; ++q) {
+      double t = active ? v[q] : 0.0;
+      for (int o = WAVE / 2; o > 0; o >>= 1) t += __shfl_xor(t, o);
+      if (lane == 0 && t != 0) atomic_add(&D.sys_acc[(size_t)s0 * A_N + base + q], t);
+    }
+  } else if (active) {
+    for (int q = 0; q < NV; ++q)
+      if (v[q] != 0) atomic_add(&D.sys_acc[(size_t)sysid * A_N + base + q], v[q]);
   }
 }
 
@@ -365,7 +440,7 @@ struct EndF {
 
 template <typename R>
 __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, int so, V3<R> rco, R rlen, R rlam,
-                        EndF<R>& e) {
+                        EndF<R>& e, int* st) {
   int n = D.sn[c];
   R NC = 0, NH = 0;
   for (int q = 0; q < n; ++q) {
@@ -385,7 +460,7 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
     R w = (R)D.sw[c * SCAP + q].x;
     R cth = dot(rco, d) / (rlen * r);
     R dgc, dgN;
-    R g = gfun(P, sc, cth, N, dgc, dgN);
+    R g = gfun(P, sc, cth, N, dgc, dgN, st);
     R el = 1;
     if (sc == 1) el = xexp((R)P.lambda_pref * (((R)P.rho[sk] - r) - ((R)P.rho[so] - rlam)));
     S += w * g * el;
@@ -397,7 +472,7 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
     }
   }
   R Pv = 0, dPC = 0, dPH = 0;
-  if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH);
+  if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH, st);
   e.NC = NC; e.NH = NH; e.N = N; e.S = S; e.P = Pv; e.dPC = dPC; e.dPH = dPH;
   e.p = (R)1 / xsqrt((R)1 + S + Pv);
   e.conj = conj;
@@ -425,7 +500,7 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
     R inv = (R)1 / (rlen * r);
     R cth = dot(rco, d) * inv;
     R dgc, dgN;
-    R g = gfun(P, sc, cth, e.N, dgc, dgN);
+    R g = gfun(P, sc, cth, e.N, dgc, dgN, acc.st);
     R el = 1;
     R Gr = 0;
     if (sc == 1) {
@@ -540,20 +615,20 @@ __device__ R bond_order(const DevParams& P, const Dev& D, int i, int j, V3<R> ri
   R rlam = (bstar && P.bstar_use_R1) ? (R)P.R1[p] : r;
   EndF<R> ei, ej;
   V3<R> rji = -rij;
-  end_fwd(P, D, i, si, j, sj, rij, r, rlam, ei);
-  end_fwd(P, D, j, sj, i, si, rji, r, rlam, ej);
+  end_fwd(P, D, i, si, j, sj, rij, r, rlam, ei, acc.st);
+  end_fwd(P, D, j, sj, i, si, rji, r, rlam, ej, acc.st);
   R Nconj = (R)1 + ei.conj * ei.conj + ej.conj * ej.conj;
   R dFa, dFb, dFc;
   R pirc;
   bool swap = (p == 1 && si == 1);   // C-H table takes the carbon side first
   int tF = p == 0 ? TRI_FCC : (p == 1 ? TRI_FCH : TRI_FHH);
   R Fij, Fji;
-  if (!swap) { pirc = tricubic(P, tF, ei.N, ej.N, Nconj, dFa, dFb, dFc); Fij = dFa; Fji = dFb; }
-  else { pirc = tricubic(P, tF, ej.N, ei.N, Nconj, dFa, dFb, dFc); Fij = dFb; Fji = dFa; }
+  if (!swap) { pirc = tricubic(P, tF, ei.N, ej.N, Nconj, dFa, dFb, dFc, acc.st); Fij = dFa; Fji = dFb; }
+  else { pirc = tricubic(P, tF, ej.N, ei.N, Nconj, dFa, dFb, dFc, acc.st); Fij = dFb; Fji = dFa; }
   R Tv = 0, dTa = 0, dTb = 0, dTc = 0, Sdh = 0, Et = 0, Gwij = 0;
   bool dh = false;
   if (p == 0) {
-    Tv = tricubic(P, TRI_TCC, ei.N, ej.N, Nconj, dTa, dTb, dTc);
+    Tv = tricubic(P, TRI_TCC, ei.N, ej.N, Nconj, dTa, dTb, dTc, acc.st);
     dh = Tv != (R)0 || dTa != (R)0 || dTb != (R)0 || dTc != (R)0;
     if (dh) { V3<R> dummy = {0, 0, 0}; dihedral(P, D, i, j, rij, r, (R)0, false, false, (R)0, Sdh, Et, dummy, Gwij, acc); }
   }
@@ -591,11 +666,12 @@ __global__ void k_load(Dev D, const double* __restrict__ pos, const int* __restr
     if (spec[i] != 0 && spec[i] != 1) atomicOr(D.flags, F_BADSPEC);
   }
   double* xc = &x.x;
+  const SysBox& B = box_of(D, i);
   for (int c = 0; c < 3; ++c) {
     if (!isfinite(xc[c])) atomicOr(D.flags, F_NONFINITE);
-    if (D.per[c]) {
-      xc[c] -= D.L[c] * floor(xc[c] * D.invL[c]);
-      if (xc[c] >= D.L[c]) xc[c] -= D.L[c];
+    if (B.per[c]) {
+      xc[c] -= B.L[c] * floor(xc[c] * B.invL[c]);
+      if (xc[c] >= B.L[c]) xc[c] -= B.L[c];
       if (xc[c] < 0) xc[c] = 0;
     }
   }
@@ -608,17 +684,18 @@ __global__ void k_bin(Dev D) {
   if (i >= D.n) return;
   double4 x = D.x[i];
   double* xc = &x.x;
+  const SysBox& B = box_of(D, i);
   for (int c = 0; c < 3; ++c) {
-    if (D.per[c]) {
-      xc[c] -= D.L[c] * floor(xc[c] * D.invL[c]);
-      if (xc[c] >= D.L[c]) xc[c] -= D.L[c];
+    if (B.per[c]) {
+      xc[c] -= B.L[c] * floor(xc[c] * B.invL[c]);
+      if (xc[c] >= B.L[c]) xc[c] -= B.L[c];
       if (xc[c] < 0) xc[c] = 0;
     }
   }
   D.x[i] = x;
   D.xref[i] = x;
-  int c = (cell_coord(x.x, D.invL[0], D.nc[0]) * D.nc[1] + cell_coord(x.y, D.invL[1], D.nc[1])) * D.nc[2] +
-          cell_coord(x.z, D.invL[2], D.nc[2]);
+  int c = B.cell_off + (cell_coord(x.x, B.invL[0], B.nc[0]) * B.nc[1] + cell_coord(x.y, B.invL[1], B.nc[1])) * B.nc[2] +
+          cell_coord(x.z, B.invL[2], B.nc[2]);
   D.cell_of[i] = c;
   atomicAdd(&D.cell_count[c], 1);
 }
@@ -667,8 +744,9 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
   if (i >= D.n) return;
   double4 xi = D.x[i];
   int si = __double2int_rn(xi.w);
-  int ci[3] = {cell_coord(xi.x, D.invL[0], D.nc[0]), cell_coord(xi.y, D.invL[1], D.nc[1]),
-               cell_coord(xi.z, D.invL[2], D.nc[2])};
+  const SysBox& B = box_of(D, i);
+  int ci[3] = {cell_coord(xi.x, B.invL[0], B.nc[0]), cell_coord(xi.y, B.invL[1], B.nc[1]),
+               cell_coord(xi.z, B.invL[2], B.nc[2])};
   int nlj = 0, nin = 0;
   unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
   for (int o = 0; o < 27; ++o) {
@@ -677,21 +755,21 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
     bool skip = false;
     for (int c = 0; c < 3; ++c) {
       int t = ci[c] + off[c];
-      if (D.per[c]) {
-        sh[c] = t < 0 ? -1 : (t >= D.nc[c] ? 1 : 0);
-        cc[c] = t - sh[c] * D.nc[c];
-        if (cc[c] < 0 || cc[c] >= D.nc[c]) skip = true;   // nc == 1 wraps once only
+      if (B.per[c]) {
+        sh[c] = t < 0 ? -1 : (t >= B.nc[c] ? 1 : 0);
+        cc[c] = t - sh[c] * B.nc[c];
+        if (cc[c] < 0 || cc[c] >= B.nc[c]) skip = true;   // nc == 1 wraps once only
       } else {
         sh[c] = 0;
         cc[c] = t;
-        if (t < 0 || t >= D.nc[c]) skip = true;
+        if (t < 0 || t >= B.nc[c]) skip = true;
       }
     }
     if (skip) continue;
-    int cell = (cc[0] * D.nc[1] + cc[1]) * D.nc[2] + cc[2];
+    int cell = B.cell_off + (cc[0] * B.nc[1] + cc[1]) * B.nc[2] + cc[2];
     int start = D.cell_start[cell], cnt = D.cell_start[cell + 1] - start;
     unsigned code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
-    double shx = sh[0] * D.L[0], shy = sh[1] * D.L[1], shz = sh[2] * D.L[2];
+    double shx = sh[0] * B.L[0], shy = sh[1] * B.L[1], shz = sh[2] * B.L[2];
     for (int base = 0; base < cnt; base += WAVE) {
       int idx = base + lane;
       bool ok_lj = false, ok_in = false;
@@ -742,18 +820,20 @@ __global__ void k_zero(Dev D) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k = t; k < 3 * D.n; k += gridDim.x * blockDim.x) D.F[k] = 0;
   if (t < NSLOT * A_N) D.acc[t] = 0;
+  if (D.nsys > 1)
+    for (int k = t; k < D.nsys * A_N; k += gridDim.x * blockDim.x) D.sys_acc[k] = 0;
   if (t < 3) D.bcount[t] = 0;
   if (t < NSEG) D.qcount[t * QSTRIDE] = 0;
 }
 
-__device__ __forceinline__ void minimg(const Dev& D, double& dx, double& dy, double& dz) {
-  if (D.per[0]) dx -= D.L[0] * rint(dx * D.invL[0]);
-  if (D.per[1]) dy -= D.L[1] * rint(dy * D.invL[1]);
-  if (D.per[2]) dz -= D.L[2] * rint(dz * D.invL[2]);
+__device__ __forceinline__ void minimg(const SysBox& B, double& dx, double& dy, double& dz) {
+  if (B.per[0]) dx -= B.L[0] * rint(dx * B.invL[0]);
+  if (B.per[1]) dy -= B.L[1] * rint(dy * B.invL[1]);
+  if (B.per[2]) dz -= B.L[2] * rint(dz * B.invL[2]);
 }
 
 // Exact short list, weights and coordination; species-bucketed bond list.
-__global__ void k_short(Dev D, const DevParams* __restrict__ Pp) {
+__global__ __launch_bounds__(256) void k_short(Dev D, const DevParams* __restrict__ Pp) {
   const DevParams& P = *Pp;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = i < D.n;
@@ -762,13 +842,14 @@ __global__ void k_short(Dev D, const DevParams* __restrict__ Pp) {
   if (live) {
   double4 xi = D.x[i];
   int si = __double2int_rn(xi.w);
+  const SysBox& B = box_of(D, i);
   int m = D.in_n[i];
   double NC = 0, NH = 0;
   for (int e = 0; e < m; ++e) {
     int j = D.in_e[i * ICAP + e];
     double4 xj = D.x[j];
     double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-    minimg(D, dx, dy, dz);
+    minimg(B, dx, dy, dz);
     double r2 = dx * dx + dy * dy + dz * dz;
     int sj = __double2int_rn(xj.w);
     int p = si + sj;
@@ -856,7 +937,7 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
 
 // REBO pair + bond order + torsion, one lane per bond (Alg. 1 and 2 merged).
 template <typename R>
-__global__ __launch_bounds__(128) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
+__global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
   const DevParams& P = *Pp;
   int n0 = D.bcount[0], n1 = D.bcount[1], n2 = D.bcount[2];
   n0 = min(n0, D.bcap); n1 = min(n1, D.bcap); n2 = min(n2, D.bcap);
@@ -877,6 +958,8 @@ __global__ __launch_bounds__(128) void k_bond(Dev D, const DevParams* __restrict
     int p = seg;
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
+    double er0 = er, et0 = et, W0[6];
+    for (int c = 0; c < 6; ++c) W0[c] = acc.W[c];
     V3<R> gij = {0, 0, 0};
     R Gr = 0;
     if (mask & AIREBO_TERM_REBO) {
@@ -905,21 +988,31 @@ __global__ __launch_bounds__(128) void k_bond(Dev D, const DevParams* __restrict
     gij = gij + (Gr / r) * rij;
     acc.vec(i, j, rij, gij);
     acc.flush();
+    if (D.nsys > 1) {
+      double dv[9] = {er - er0, et - et0, 0.0};
+      for (int c = 0; c < 6; ++c) dv[3 + c] = acc.W[c] - W0[c];
+      int sid = sys_of(D, i);
+      for (int q = 0; q < 9; ++q)
+        if (dv[q] != 0) atomic_add(&D.sys_acc[(size_t)sid * A_N + A_EREBO + q], dv[q]);
+    }
   }
-  double v9[9] = {er, et, 0.0, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5]};
-  block_reduce_add<9>(v9, D.acc + A_EREBO);  // A_EREBO, A_ETORS, A_ELJ, A_VIR .. A_VIR+5
+  double v15[15] = {er, et, 0.0, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5], 0.0, 0.0, 0.0, 0.0,
+                    (double)acc.st[0], (double)acc.st[1]};
+  block_reduce_add<15>(v15, D.acc + A_EREBO);  // A_EREBO .. A_SPL64
 }
 
-__device__ __forceinline__ void lj_pair(const DevParams& P, int p, double r, double& V, double& dV) {
-  double s = P.sigma[p] / r;
-  double s2 = s * s, s6 = s2 * s2 * s2;
-  double e4 = 4.0 * P.eps[p];
-  double v = e4 * (s6 * s6 - s6);
-  double dv = e4 * (-12.0 * s6 * s6 + 6.0 * s6) / r;
-  double t = (r - (P.rc[p] - P.lj_sw)) / P.lj_sw, dS;
-  double S = Sw(t, dS);
+template <typename R>
+__device__ __forceinline__ void lj_pair(const DevParams& P, int p, R r, R& V, R& dV) {
+  R s = (R)P.sigma[p] / r;
+  R s2 = s * s, s6 = s2 * s2 * s2;
+  R e4 = (R)(4.0 * P.eps[p]);
+  R v = e4 * (s6 * s6 - s6);
+  R dv = e4 * ((R)-12 * s6 * s6 + (R)6 * s6) / r;
+  R isw = (R)(1.0 / P.lj_sw);
+  R t = (r - (R)(P.rc[p] - P.lj_sw)) * isw, dS;
+  R S = Sw(t, dS);
   V = v * S;
-  dV = dv * S + v * dS / P.lj_sw;
+  dV = dv * S + v * dS * isw;
 }
 
 // LJ term (Alg. 3), one wavefront per atom over its full list.
@@ -935,6 +1028,7 @@ __device__ __forceinline__ void lj_pair(const DevParams& P, int p, double r, dou
 // inside the S_r range) is deferred to a queue that k_defer evaluates in
 // full.  Each pair is seen from both ends: each end adds half the energy and
 // virial and the full force on its own atom.
+template <typename R>
 __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restrict__ Pp) {
   const DevParams& P = *Pp;
   __shared__ int c_atom[LJ_BLOCK / WAVE][PCAP];
@@ -951,6 +1045,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
   if (i < D.n) {
     double4 xi = D.x[i];
     int si = __double2int_rn(xi.w);
+    const SysBox& B = box_of(D, i);
     // ---- path map: levels 1 and 2, one lane per (q1, q2)
     int ncand = 0;
     {
@@ -1023,9 +1118,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
         j = (int)(ent & 0x7FFFFFFu);
         code = (int)(ent >> 27);
         double4 xj = D.x[j];
-        double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
-        double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * D.L[1];
-        double dz = xj.z - xi.z + (code % 3 - 1) * D.L[2];
+        double dx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
+        double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
+        double dz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
         double r2 = dx * dx + dy * dy + dz * dz;
         int p = si + __double2int_rn(xj.w);
         if (r2 < P.rc2[p]) {
@@ -1045,13 +1140,15 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
             }
           }
           if (plain) {
-            double V, dV;
-            lj_pair(P, p, r, V, dV);
-            e += 0.5 * V;
-            double g = dV / r;    // dE/dr_ij vector = g * d
-            fi[0] += g * dx; fi[1] += g * dy; fi[2] += g * dz;
-            W[0] -= 0.5 * g * dx * dx; W[1] -= 0.5 * g * dy * dy; W[2] -= 0.5 * g * dz * dz;
-            W[3] -= 0.5 * g * dx * dy; W[4] -= 0.5 * g * dx * dz; W[5] -= 0.5 * g * dy * dz;
+            // pair arithmetic in R on the FP64 relative vector; FP64 accumulation
+            R rr = (R)r, V, dV;
+            lj_pair<R>(P, p, rr, V, dV);
+            e += 0.5 * (double)V;
+            R g = dV / rr;    // dE/dr_ij vector = g * d
+            R fx = g * (R)dx, fy = g * (R)dy, fz = g * (R)dz;
+            fi[0] += (double)fx; fi[1] += (double)fy; fi[2] += (double)fz;
+            W[0] -= 0.5 * (double)(fx * (R)dx); W[1] -= 0.5 * (double)(fy * (R)dy); W[2] -= 0.5 * (double)(fz * (R)dz);
+            W[3] -= 0.5 * (double)(fy * (R)dx); W[4] -= 0.5 * (double)(fz * (R)dx); W[5] -= 0.5 * (double)(fz * (R)dy);
           }
         }
       }
@@ -1071,6 +1168,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
     if (lane == 0 && i < D.n && s != 0) atomic_add(&D.F[3 * i + c], s);
   }
   double v9[9] = {e, W[0], W[1], W[2], W[3], W[4], W[5], (double)n_in, (double)n_c0};
+  if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v9, A_ELJ, i < D.n);
   block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
 }
 
@@ -1078,7 +1176,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
 // bond order b* enters through S_b): energy and the full gradient, including
 // the path atoms of C_ij and, where 0 < t_b < 1, the b* neighbourhood.
 template <typename R>
-__global__ __launch_bounds__(128) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
+__global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
   const DevParams& P = *Pp;
   __shared__ int seg_start[NSEG + 1];
   if (threadIdx.x == 0) {
@@ -1096,17 +1194,20 @@ __global__ __launch_bounds__(128) void k_bstar(Dev D, const DevParams* __restric
     int g = 0;
     while (seg_start[g + 1] <= t) ++g;
     int4 qe = D.q[(size_t)g * D.qcap + (t - seg_start[g])];
+    double W0[6];
+    for (int c = 0; c < 6; ++c) W0[c] = acc.W[c];
     int i = qe.x, j = qe.y, code = qe.z, pcode = qe.w;
     double4 xi = D.x[i], xj = D.x[j];
-    double dx = xj.x - xi.x + (code / 9 - 1) * D.L[0];
-    double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * D.L[1];
-    double dz = xj.z - xi.z + (code % 3 - 1) * D.L[2];
+    const SysBox& B = box_of(D, i);
+    double dx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
+    double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
+    double dz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
     int p = __double2int_rn(xi.w) + __double2int_rn(xj.w);
     double r = sqrt(dx * dx + dy * dy + dz * dz);
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
     double V, dV;
-    lj_pair(P, p, r, V, dV);
+    lj_pair<double>(P, p, r, V, dV);
     double prod = 0;
     PathInfo pi;
     pi.len = 0;
@@ -1140,10 +1241,18 @@ __global__ __launch_bounds__(128) void k_bstar(Dev D, const DevParams* __restric
     gij = gij + (R)(Gr / r) * rij;
     acc.vec(i, j, rij, gij);
     acc.flush();
+    if (D.nsys > 1) {
+      double dv[7] = {Qf * C * V};
+      for (int c = 0; c < 6; ++c) dv[1 + c] = acc.W[c] - W0[c];
+      int sid = sys_of(D, i);
+      for (int q = 0; q < 7; ++q)
+        if (dv[q] != 0) atomic_add(&D.sys_acc[(size_t)sid * A_N + A_ELJ + q], dv[q]);
+    }
   }
   __syncthreads();
-  double v10[10] = {e, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5], 0.0, 0.0, (double)ndsb};
-  block_reduce_add<10>(v10, D.acc + A_ELJ);  // A_ELJ .. A_NDSB
+  double v13[13] = {e, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5], 0.0, 0.0, (double)ndsb, 0.0,
+                    (double)acc.st[0], (double)acc.st[1]};
+  block_reduce_add<13>(v13, D.acc + A_ELJ);  // A_ELJ .. A_SPL64
 }
 
 // Maximum of per-atom counts into a statistics slot (one atomic per wavefront).
@@ -1164,10 +1273,12 @@ __global__ void k_finish(Dev D, double* energy, double* virial) {
   }
   __syncthreads();
   if (t == 0) {
-    energy[1] = tot[A_EREBO];
-    energy[2] = tot[A_ELJ];
-    energy[3] = tot[A_ETORS];
-    energy[0] = tot[A_EREBO] + tot[A_ELJ] + tot[A_ETORS];
+    if (D.nsys == 1) {
+      energy[1] = tot[A_EREBO];
+      energy[2] = tot[A_ELJ];
+      energy[3] = tot[A_ETORS];
+      energy[0] = tot[A_EREBO] + tot[A_ELJ] + tot[A_ETORS];
+    }
     unsigned long long nq = 0;
     for (int g = 0; g < NSEG; ++g) nq += (unsigned long long)min(D.qcount[g * QSTRIDE], D.qcap);
     D.stats[S_BSTAR] = nq;
@@ -1175,9 +1286,22 @@ __global__ void k_finish(Dev D, double* energy, double* virial) {
     D.stats[S_INCUT] = (unsigned long long)tot[A_NIN];
     D.stats[S_CIJ0] = (unsigned long long)tot[A_NC0];
     D.stats[S_DSB] = (unsigned long long)tot[A_NDSB];
-    if (!isfinite(energy[0])) atomicOr(D.flags, F_NONFINITE);
+    D.stats[S_SPL] = (unsigned long long)tot[A_SPL];
+    D.stats[S_SPL64] = (unsigned long long)tot[A_SPL64];
+    if (!isfinite(tot[A_EREBO] + tot[A_ELJ] + tot[A_ETORS])) atomicOr(D.flags, F_NONFINITE);
   }
-  if (t < 6) virial[t] = tot[A_VIR + t];
+  if (D.nsys == 1) {
+    if (t < 6) virial[t] = tot[A_VIR + t];
+    return;
+  }
+  for (int sid = t; sid < D.nsys; sid += blockDim.x) {
+    const double* a = D.sys_acc + (size_t)sid * A_N;
+    energy[4 * sid + 1] = a[A_EREBO];
+    energy[4 * sid + 2] = a[A_ELJ];
+    energy[4 * sid + 3] = a[A_ETORS];
+    energy[4 * sid + 0] = a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
+    for (int q = 0; q < 6; ++q) virial[6 * sid + q] = a[A_VIR + q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1214,28 +1338,41 @@ __global__ void k_kick(Dev D, double* vel, double m0, double m1, double dt) {
     }
   }
   double v1[1] = {ke};
+  if (D.nsys > 1) sys_add<1>(D, i < D.n ? sys_of(D, i) : 0, v1, A_KE, i < D.n);
   block_reduce_add<1>(v1, D.acc + A_KE);
 }
 
+// Thermo rows {step, PE, KE, Etot, T, rebuilds}: one row per system and
+// output step ([row][nsys][6]); one block.
 __global__ void k_thermo(Dev D, double* thermo, int every, int nrows) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int s = *D.step;
-  if (thermo && every > 0 && s % every == 0 && s / every < nrows) {
-    double* row = thermo + 6 * (s / every);
-    double pe = 0, ke = 0;
-    for (int g = 0; g < NSLOT; ++g) {
-      const double* a = D.acc + g * A_N;
-      pe += a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
-      ke += a[A_KE];
+  __syncthreads();
+  if (blockIdx.x == 0 && thermo && every > 0 && s % every == 0 && s / every < nrows) {
+    for (int sid = threadIdx.x; sid < D.nsys; sid += blockDim.x) {
+      double pe = 0, ke = 0;
+      int na = D.sys[sid].natoms;
+      if (D.nsys == 1) {
+        for (int g = 0; g < NSLOT; ++g) {
+          const double* a = D.acc + g * A_N;
+          pe += a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
+          ke += a[A_KE];
+        }
+      } else {
+        const double* a = D.sys_acc + (size_t)sid * A_N;
+        pe = a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
+        ke = a[A_KE];
+      }
+      double* row = thermo + 6 * ((size_t)(s / every) * D.nsys + sid);
+      row[0] = s;
+      row[1] = pe;
+      row[2] = ke;
+      row[3] = pe + ke;
+      row[4] = na > 1 ? 2.0 * ke / ((3.0 * na - 3.0) * KB) : 0.0;
+      row[5] = (double)D.stats[S_REBUILD];
     }
-    row[0] = s;
-    row[1] = pe;
-    row[2] = ke;
-    row[3] = pe + ke;
-    row[4] = D.n > 1 ? 2.0 * ke / ((3.0 * D.n - 3.0) * KB) : 0.0;
-    row[5] = (double)D.stats[S_REBUILD];
   }
-  *D.step = s + 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && blockIdx.x == 0) *D.step = s + 1;
 }
 
 __global__ void k_store(Dev D, double* pos) {
@@ -1331,6 +1468,16 @@ struct airebo_ctx {
   int* step = nullptr;
   size_t c_stp = 0;
   unsigned long long host_stats[S_N] = {};
+  // batch description
+  int ncell = 0;
+  std::vector<SysBox> hsys;
+  std::vector<int> hatom_sys;
+  SysBox* dsys = nullptr;
+  size_t c_dsys = 0;
+  int* atom_sys = nullptr;
+  size_t c_asys = 0;
+  double* sys_acc = nullptr;
+  size_t c_sacc = 0;
   // per-kernel timing (profile mode)
   bool prof = false;
   struct Ev { int k; hipEvent_t a, b; };
@@ -1375,6 +1522,9 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
   if (o.precision != AIREBO_FP64 && o.precision != AIREBO_MIXED) return fail(AIREBO_E_ARG, "unknown precision");
   if (o.term_mask < 0 || o.term_mask > 7) return fail(AIREBO_E_ARG, "bad term mask");
   if (o.lj_cap < 0) return fail(AIREBO_E_ARG, "bad lj_cap");
+  auto okb = [](int b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; };
+  if (!okb(o.bond_block) || !okb(o.defer_block) || !okb(o.short_block) || o.bond_grid < 0)
+    return fail(AIREBO_E_ARG, "launch shapes must be 0 or 64, 128, 192, 256 threads");
   airebo_ctx* c = new airebo_ctx();
   c->opt = o;
   std::vector<double> tri((size_t)TRI_N * kTriCells * kTriCoef);
@@ -1405,7 +1555,7 @@ void airebo_ctx_free(airebo_ctx_t c) {
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->xsort, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
                   c->cell_atoms, c->lj_n, c->lj_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
-                  c->bcount, c->bonds, c->qcount, c->q, c->F, c->acc,
+                  c->bcount, c->bonds, c->qcount, c->q, c->F, c->acc, c->dsys, c->atom_sys, c->sys_acc,
                   c->stats, c->flags, c->step};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -1416,28 +1566,44 @@ void airebo_ctx_free(airebo_ctx_t c) {
 
 namespace {
 
-// Size buffers for n atoms and the given box; fill the Dev descriptor.
-int setup(airebo_ctx* c, int64_t n, const double* box, const int32_t* per) {
-  if (n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
-  if (!box || !per) return fail(AIREBO_E_ARG, "null box or periodic");
+// Size buffers for a batch of nsys systems (atoms of system k are
+// [off[k], off[k+1]); box and periodic flags [nsys][3]); fill the Dev
+// descriptor and upload the per-system boxes.
+int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, hipStream_t s) {
+  if (nsys < 1 || !off || !boxes || !pers) return fail(AIREBO_E_ARG, "null box, periodic or offsets");
+  int64_t n = off[nsys] - off[0];
+  if (off[0] != 0 || n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
   const DevParams& P = c->P;
   double rlist = P.rc_max + c->opt.skin;
   Dev& D = c->D;
   std::memset(&D, 0, sizeof D);
   D.n = (int)n;
+  D.nsys = nsys;
   D.skin = c->opt.skin;
-  size_t ncell = 1;
-  for (int d = 0; d < 3; ++d) {
-    if (!(box[d] > 0) || !std::isfinite(box[d])) return fail(AIREBO_E_BOX, "box lengths must be positive");
-    D.L[d] = box[d];
-    D.invL[d] = 1.0 / box[d];
-    D.per[d] = per[d] ? 1 : 0;
-    if (D.per[d] && box[d] < std::max({12.0, P.rc_max + c->opt.skin}))
-      return fail(AIREBO_E_BOX, "periodic box side must be at least max(12 A, LJ cutoff + skin)");
-    D.nc[d] = std::max(1, (int)std::floor(box[d] / rlist));
-    D.nc[d] = std::min(D.nc[d], 1024);
-    ncell *= D.nc[d];
+  c->hsys.resize(nsys);
+  c->hatom_sys.clear();
+  size_t ncell = 0;
+  for (int k = 0; k < nsys; ++k) {
+    if (off[k + 1] < off[k]) return fail(AIREBO_E_ARG, "system offsets must not decrease");
+    SysBox& B = c->hsys[k];
+    std::memset(&B, 0, sizeof B);
+    size_t nc_k = 1;
+    for (int d = 0; d < 3; ++d) {
+      double L = boxes[3 * k + d];
+      if (!(L > 0) || !std::isfinite(L)) return fail(AIREBO_E_BOX, "box lengths must be positive");
+      B.L[d] = L;
+      B.invL[d] = 1.0 / L;
+      B.per[d] = pers[3 * k + d] ? 1 : 0;
+      if (B.per[d] && L < std::max({12.0, P.rc_max + c->opt.skin}))
+        return fail(AIREBO_E_BOX, "periodic box side must be at least max(12 A, LJ cutoff + skin)");
+      B.nc[d] = std::min(std::max(1, (int)std::floor(L / rlist)), 1024);
+      nc_k *= B.nc[d];
+    }
+    B.cell_off = (int)ncell;
+    B.natoms = (int)(off[k + 1] - off[k]);
+    ncell += nc_k;
   }
+  c->ncell = (int)ncell;
   for (int p = 0; p < 3; ++p) {
     D.rlist2[p] = (P.rc[p] + c->opt.skin) * (P.rc[p] + c->opt.skin);
     D.rint2[p] = (P.R2[p] + c->opt.skin) * (P.R2[p] + c->opt.skin);
@@ -1467,14 +1633,29 @@ int setup(airebo_ctx* c, int64_t n, const double* box, const int32_t* per) {
   size_t bcap = N * SCAP / 2 + 64;
   rc |= grow(c->bonds, c->c_b, 3 * bcap);
   rc |= grow(c->qcount, c->c_qc, NSEG * QSTRIDE);
-  size_t qcap = (4 * N + 1024 * NSEG) / NSEG;   // per segment
+  size_t qcap = (8 * N + 1024 * NSEG) / NSEG;   // per segment
   rc |= grow(c->q, c->c_q, qcap * NSEG);
   rc |= grow(c->F, c->c_F, 3 * N);
   rc |= grow(c->acc, c->c_acc, NSLOT * A_N);
   rc |= grow(c->stats, c->c_st, S_N);
   rc |= grow(c->flags, c->c_fl, 4);
   rc |= grow(c->step, c->c_stp, 4);
+  rc |= grow(c->dsys, c->c_dsys, nsys);
+  if (nsys > 1) {
+    rc |= grow(c->atom_sys, c->c_asys, N);
+    rc |= grow(c->sys_acc, c->c_sacc, (size_t)nsys * A_N);
+  }
   if (rc) return AIREBO_E_DEVICE;
+  HIPCHK(hipMemcpyAsync(c->dsys, c->hsys.data(), sizeof(SysBox) * nsys, hipMemcpyHostToDevice, s));
+  if (nsys > 1) {
+    c->hatom_sys.resize(n);
+    for (int k = 0; k < nsys; ++k)
+      for (int64_t i = off[k]; i < off[k + 1]; ++i) c->hatom_sys[i] = k;
+    HIPCHK(hipMemcpyAsync(c->atom_sys, c->hatom_sys.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  }
+  D.sys = c->dsys;
+  D.atom_sys = nsys > 1 ? c->atom_sys : nullptr;
+  D.sys_acc = nsys > 1 ? c->sys_acc : nullptr;
   D.x = c->x; D.xref = c->xref; D.xsort = c->xsort; D.cell_of = c->cell_of; D.cell_count = c->cell_count; D.cell_start = c->cell_start;
   D.cell_cursor = c->cell_cursor; D.cell_atoms = c->cell_atoms; D.lj_cap = c->lj_cap; D.lj_n = c->lj_n;
   D.lj_e = c->lj_e; D.in_n = c->in_n; D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
@@ -1489,7 +1670,7 @@ inline int blocks(int64_t n, int t) { return (int)std::max<int64_t>(1, (n + t - 
 // Launch the rebuild chain (kernels check the rebuild flag on the device).
 void launch_rebuild(airebo_ctx* c, hipStream_t s) {
   Dev& D = c->D;
-  int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+  int ncell = c->ncell;
   LAUNCH(c, K_BIN, k_bin, dim3(blocks(D.n, 256)), dim3(256), s, D);
   LAUNCH(c, K_SCAN, k_scan, dim3(1), dim3(1024), s, D, ncell);
   LAUNCH(c, K_FILL, k_fill, dim3(blocks(D.n, 256)), dim3(256), s, D);
@@ -1502,9 +1683,12 @@ void launch_forces(airebo_ctx* c, hipStream_t s) {
   Dev& D = c->D;
   const DevParams* P = c->dP;
   int mask = c->opt.term_mask;
-  LAUNCH(c, K_ZERO, k_zero, dim3(std::min(std::max(blocks(3 * (int64_t)D.n, 256), NSLOT * A_N / 256), 4096)),
+  LAUNCH(c, K_ZERO, k_zero,
+         dim3(std::min(std::max({blocks(3 * (int64_t)D.n, 256), NSLOT * A_N / 256, blocks((int64_t)D.nsys * A_N, 256)}),
+                       4096)),
          dim3(256), s, D);
-  LAUNCH(c, K_SHORT, k_short, dim3(blocks(D.n, 128)), dim3(128), s, D, P);
+  int sblk = c->opt.short_block ? c->opt.short_block : 128;
+  LAUNCH(c, K_SHORT, k_short, dim3(blocks(D.n, sblk)), dim3(sblk), s, D, P);
   // fork: the bonded kernel runs on the side stream beside the LJ chain (the
   // profiler's per-kernel events keep everything on one stream)
   bool fork = !c->prof && (mask & AIREBO_TERM_LJ) && (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION));
@@ -1514,12 +1698,23 @@ void launch_forces(airebo_ctx* c, hipStream_t s) {
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     sb = c->side;
   }
-  int nb = std::min(blocks((int64_t)D.n * 2, 64), 8192);
-  if (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION))
-    LAUNCH(c, K_BOND, k_bond<double>, dim3(nb), dim3(64), sb, D, P, mask);
+  int bblk = c->opt.bond_block ? c->opt.bond_block : 64;
+  int nb = c->opt.bond_grid ? c->opt.bond_grid : std::min(blocks((int64_t)D.n * 2, bblk), 8192);
+  int qblk = c->opt.defer_block ? c->opt.defer_block : 64;
+  bool mixed = c->opt.precision == AIREBO_MIXED;
+  if (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION)) {
+    if (mixed) LAUNCH(c, K_BOND, k_bond<float>, dim3(nb), dim3(bblk), sb, D, P, mask);
+    else LAUNCH(c, K_BOND, k_bond<double>, dim3(nb), dim3(bblk), sb, D, P, mask);
+  }
   if (mask & AIREBO_TERM_LJ) {
-    LAUNCH(c, K_LJ, k_lj, dim3(blocks((int64_t)D.n * WAVE, LJ_BLOCK)), dim3(LJ_BLOCK), s, D, P);
-    LAUNCH(c, K_BSTAR, k_bstar<double>, dim3(std::min(blocks(D.n, 64), 4096)), dim3(64), s, D, P);
+    dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK)), gq(std::min(blocks(D.n, qblk), 4096));
+    if (mixed) {
+      LAUNCH(c, K_LJ, k_lj<float>, glj, dim3(LJ_BLOCK), s, D, P);
+      LAUNCH(c, K_BSTAR, k_bstar<float>, gq, dim3(qblk), s, D, P);
+    } else {
+      LAUNCH(c, K_LJ, k_lj<double>, glj, dim3(LJ_BLOCK), s, D, P);
+      LAUNCH(c, K_BSTAR, k_bstar<double>, gq, dim3(qblk), s, D, P);
+    }
   }
   if (fork) {
     (void)hipEventRecord(c->ev_join, c->side);
@@ -1538,27 +1733,31 @@ int check_flags(airebo_ctx* c, int flags) {
   return 0;
 }
 
-// One evaluation; forces == nullptr evaluates into the context's own buffer.
-int compute_impl(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
-                 const int32_t* periodic, double* energy, double* forces, double* virial, void* stream) {
+// One evaluation of a batch; forces == nullptr evaluates into the context's
+// own buffer.  energy [nsys][4], virial [nsys][6] (device).
+int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers,
+                 const double* pos, const int32_t* species, double* energy, double* forces, double* virial,
+                 void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->opt.device));
   for (int attempt = 0; attempt < 4; ++attempt) {
-    int rc = setup(c, n, box, periodic);
+    int rc = setup(c, nsys, off, boxes, pers, s);
     if (rc) return rc;
     Dev& D = c->D;
+    int64_t n = D.n;
     D.F = forces ? forces : c->F;
     HIPCHK(hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s));
     hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
-    HIPCHK(hipMemsetAsync(c->cell_count, 0, sizeof(int) * D.nc[0] * D.nc[1] * D.nc[2], s));
+    HIPCHK(hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, s));
     if (n > 0) {
       hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
       launch_rebuild(c, s);
       launch_forces(c, s);
     } else {
-      hipLaunchKernelGGL(k_zero, dim3(NSLOT * A_N / 256), dim3(256), 0, s, D);
+      hipLaunchKernelGGL(k_zero, dim3(std::max(NSLOT * A_N / 256, blocks((int64_t)nsys * A_N, 256))), dim3(256), 0,
+                         s, D);
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, D, energy, virial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, energy, virial);
     if (n > 0) {
       int g = std::min(blocks(n, 256), 1024);
       hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.stats + S_MAXLJ);
@@ -1577,53 +1776,41 @@ int compute_impl(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* sp
   return fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established");
 }
 
-}  // namespace
-
-extern "C" {
-
-int airebo_compute(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
-                   const int32_t* periodic, double* energy, double* forces, double* virial, void* stream) {
-  if (!c || (n > 0 && (!pos || !species || !forces)) || !energy || !virial) return fail(AIREBO_E_ARG, "null argument");
-  return compute_impl(c, n, pos, species, box, periodic, energy, forces, virial, stream);
-}
-
-int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species, const double* box,
-               const int32_t* periodic, const double* mass, double dt, int64_t nsteps, int64_t every,
-               double* thermo, void* stream) {
-  if (!c || (n > 0 && (!pos || !vel || !species)) || !mass) return fail(AIREBO_E_ARG, "null argument");
-  if (nsteps < 0 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0)) return fail(AIREBO_E_ARG, "bad step count, dt or mass");
-  if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+// Velocity Verlet over a batch; thermo [rows][nsys][6] (device).
+int nve_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, double* pos,
+             double* vel, const int32_t* species, const double* mass, double dt, int64_t nsteps, int64_t every,
+             double* thermo, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->opt.device));
+  int64_t n = off[nsys] - off[0];
   if (n == 0) return 0;
   // establish list capacity with a plain evaluation first
-  double *e4 = nullptr, *w6 = nullptr;
-  HIPCHK(hipMalloc((void**)&e4, 16 * sizeof(double)));
-  w6 = e4 + 8;
-  int rc = compute_impl(c, n, pos, species, box, periodic, e4, nullptr, w6, stream);
-  if (rc) { hipFree(e4); return rc; }
+  double* scratch = nullptr;
+  HIPCHK(hipMalloc((void**)&scratch, sizeof(double) * 10 * (size_t)nsys));
+  int rc = compute_impl(c, nsys, off, boxes, pers, pos, species, scratch, nullptr, scratch + 4 * (size_t)nsys, stream);
+  if (rc) { (void)hipFree(scratch); return rc; }
   // headroom for list growth between rebuilds
   c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32, 1u << 16);
-  rc = setup(c, n, box, periodic);
-  if (rc) { hipFree(e4); return rc; }
+  rc = setup(c, nsys, off, boxes, pers, s);
+  if (rc) { (void)hipFree(scratch); return rc; }
   Dev& D = c->D;
   D.F = c->F;
   int nrows = every > 0 ? (int)(nsteps / every) + 1 : 0;
   double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
-  int ncell = D.nc[0] * D.nc[1] * D.nc[2];
+  int tb = std::min(1024, std::max(64, ((nsys + 63) / 64) * 64));
   hipError_t err = hipSuccess;
   auto body = [&](bool first) {
     if (first) {
       hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
-      hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s);
-      hipMemsetAsync(c->cell_count, 0, sizeof(int) * ncell, s);
-      hipMemsetAsync(c->step, 0, sizeof(int), s);
+      (void)hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s);
+      (void)hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, s);
+      (void)hipMemsetAsync(c->step, 0, sizeof(int), s);
       hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
       launch_rebuild(c, s);
       launch_forces(c, s);
       // kinetic energy of the initial state (zero-length kick)
       hipLaunchKernelGGL(k_kick, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], 0.0);
-      hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
+      hipLaunchKernelGGL(k_thermo, dim3(1), dim3(tb), 0, s, D, thermo, (int)every, nrows);
       return;
     }
     LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt,
@@ -1631,7 +1818,7 @@ int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_
     launch_rebuild(c, s);
     launch_forces(c, s);
     LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt);
-    LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(64), s, D, thermo, (int)every, nrows);
+    LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(tb), s, D, thermo, (int)every, nrows);
   };
   body(true);
   if (c->prof) {   // per-kernel timing: eager launches, one event pair per kernel
@@ -1659,18 +1846,64 @@ int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_
   if (err == hipSuccess && cs) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) err = hipGraphLaunch(exec, cs);
   if (err == hipSuccess && cs) err = hipStreamSynchronize(cs);
-  if (exec) hipGraphExecDestroy(exec);
-  if (graph) hipGraphDestroy(graph);
-  if (cs) hipStreamDestroy(cs);
-  if (err != hipSuccess) { hipFree(e4); return fail(AIREBO_E_DEVICE, std::string("nve: ") + hipGetErrorString(err)); }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (err != hipSuccess) {
+    (void)hipFree(scratch);
+    return fail(AIREBO_E_DEVICE, std::string("nve: ") + hipGetErrorString(err));
+  }
   hipLaunchKernelGGL(k_store, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos);
   int flags = 0;
   HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  hipFree(e4);
+  (void)hipFree(scratch);
   if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded during NVE");
   return check_flags(c, flags);
+}
+
+}  // namespace
+
+extern "C" {
+
+int airebo_compute(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
+                   const int32_t* periodic, double* energy, double* forces, double* virial, void* stream) {
+  if (!c || (n > 0 && (!pos || !species || !forces)) || !energy || !virial || !box || !periodic)
+    return fail(AIREBO_E_ARG, "null argument");
+  if (n < 0) return fail(AIREBO_E_ARG, "n must be >= 0");
+  int64_t off[2] = {0, n};
+  return compute_impl(c, 1, off, box, periodic, pos, species, energy, forces, virial, stream);
+}
+
+int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species, const double* box,
+               const int32_t* periodic, const double* mass, double dt, int64_t nsteps, int64_t every,
+               double* thermo, void* stream) {
+  if (!c || (n > 0 && (!pos || !vel || !species)) || !mass || !box || !periodic)
+    return fail(AIREBO_E_ARG, "null argument");
+  if (n < 0 || nsteps < 0 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0))
+    return fail(AIREBO_E_ARG, "bad n, step count, dt or mass");
+  if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+  int64_t off[2] = {0, n};
+  return nve_impl(c, 1, off, box, periodic, pos, vel, species, mass, dt, nsteps, every, thermo, stream);
+}
+
+int airebo_batch_compute(airebo_ctx_t c, int32_t nsys, const int64_t* sys_off, const double* boxes,
+                         const int32_t* periodic, const double* pos, const int32_t* species, double* energy,
+                         double* forces, double* virial, void* stream) {
+  if (!c || nsys < 1 || !sys_off || !boxes || !periodic || !energy || !virial) return fail(AIREBO_E_ARG, "null argument");
+  if (sys_off[nsys] > 0 && (!pos || !species || !forces)) return fail(AIREBO_E_ARG, "null argument");
+  return compute_impl(c, nsys, sys_off, boxes, periodic, pos, species, energy, forces, virial, stream);
+}
+
+int airebo_batch_nve(airebo_ctx_t c, int32_t nsys, const int64_t* sys_off, const double* boxes,
+                     const int32_t* periodic, double* pos, double* vel, const int32_t* species, const double* mass,
+                     double dt, int64_t nsteps, int64_t every, double* thermo, void* stream) {
+  if (!c || nsys < 1 || !sys_off || !boxes || !periodic || !mass) return fail(AIREBO_E_ARG, "null argument");
+  if (sys_off[nsys] > 0 && (!pos || !vel || !species)) return fail(AIREBO_E_ARG, "null argument");
+  if (nsteps < 0 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0)) return fail(AIREBO_E_ARG, "bad step count, dt or mass");
+  if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+  return nve_impl(c, nsys, sys_off, boxes, periodic, pos, vel, species, mass, dt, nsteps, every, thermo, stream);
 }
 
 int airebo_profile_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species,

@@ -285,7 +285,7 @@ def _grow_all(pk, n_chains, nC, rng, K=24, lo=None, hi=None):
     sweeps = 0
     while not all(ch.done for ch in chains):
         sweeps += 1
-        if sweeps > 20 * nC:
+        if sweeps > 100 * nC:
             raise RuntimeError("chain growth did not converge")
         for c in rng.permutation(n_chains):
             ch = chains[c]
@@ -591,3 +591,304 @@ def graphene_flake(nx, ny, cc=1.42):
             v = _unit(2 * C[i] - C[nb[0]] - C[nb[1]])
             xs.append(C[i] + CH * v); ss.append(1)
     return np.array(xs), np.array(ss, np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Crystalline slabs and the ~10^6-atom hybrid system
+# ---------------------------------------------------------------------------
+DIAMOND_A = 3.567
+GRAPHITE_CC = 1.42
+GRAPHITE_GAP = 3.35
+
+
+def graphite_stack(nx, ny, layers, lx=None, ly=None):
+    """AB graphite: nx x ny rectangular cells (a, 3 d) of 4 atoms per layer,
+    optionally scaled in-plane to lx, ly; layers 3.35 A apart, origin at z = 0."""
+    d = GRAPHITE_CC
+    a = d * math.sqrt(3.0)
+    basis = np.array([[0, 0], [a / 2, d / 2], [a / 2, 1.5 * d], [0, 2 * d]])
+    cells = np.array([[i * a, j * 3 * d] for i in range(nx) for j in range(ny)])
+    layer = (cells[:, None, :] + basis[None]).reshape(-1, 2)
+    sx = 1.0 if lx is None else lx / (nx * a)
+    sy = 1.0 if ly is None else ly / (ny * 3 * d)
+    out = []
+    for k in range(layers):
+        xy = layer + (np.array([0.0, d]) if k % 2 else 0.0)
+        z = np.full((len(xy), 1), k * GRAPHITE_GAP)
+        out.append(np.hstack([xy * [sx, sy], z]))
+    x = np.vstack(out)
+    x[:, 1] %= ny * 3 * d * sy
+    return x, np.zeros(len(x), np.int32)
+
+
+def diamond111_slab(nx, ny, bilayers, a=DIAMOND_A, lx=None, ly=None):
+    """H-terminated diamond (111) slab: orthorhombic cells (a/sqrt2, a sqrt6/2)
+    in-plane, `bilayers` (111) bilayers, one H per dangling bond, origin z = 0."""
+    R = np.array([[1, -1, 0], [1, 1, -2], [1, 1, 1]], float)
+    R /= np.linalg.norm(R, axis=1, keepdims=True)
+    c1, c2, c3 = a / math.sqrt(2), a * math.sqrt(6) / 2, a * math.sqrt(3)
+    fcc = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    basis = np.vstack([fcc, fcc + 0.25]) * a
+    rng_ = range(-4, 5)
+    pts = np.array([[i, j, k] for i in rng_ for j in rng_ for k in rng_], float) * a
+    lat = (pts[:, None, :] + basis[None]).reshape(-1, 3) @ R.T
+    frac = lat / [c1, c2, c3]
+    keep = np.all((frac >= -1e-6) & (frac < 1 - 1e-6), axis=1)
+    cell = lat[keep]
+    assert len(cell) == 12, len(cell)
+    nz = bilayers // 3 + 2
+    reps = np.array([[i, j, k] for i in range(nx) for j in range(ny) for k in range(nz)], float) * [c1, c2, c3]
+    C = (reps[:, None, :] + cell[None]).reshape(-1, 3)
+    # bilayers: z-levels come in pairs 0.515 A apart; cut through the 1.545 A vertical bonds
+    zs = np.unique(np.round(C[:, 2], 3))
+    pairs = [(zs[i], zs[i + 1]) for i in range(0, len(zs) - 1) if zs[i + 1] - zs[i] < 0.8]
+    # choose pairs that form true bilayers (first of each pair is the lower sublayer)
+    bl = []
+    for lo, hi in pairs:
+        if not bl or lo > bl[-1][1] + 0.1:
+            bl.append((lo, hi))
+    bl = bl[1:1 + bilayers]
+    zmin, zmax = bl[0][0] - 0.01, bl[-1][1] + 0.01
+    C = C[(C[:, 2] >= zmin) & (C[:, 2] <= zmax)]
+    C[:, 2] -= C[:, 2].min()
+    L = np.array([nx * c1, ny * c2])
+    # hydrogens on under-coordinated surface carbons
+    from scipy.spatial import cKDTree
+    xy = C.copy()
+    xy[:, :2] %= L
+    xy[:, :2] = np.where(xy[:, :2] >= L, xy[:, :2] - L, xy[:, :2])
+    tree = cKDTree(xy, boxsize=[L[0], L[1], 1e6])
+    pairs = tree.query_pairs(1.7, output_type="ndarray")
+    deg = np.bincount(pairs.ravel(), minlength=len(C))
+    nbsum = np.zeros_like(C)
+    for a_, b_ in ((0, 1), (1, 0)):
+        d = xy[pairs[:, b_]] - xy[pairs[:, a_]]
+        d[:, :2] -= L * np.round(d[:, :2] / L)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        np.add.at(nbsum, pairs[:, a_], d)
+    H = []
+    for i in np.where(deg == 3)[0]:
+        u = -nbsum[i] / np.linalg.norm(nbsum[i])
+        H.append(xy[i] + CH * u)
+    x = np.vstack([xy, np.array(H)])
+    s = np.concatenate([np.zeros(len(xy), np.int32), np.ones(len(H), np.int32)])
+    if lx is not None:
+        sc = np.array([lx / L[0], ly / L[1]])
+        x[:, :2] = (x[:, :2] % L) * sc
+        L = L * sc
+    return x, s, L
+
+
+def pe_melt_cell(n_chains, lx, ly, density_gcc=0.85, n_carbon=100, seed=SEED0 + 21, T=300.0):
+    """Periodic melt cell with in-plane sides lx, ly (cached like pe_melt)."""
+    mass = n_chains * (n_carbon * MASS[0] + (2 * n_carbon + 2) * MASS[1])
+    lz = mass * 1.66053906660 / density_gcc / (lx * ly)
+    return pe_melt(n_chains, n_carbon, density_gcc, seed, T, shape=(lx, ly, lz))
+
+
+def hybrid_1m(seed=SEED0 + 2, T=300.0, melt_tiles=(2, 2, 5)):
+    """~10^6 atoms: AB graphite stack (30 layers), H-terminated diamond (111)
+    slab (31 bilayers) and a polyethylene melt slab (tiles of the 32,012-atom
+    melt), stacked along z with 3.4 A gaps in one periodic box.  The in-plane
+    cell is that of the tiled melt; the crystals are strained to it (diamond
+    by about 1%, graphite by about 0.3%)."""
+    tile = pe_melt()
+    tb = tile["box"]
+    lx, ly = melt_tiles[0] * tb[0], melt_tiles[1] * tb[1]
+    c1, c2 = DIAMOND_A / math.sqrt(2), DIAMOND_A * math.sqrt(6) / 2
+    dx, ds, L = diamond111_slab(int(round(lx / c1)), int(round(ly / c2)), 31, lx=lx, ly=ly)
+    ga = GRAPHITE_CC * math.sqrt(3)
+    gx, gs = graphite_stack(int(round(lx / ga)), int(round(ly / (3 * GRAPHITE_CC))), 30, lx=lx, ly=ly)
+    # unwrap every chain of the melt cell along z (atoms of a chain are stored
+    # together; each atom taken at the image nearest to the previous one)
+    per = 3 * 100 + 2
+    cz = tile["x"][:, 2].reshape(-1, per).copy()
+    step = np.diff(cz, axis=1)
+    cz[:, 1:] = cz[:, :1] + np.cumsum(step - tb[2] * np.round(step / tb[2]), axis=1)
+    cell = tile["x"].copy()
+    cell[:, 2] = cz.ravel()
+    reps = [(a, b, c) for a in range(melt_tiles[0]) for b in range(melt_tiles[1]) for c in range(melt_tiles[2])]
+    mx = np.vstack([cell + np.array(r) * tb for r in reps])
+    ms = np.tile(tile["species"], len(reps))
+    # stacked copies stay continuous inside the block; chains that cross the
+    # block's outer z faces (which border the crystals) are removed whole
+    hz = melt_tiles[2] * tb[2]
+    nch = len(ms) // per
+    zc = mx[:, 2].reshape(nch, per)
+    keep = (zc.min(1) >= 0.0) & (zc.max(1) < hz)
+    mx = mx.reshape(nch, per, 3)[keep].reshape(-1, 3)
+    ms = ms.reshape(nch, per)[keep].ravel()
+    mx[:, :2] %= [melt_tiles[0] * tb[0], melt_tiles[1] * tb[1]]
+    gap = 3.4
+    parts, z = [], 0.0
+    for x, s in ((gx, gs), (dx, ds), (mx, ms)):
+        x = x.copy()
+        x[:, 2] += z - x[:, 2].min()
+        parts.append((x, s))
+        z = x[:, 2].max() + gap
+    X = np.vstack([p[0] for p in parts])
+    S = np.concatenate([p[1] for p in parts])
+    box = np.array([lx, ly, z])
+    X[:, :2] %= box[:2]
+    rng = np.random.default_rng(seed)
+    V = maxwell_velocities(S, T, rng)
+    meta = dict(kind="hybrid_1m", graphite=len(gs), diamond=int((ds == 0).sum()), diamond_h=int((ds == 1).sum()),
+                melt=len(ms), melt_chains=int(keep.sum()), seed=seed)
+    return dict(x=X, species=S, box=box, periodic=np.ones(3, np.int32), v=V, meta=meta)
+
+
+# ---------------------------------------------------------------------------
+# Batches of small systems
+# ---------------------------------------------------------------------------
+def diamond_cluster(radius, a=DIAMOND_A):
+    """H-terminated piece of diamond: lattice sites within `radius` of the
+    origin, every missing tetrahedral bond capped with H (carbons left with
+    no carbon neighbour are dropped)."""
+    fcc = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    n = int(math.ceil(radius / a)) + 1
+    cells = np.array([[i, j, k] for i in range(-n, n + 1) for j in range(-n, n + 1) for k in range(-n, n + 1)], float)
+    A = ((cells[:, None] + fcc[None]) * a).reshape(-1, 3)
+    B = A + a / 4
+    dirs_a = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float) / 4 * a
+    sites = [(p, +1) for p in A if np.linalg.norm(p) <= radius] + [(p, -1) for p in B if np.linalg.norm(p) <= radius]
+    pos = np.array([p for p, _ in sites])
+    sub = np.array([g for _, g in sites])
+    key = {tuple(np.round(p, 3)): i for i, p in enumerate(pos)}
+    # grow the site set until no empty site has two or more occupied neighbours
+    # (two caps pointing into one vacancy would collide)
+    changed = True
+    while changed:
+        changed = False
+        cand = {}
+        for p, g in zip(pos, sub):
+            for d in dirs_a:
+                q = tuple(np.round(p + g * d, 3))
+                if q not in key:
+                    cand.setdefault(q, [np.array(q), -g, 0])[2] += 1
+        for q, (p, g, cnt) in cand.items():
+            if cnt >= 2:
+                key[q] = len(pos)
+                pos = np.vstack([pos, p])
+                sub = np.append(sub, g)
+                changed = True
+    keep = []
+    for i, (p, g) in enumerate(zip(pos, sub)):
+        nbc = sum(tuple(np.round(p + g * d, 3)) in key for d in dirs_a)
+        if nbc >= 1:
+            keep.append(i)
+    keepset = set(keep)
+    xs, ss = [], []
+    for i in keep:
+        xs.append(pos[i]); ss.append(0)
+        for d in dirs_a:
+            q = tuple(np.round(pos[i] + sub[i] * d, 3))
+            if q not in key or key[q] not in keepset:
+                xs.append(pos[i] + sub[i] * d / np.linalg.norm(d) * CH); ss.append(1)
+    return np.array(xs), np.array(ss, np.int32)
+
+
+def branched_alkane(n_carbon, rng):
+    """Alkane backbone with one or two methyl branches replacing hydrogens."""
+    x, s = alkane(n_carbon, torsions=list(rng.choice([math.pi, math.pi / 3, -math.pi / 3], size=max(0, n_carbon - 3))))
+    hs = np.where(s == 1)[0]
+    for h in rng.choice(hs, size=min(2, len(hs)), replace=False):
+        # carbon bonded to this hydrogen
+        c = int(np.argmin(np.where(s == 0, np.linalg.norm(x - x[h], axis=1), 1e9)))
+        u = _unit(x[h] - x[c])
+        cnew = x[c] + CC * u
+        ref = x[c] + np.cross(u, rng.normal(size=3))
+        hs3 = [_nerf(ref, x[c], cnew, CH, TETRA, t) for t in (0, 2 * math.pi / 3, -2 * math.pi / 3)]
+        x = np.vstack([x[:h], [cnew], x[h + 1:], hs3])
+        s = np.concatenate([s[:h], [0], s[h + 1:], [1, 1, 1]]).astype(np.int32)
+    return x, s
+
+
+FAMILIES = ("linear_alkane", "branched_alkane", "aromatic", "graphene_flake", "diamond_cluster")
+
+
+def _clean(x, s):
+    """True when every pair closer than the REBO range is a proper bond:
+    C-C 1.3-1.6 A, C-H 1.0-1.15 A, and no H-H pair below 1.7 A."""
+    d = np.linalg.norm(x[:, None] - x[None], axis=2)
+    iu = np.triu_indices(len(s), 1)
+    dd, a, b = d[iu], s[iu[0]], s[iu[1]]
+    hh = (a == 1) & (b == 1)
+    ch = (a + b) == 1
+    cc = (a == 0) & (b == 0)
+    bad = (hh & (dd < 1.7)) | (ch & ((dd < 1.0) | ((dd > 1.15) & (dd < 1.8)))) | \
+          (cc & ((dd < 1.3) | ((dd > 1.6) & (dd < 2.0))))
+    return not bad.any()
+
+
+def molecule(family, rng, tries=400):
+    """A random molecule of the family whose geometry is chemically clean."""
+    for _ in range(tries):
+        x, s = _molecule(family, rng)
+        if _clean(x, s):
+            return x, s
+    raise RuntimeError(f"could not build a clean {family} molecule")
+
+
+def _molecule(family, rng):
+    if family == "linear_alkane":
+        k = int(rng.integers(4, 17))
+        return alkane(k, torsions=list(rng.choice([math.pi, math.pi / 3, -math.pi / 3], size=max(0, k - 3))))
+    if family == "branched_alkane":
+        return branched_alkane(int(rng.integers(5, 13)), rng)
+    if family == "aromatic":
+        return ring_aromatic(int(rng.integers(1, 4)))
+    if family == "graphene_flake":
+        return graphene_flake(int(rng.integers(2, 5)), int(rng.integers(2, 4)))
+    return diamond_cluster(float(rng.uniform(2.5, 3.8)))
+
+
+def molecular_box(family, n_target, rng, density=0.05, min_side=13.0, min_dist=2.6, tries=200):
+    """Molecules of one family at random positions and orientations in a
+    periodic cube of side max((n/density)^(1/3), min_side) until ~n_target atoms."""
+    L = max((n_target / density) ** (1.0 / 3.0), min_side)
+    box = np.array([L, L, L])
+    X = np.zeros((0, 3))
+    S = np.zeros(0, np.int32)
+    fails = 0
+    while len(S) < n_target and fails < tries:
+        x, s = molecule(family, rng)
+        if len(S) + len(s) > 1.1 * n_target and len(S) > 0:
+            fails += 1
+            continue
+        x = (x - x.mean(0)) @ _random_rotation(rng).T + rng.uniform(0, L, 3)
+        if np.ptp(x, axis=0).max() > L - min_dist:
+            fails += 1
+            continue
+        if len(S):
+            d = x[:, None, :] - X[None, :, :]
+            d -= box * np.round(d / box)
+            if (d * d).sum(-1).min() < min_dist ** 2:
+                fails += 1
+                continue
+        X = np.vstack([X, x])
+        S = np.concatenate([S, s])
+    return X % box, S, box
+
+
+def batch_systems(nsys=512, nmin=50, nmax=5000, seed=SEED0 + 3, T=300.0):
+    """nsys independent systems (sizes log-uniform in [nmin, nmax]), families
+    round-robin, each in its own periodic cube; concatenated."""
+    rng = np.random.default_rng(seed)
+    xs, ss, vs, boxes, sizes, fams = [], [], [], [], [], []
+    for k in range(nsys):
+        fam = FAMILIES[k % len(FAMILIES)]
+        n_target = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        x, s, box = molecular_box(fam, n_target, rng)
+        xs.append(x); ss.append(s); boxes.append(box); sizes.append(len(s)); fams.append(fam)
+        vs.append(maxwell_velocities(s, T, rng))
+    return dict(x=np.vstack(xs), species=np.concatenate(ss), v=np.vstack(vs), boxes=np.array(boxes),
+                sizes=np.array(sizes), periodic=np.ones((nsys, 3), np.int32),
+                meta=dict(kind="batch", nsys=nsys, families=fams, seed=seed))
+
+
+def batch_cached(nsys=512, seed=SEED0 + 3):
+    def make():
+        d = batch_systems(nsys, seed=seed)
+        d["meta"] = {k: v for k, v in d["meta"].items() if k != "families"}
+        return d
+    return cached(f"batch_{nsys}_s{seed}", make)

@@ -178,3 +178,52 @@ def test_nve_energy_conservation():
     drift = np.abs(th[:, 3] - th[0, 3]).max() / len(d["species"])
     assert drift < 2e-4, drift      # eV/atom over 100 fs
     assert th[-1, 5] >= 1           # lists were rebuilt at least once
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision: pair and bond-order arithmetic in FP32 on FP64-formed
+# relative vectors, FP64 accumulation and near-knot splines.  Error bound:
+# FP32 unit roundoff 6e-8 amplified by the ~1e2 operations of a bond-order
+# chain and the cancellation between the large per-term gradients (|dE/dr| of
+# tens of eV/A) and the net forces (RMS ~3 eV/A): relative force error below
+# 1e-4, energy below 1e-6 relative.
+# ---------------------------------------------------------------------------
+TOL_MIXED_F, TOL_MIXED_E = 1e-4, 1e-6
+
+
+@pytest.fixture(scope="module")
+def mixed_ctx():
+    from paper_1810_07026_amd import airebo
+    c = airebo.Context(precision=airebo.MIXED)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("case", ["pe_small", "cluster", "flake", "tiled"])
+def test_mixed_error_bound(mixed_ctx, oracle, case):
+    if case == "pe_small":
+        d = synth.pe_small()
+    elif case == "cluster":
+        d = reactive_cluster(3, n=28)
+    elif case == "flake":
+        x, s = synth.graphene_flake(3, 3)
+        d = synth.isolated(x + np.random.default_rng(2).normal(scale=0.03, size=x.shape), s)
+    else:
+        d = synth.tile(synth.pe_small(seed=synth.SEED0 + 17), (2, 2, 1))
+    e, f, w = run_gpu(mixed_ctx, d)
+    eo, fo, wo = oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
+    rms = math.sqrt((fo ** 2).sum(1).mean())
+    ferr = np.abs(f - fo).max() / rms
+    assert ferr < TOL_MIXED_F, ferr
+    assert abs(e[0] - eo[0]) <= TOL_MIXED_E * max(abs(eo[0]), 1.0)
+    st = mixed_ctx.stats()
+    assert 0 < st["spline_evals_fp64"] <= st["spline_evals"]
+
+
+def test_mixed_is_not_fp64(mixed_ctx, ctxs):
+    """The mixed path really computes in FP32: its forces differ from FP64 at the FP32 level."""
+    d = synth.pe_small()
+    f32 = run_gpu(mixed_ctx, d)[1]
+    f64 = run_gpu(ctxs[7], d)[1]
+    diff = np.abs(f32 - f64).max() / math.sqrt((f64 ** 2).sum(1).mean())
+    assert 1e-9 < diff < TOL_MIXED_F
