@@ -137,7 +137,8 @@ int airebo_batch_nve(airebo_ctx_t ctx, int32_t nsys, const int64_t* sys_off, con
  *   4 bonds                                          5 neighbour-list rebuilds
  *   6 max short neighbours of one atom               7 reserved
  *   8 max LJ entries of one atom                     9 spline evaluations
- *  10 of those evaluated in FP64 near a knot (AIREBO_MIXED)   11-15 reserved
+ *  10 of those evaluated in FP64 near a knot (AIREBO_MIXED)
+ *  11 surrogate steps that fell back to AIREBO (airebo_nn_*)    12-15 reserved
  * Slots 0-4 and 9-10 refer to the last force evaluation (every step in NVE). */
 int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
 
@@ -154,6 +155,125 @@ int airebo_profile_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, co
                        double* ms_out, int64_t* launches_out, void* stream);
 int airebo_kernel_count(void);
 const char* airebo_kernel_name(int k);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate.  Not part of the paper: an approximation of the
+ * potential above (Sec. 2.1) by per-atom networks, with that potential as
+ * its fallback and as the judge of its error.
+ *
+ *   E = sum_i E_NN(G_i; s_i) + E_far
+ *
+ * G_i holds 112 symmetry functions of atom i.  The 64 radial ones are
+ * G[s*32 + m] = sum over neighbours j of species s with r < 6 A of
+ * exp(-eta (r - mu_m)^2) fc(r; 6), with mu_m = 0.8 + m 5.2/31 A and
+ * eta = 1 / (2 (2 5.2/31)^2).  The 48 angular ones are
+ * G[64 + 16 t + c] = 2^(1-zeta) sum over pairs j<k with s_j + s_k = t,
+ * both within 3.5 A, of (1 + lam cos theta_jik)^zeta
+ * exp(-eta_a (r_ij^2 + r_ik^2)) fc(r_ij; 3.5) fc(r_ik; 3.5), where
+ * c = 4 log2(zeta) + 2 [lam = -1] + [eta_a = 0.05], zeta in {1, 2, 4, 8},
+ * lam = +-1, eta_a in {0.005, 0.05} and fc(r; R) = (1 + cos(pi r / R)) / 2.
+ *
+ * E_NN(G; s) = scale * (w4 . h3 + b4) + shift[s] with
+ * h_k = SiLU(W_k h_{k-1} + b_k), h_0 = (G - mean) * istd and 64 units per
+ * layer.  There is one network per centre species, and each ensemble member
+ * holds its own pair.  Parameters of one network are 15,617 floats in the
+ * order W1 [64][112], b1 [64], W2 [64][64], b2, W3 [64][64], b3, w4 [64],
+ * b4 [1].  A member holds [2][15617] (species 0, then 1).  The networks run
+ * on BF16 matrix cores with FP32 accumulation.
+ *
+ * E_far is the LJ pair term of the context's parameters (with its outer
+ * cutoff switch) times a cubic switch that rises from 0 at 5 A to 1 at 6 A.
+ * It has no C_ij and no bond-order switch, and is evaluated in FP64.
+ *
+ * Every call takes the AIREBO context whose neighbour lists and integrator
+ * it uses.  Both objects must live on the same device.  Box rules and
+ * errors are those of the context.  AIREBO_E_CAPACITY is returned when an
+ * atom has more than 256 neighbours within 6 A or more than 48 within
+ * 3.5 A.  A surrogate object is not thread safe.
+ * ------------------------------------------------------------------------ */
+typedef struct airebo_nn* airebo_nn_t;
+
+/* New ensemble of nmodels (1..4) members: zero weights, mean 0, istd 1,
+ * scale 1, shift 0. */
+int airebo_nn_create(int32_t nmodels, int32_t device, airebo_nn_t* out);
+void airebo_nn_free(airebo_nn_t nn);
+/* Descriptor length (112) and floats per network (15617). */
+int airebo_nn_sizes(int32_t* dim, int32_t* params_per_net);
+int airebo_nn_models(airebo_nn_t nn);
+/* Weights, host arrays of [nmodels][2][15617] floats.  Setting them resets
+ * the optimiser state; non-finite values are rejected. */
+int airebo_nn_set_params(airebo_nn_t nn, const float* host);
+int airebo_nn_get_params(airebo_nn_t nn, float* host);
+/* Gradient left by the last airebo_nn_gradient, same layout (host). */
+int airebo_nn_get_grad(airebo_nn_t nn, float* host);
+/* Input normalisation mean[112] and istd[112] (> 0), output scale (> 0) and
+ * per-species shift[2] in eV, all host arrays. */
+int airebo_nn_set_norm(airebo_nn_t nn, const float* mean, const float* istd, double scale, const double* shift);
+int airebo_nn_get_norm(airebo_nn_t nn, float* mean, float* istd, double* scale, double* shift);
+/* Column sums and sums of squares of a device descriptor array G [rows][112]
+ * into mom_host[2][112] (host); synchronous. */
+int airebo_nn_moments(airebo_nn_t nn, const float* G, int64_t rows, double* mom_host, void* stream);
+
+/* Descriptors G [n][112] (device FP32) of a configuration.  Positions,
+ * species, box and periodic flags are as for airebo_compute.
+ * Synchronous. */
+int airebo_nn_descriptors(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species,
+                          const double* box, const int32_t* periodic, float* G, void* stream);
+/* Jacobian-vector product out[i][f] = sum_a dG_if/dx_a . w_a, with
+ * w [n][3] and out [n][112], both device FP32.  Synchronous. */
+int airebo_nn_descriptor_jvp(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species,
+                             const double* box, const int32_t* periodic, const float* w, float* out, void* stream);
+/* Vector-Jacobian product for nsets (1..4) sets of descriptor gradients:
+ * F[k][a] = -sum_{i,f} g[k][i][f] dG_if/dx_a.  g is [nsets][n][112] and F is
+ * [nsets][n][3], both device FP32.  virial[6] (device FP64) receives the
+ * virial of the mean over sets, {xx,yy,zz,xy,xz,yz}, as for airebo_compute.
+ * Synchronous. */
+int airebo_nn_descriptor_vjp(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species,
+                             const double* box, const int32_t* periodic, const float* g, int32_t nsets, float* F,
+                             double* virial, void* stream);
+
+/* One surrogate evaluation.  Forces are the ensemble mean plus the far field.
+ * spread[i] (device FP32, optional) is the RMS over members of
+ * |F_member - F_mean| for atom i.  When max_i spread > threshold (eV/A, > 0),
+ * the context's AIREBO evaluation replaces energy[0], the forces and the
+ * virial.  energy[4] (device) is {E used, E_NN ensemble mean, E_far,
+ * E_NN spread over members}; forces [n][3] and virial[6] are device FP64.
+ * info[5] (host, optional) is {E_NN mean, E_far, E_NN spread, max force
+ * spread, 1 if AIREBO was used else 0}.  Synchronous. */
+int airebo_nn_compute(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species,
+                      const double* box, const int32_t* periodic, double threshold, double* energy, double* forces,
+                      double* virial, float* spread, double* info, void* stream);
+/* Loss and gradient for one labelled configuration, for every member m:
+ *   L_m = w_force sum_i |F_m,i - (f_ref_i - F_far,i)|^2 + w_energy (E_m + E_far - e_ref)^2
+ * Here F_m and E_m are member m's network forces and energy, and f_ref [n][3]
+ * is device FP64 (e.g. AIREBO forces).  loss[nmodels] is host output.  The
+ * gradient with respect to every weight stays on the device for
+ * airebo_nn_adam or airebo_nn_get_grad.  Synchronous. */
+int airebo_nn_gradient(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species,
+                       const double* box, const int32_t* periodic, const double* f_ref, double e_ref, double w_force,
+                       double w_energy, double* loss, void* stream);
+/* One Adam step (bias-corrected) on every weight with the last gradient. */
+int airebo_nn_adam(airebo_nn_t nn, double lr, double beta1, double beta2, double eps, void* stream);
+/* Velocity Verlet with surrogate forces.  Arguments are as for airebo_nve,
+ * plus the fallback threshold (see airebo_nn_compute), which is checked every
+ * step on the device.  *fallbacks (host, optional) returns the number of
+ * steps evaluated by AIREBO.  thermo PE is the energy used for the step. */
+int airebo_nn_nve(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int32_t* species,
+                  const double* box, const int32_t* periodic, const double* mass, double dt_fs, int64_t nsteps,
+                  int64_t thermo_every, double* thermo, double threshold, int64_t* fallbacks, void* stream);
+/* Per-kernel timing of airebo_nn_nve; output as for airebo_profile_nve. */
+int airebo_nn_profile_nve(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, double* pos, double* vel,
+                          const int32_t* species, const double* box, const int32_t* periodic, const double* mass,
+                          double dt_fs, int64_t nsteps, double threshold, double* ms_out, int64_t* launches_out,
+                          void* stream);
+/* Save the weights and normalisation to a binary file; load one into a new
+ * object on `device`. */
+int airebo_nn_save(airebo_nn_t nn, const char* path);
+int airebo_nn_load(const char* path, int32_t device, airebo_nn_t* out);
+/* Check of the matrix-core lane layout: D = A B for 16x16 row-major FP32
+ * device matrices.  The inputs are rounded to BF16 and the products
+ * accumulated in FP32.  Asynchronous on `stream`. */
+int airebo_nn_mfma_check(const float* A, const float* B, float* D, void* stream);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* airebo_last_error(void);

@@ -17,11 +17,16 @@ DEFAULT_PARAMS = os.path.join(HERE, "params", "airebo_ch.param")
 FP64, MIXED = 0, 1
 TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
-              "reserved7", "max_lj", "spline_evals", "spline_evals_fp64"]
+              "reserved7", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks"]
 
 EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "airebo_compute", "airebo_nve",
            "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name",
-           "airebo_batch_compute", "airebo_batch_nve"]
+           "airebo_batch_compute", "airebo_batch_nve",
+           "airebo_nn_create", "airebo_nn_free", "airebo_nn_sizes", "airebo_nn_models", "airebo_nn_set_params",
+           "airebo_nn_get_params", "airebo_nn_get_grad", "airebo_nn_set_norm", "airebo_nn_get_norm",
+           "airebo_nn_moments", "airebo_nn_descriptors", "airebo_nn_descriptor_jvp", "airebo_nn_descriptor_vjp",
+           "airebo_nn_compute", "airebo_nn_gradient", "airebo_nn_adam", "airebo_nn_nve", "airebo_nn_profile_nve",
+           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check"]
 
 
 class AireboError(RuntimeError):
@@ -83,6 +88,40 @@ def load_library(path=LIB_PATH):
     L.airebo_batch_nve.restype = ctypes.c_int
     L.airebo_last_error.argtypes = []
     L.airebo_last_error.restype = ctypes.c_char_p
+    # learned surrogate
+    c_d, c_i32, c_i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+    hd, hi32 = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    geo = [vp, vp, c_i64, dp, ip, hd, hi32]      # nn, ctx, n, pos, species, box, periodic
+    sig = {
+        "airebo_nn_create": [c_i32, c_i32, ctypes.POINTER(ctypes.c_void_p)],
+        "airebo_nn_sizes": [hi32, hi32],
+        "airebo_nn_models": [vp],
+        "airebo_nn_set_params": [vp, vp],
+        "airebo_nn_get_params": [vp, vp],
+        "airebo_nn_get_grad": [vp, vp],
+        "airebo_nn_set_norm": [vp, vp, vp, c_d, hd],
+        "airebo_nn_get_norm": [vp, vp, vp, hd, hd],
+        "airebo_nn_moments": [vp, dp, c_i64, hd, vp],
+        "airebo_nn_descriptors": geo + [dp, vp],
+        "airebo_nn_descriptor_jvp": geo + [dp, dp, vp],
+        "airebo_nn_descriptor_vjp": geo + [dp, c_i32, dp, dp, vp],
+        "airebo_nn_compute": geo + [c_d, dp, dp, dp, dp, hd, vp],
+        "airebo_nn_gradient": geo + [dp, c_d, c_d, c_d, hd, vp],
+        "airebo_nn_adam": [vp, c_d, c_d, c_d, c_d, vp],
+        "airebo_nn_nve": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_i64, c_i64, dp, c_d,
+                          ctypes.POINTER(ctypes.c_int64), vp],
+        "airebo_nn_profile_nve": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_i64, c_d,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp],
+        "airebo_nn_save": [vp, ctypes.c_char_p],
+        "airebo_nn_load": [ctypes.c_char_p, c_i32, ctypes.POINTER(ctypes.c_void_p)],
+        "airebo_nn_mfma_check": [dp, dp, dp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.airebo_nn_free.argtypes = [vp]
+    L.airebo_nn_free.restype = None
     _lib = L
     return L
 
@@ -234,3 +273,195 @@ class Context:
         out = (ctypes.c_int64 * 16)()
         _check(self.L, self.L.airebo_stats(self.h, out))
         return dict(zip(STAT_NAMES, list(out)[:len(STAT_NAMES)]))
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Surrogate:
+    """Ensemble of descriptor networks (learned surrogate of the potential).
+
+    Every evaluation takes an AIREBO Context on the same device: its
+    neighbour lists, its integrator, and its AIREBO evaluation as the
+    fallback when the ensemble disagrees."""
+
+    def __init__(self, nmodels=4, device=0, path=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise AireboError(-7, "no GPU visible: the surrogate runs on the GPU only")
+        self.L = load_library()
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(self.L, self.L.airebo_nn_load(path.encode(), device, ctypes.byref(h)))
+        else:
+            _check(self.L, self.L.airebo_nn_create(nmodels, device, ctypes.byref(h)))
+        self.h = h
+        self.device = torch.device("cuda", device)
+        d, npar = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L, self.L.airebo_nn_sizes(ctypes.byref(d), ctypes.byref(npar)))
+        self.dim, self.npar = d.value, npar.value
+        self.nmodels = self.L.airebo_nn_models(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.airebo_nn_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _stream(self):
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _geo(self, ctx, x, species, box, periodic):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float64, device=self.device).reshape(-1, 3).contiguous()
+        s = torch.as_tensor(species, dtype=torch.int32, device=self.device).contiguous()
+        return x, s, [self.h, ctx.h, x.shape[0], _p(x), _p(s), _host3(box, ctypes.c_double),
+                      _host3(periodic, ctypes.c_int32)]
+
+    # ---- weights and normalisation
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(self.nmodels, 2, self.npar)
+        _check(self.L, self.L.airebo_nn_set_params(self.h, w.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        w = np.zeros((self.nmodels, 2, self.npar), np.float32)
+        _check(self.L, self.L.airebo_nn_get_params(self.h, w.ctypes.data_as(ctypes.c_void_p)))
+        return w
+
+    def get_grad(self):
+        g = np.zeros((self.nmodels, 2, self.npar), np.float32)
+        _check(self.L, self.L.airebo_nn_get_grad(self.h, g.ctypes.data_as(ctypes.c_void_p)))
+        return g
+
+    def set_norm(self, mean, istd, scale, shift):
+        mean = np.ascontiguousarray(mean, dtype=np.float32)
+        istd = np.ascontiguousarray(istd, dtype=np.float32)
+        sh = (ctypes.c_double * 2)(*shift)
+        _check(self.L, self.L.airebo_nn_set_norm(self.h, mean.ctypes.data_as(ctypes.c_void_p),
+                                                  istd.ctypes.data_as(ctypes.c_void_p), float(scale), sh))
+
+    def get_norm(self):
+        mean = np.zeros(self.dim, np.float32)
+        istd = np.zeros(self.dim, np.float32)
+        sc = ctypes.c_double()
+        sh = (ctypes.c_double * 2)()
+        _check(self.L, self.L.airebo_nn_get_norm(self.h, mean.ctypes.data_as(ctypes.c_void_p),
+                                                  istd.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sc), sh))
+        return mean, istd, sc.value, [sh[0], sh[1]]
+
+    def moments(self, G):
+        """Column sums and sums of squares of a device descriptor array [rows, dim]."""
+        mom = np.zeros(2 * self.dim)
+        _check(self.L, self.L.airebo_nn_moments(self.h, _p(G), G.shape[0],
+                                                 mom.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 self._stream()))
+        return mom[:self.dim], mom[self.dim:]
+
+    def save(self, path):
+        _check(self.L, self.L.airebo_nn_save(self.h, path.encode()))
+
+    # ---- descriptor operators
+    def descriptors(self, ctx, x, species, box, periodic=(1, 1, 1)):
+        import torch
+        x, s, a = self._geo(ctx, x, species, box, periodic)
+        G = torch.empty((x.shape[0], self.dim), dtype=torch.float32, device=self.device)
+        _check(self.L, self.L.airebo_nn_descriptors(*a, _p(G), self._stream()))
+        return G
+
+    def descriptor_jvp(self, ctx, x, species, box, w, periodic=(1, 1, 1)):
+        import torch
+        x, s, a = self._geo(ctx, x, species, box, periodic)
+        w = torch.as_tensor(w, dtype=torch.float32, device=self.device).reshape(-1, 3).contiguous()
+        out = torch.empty((x.shape[0], self.dim), dtype=torch.float32, device=self.device)
+        _check(self.L, self.L.airebo_nn_descriptor_jvp(*a, _p(w), _p(out), self._stream()))
+        return out
+
+    def descriptor_vjp(self, ctx, x, species, box, g, periodic=(1, 1, 1)):
+        """F[k] = -g[k] . dG/dx for sets g [k, n, dim]; returns (F [k, n, 3], virial [6])."""
+        import torch
+        x, s, a = self._geo(ctx, x, species, box, periodic)
+        g = torch.as_tensor(g, dtype=torch.float32, device=self.device).reshape(-1, x.shape[0], self.dim)
+        g = g.contiguous()
+        F = torch.empty((g.shape[0], x.shape[0], 3), dtype=torch.float32, device=self.device)
+        w = torch.empty(6, dtype=torch.float64, device=self.device)
+        _check(self.L, self.L.airebo_nn_descriptor_vjp(*a, _p(g), g.shape[0], _p(F), _p(w), self._stream()))
+        return F, w
+
+    # ---- evaluation, training, dynamics
+    def compute(self, ctx, x, species, box, periodic=(1, 1, 1), threshold=0.1, want_spread=False):
+        """Returns energy [4] (used, NN mean, far, NN spread), forces [n,3], virial [6] (device),
+        the per-atom force spread (device, or None) and info {E_nn, E_far, E_spread, max_spread,
+        fallback}."""
+        import torch
+        x, s, a = self._geo(ctx, x, species, box, periodic)
+        n = x.shape[0]
+        e = torch.empty(4, dtype=torch.float64, device=self.device)
+        f = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        w = torch.empty(6, dtype=torch.float64, device=self.device)
+        sp = torch.empty(n, dtype=torch.float32, device=self.device) if want_spread else None
+        info = (ctypes.c_double * 5)()
+        _check(self.L, self.L.airebo_nn_compute(*a, float(threshold), _p(e), _p(f), _p(w),
+                                                 _p(sp) if sp is not None else None, info, self._stream()))
+        keys = ("E_nn", "E_far", "E_spread", "max_spread", "fallback")
+        return e, f, w, sp, dict(zip(keys, list(info)))
+
+    def gradient(self, ctx, x, species, box, f_ref, e_ref, w_force, w_energy, periodic=(1, 1, 1)):
+        """Loss per member for one labelled configuration; leaves the gradient on the device."""
+        import torch
+        x, s, a = self._geo(ctx, x, species, box, periodic)
+        f_ref = torch.as_tensor(f_ref, dtype=torch.float64, device=self.device).reshape(-1, 3).contiguous()
+        loss = (ctypes.c_double * self.nmodels)()
+        _check(self.L, self.L.airebo_nn_gradient(*a, _p(f_ref), float(e_ref), float(w_force), float(w_energy),
+                                                  loss, self._stream()))
+        return np.array(list(loss))
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(self.L, self.L.airebo_nn_adam(self.h, lr, beta1, beta2, eps, self._stream()))
+
+    def nve(self, ctx, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5, nsteps=10,
+            thermo_every=1, threshold=0.1):
+        """Velocity Verlet with surrogate forces in place on device tensors x, v.
+
+        Returns (thermo rows, steps evaluated by AIREBO)."""
+        import torch
+        assert x.is_cuda and v.is_cuda and x.dtype == torch.float64 and v.dtype == torch.float64
+        s = torch.as_tensor(species, dtype=torch.int32, device=self.device).contiguous()
+        rows = nsteps // thermo_every + 1 if thermo_every > 0 else 1
+        th = torch.zeros((rows, 6), dtype=torch.float64, device=self.device)
+        m = (ctypes.c_double * 2)(*masses)
+        nfb = ctypes.c_int64()
+        _check(self.L, self.L.airebo_nn_nve(self.h, ctx.h, x.shape[0], _p(x), _p(v), _p(s),
+                                             _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32), m, dt,
+                                             nsteps, thermo_every, _p(th), float(threshold), ctypes.byref(nfb),
+                                             self._stream()))
+        return th, nfb.value
+
+    def profile_nve(self, ctx, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5, nsteps=10,
+                    threshold=0.1):
+        """Per-kernel device time over nsteps eager surrogate NVE steps: {name: (total ms, launches)}."""
+        import torch
+        s = torch.as_tensor(species, dtype=torch.int32, device=self.device).contiguous()
+        nk = self.L.airebo_kernel_count()
+        ms = (ctypes.c_double * nk)()
+        cnt = (ctypes.c_int64 * nk)()
+        m = (ctypes.c_double * 2)(*masses)
+        _check(self.L, self.L.airebo_nn_profile_nve(self.h, ctx.h, x.shape[0], _p(x), _p(v), _p(s),
+                                                     _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32),
+                                                     m, dt, nsteps, float(threshold), ms, cnt, self._stream()))
+        return {self.L.airebo_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(nk)}
+
+
+def mfma_check(A, B):
+    """D = A B for 16x16 FP32 device matrices through the library's matrix-core tile."""
+    import torch
+    L = load_library()
+    D = torch.empty((16, 16), dtype=torch.float32, device=A.device)
+    A = A.contiguous()
+    B = B.contiguous()
+    _check(L, L.airebo_nn_mfma_check(_p(A), _p(B), _p(D),
+                                      ctypes.c_void_p(torch.cuda.current_stream(A.device).cuda_stream)))
+    return D

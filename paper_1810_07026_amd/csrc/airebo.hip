@@ -56,7 +56,7 @@ constexpr int WAVE = 64;
 
 // flag bits
 enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16, F_OV_BOND = 32, F_OV_QUEUE = 64,
-       F_NONFINITE = 128, F_BADSPEC = 256 };
+       F_NONFINITE = 128, F_BADSPEC = 256, F_OV_NN = 512 };
 // accumulator quantities; each lives in NSLOT copies (one per group of blocks,
 // one cache line apart) that k_finish / k_thermo add up
 enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_SPL = 13,
@@ -68,13 +68,15 @@ constexpr int NSLOT = 64;
 constexpr int NSEG = 64, QSTRIDE = 32;
 // kernel ids for per-kernel timing
 enum { K_LOAD, K_BIN, K_SCAN, K_FILL, K_BUILD, K_BUILD_DONE, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
-       K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_COUNT };
-__host__ const char* const kKernelNames[K_COUNT] = {
+       K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_FAR,
+       K_NN_ENS, K_NN_DECIDE, K_COUNT };
+const char* const kKernelNames[K_COUNT] = {
     "k_load", "k_bin", "k_scan", "k_fill", "k_build", "k_build_done", "k_zero", "k_short", "k_bond",
-    "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo"};
+    "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo", "nn_zero", "nn_order", "nn_desc",
+    "nn_mlp", "nn_desc_force", "nn_far", "nn_ens", "nn_decide"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
-       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_N = 16 };
+       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_N = 16 };
 
 // One system of a batch: its own periodic box and cell grid.  A single
 // configuration is a batch of one.
@@ -123,6 +125,7 @@ struct Dev {
   unsigned long long* stats;
   int* flags;
   int* step;
+  const int* skip;   // when set and nonzero, the force kernels return at once (surrogate step kept)
 };
 
 // ---------------------------------------------------------------------------
@@ -817,6 +820,7 @@ __global__ void k_build_done(Dev D) {
 // Kernels: per-step force evaluation
 // ---------------------------------------------------------------------------
 __global__ void k_zero(Dev D) {
+  if (D.skip && *D.skip) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k = t; k < 3 * D.n; k += gridDim.x * blockDim.x) D.F[k] = 0;
   if (t < NSLOT * A_N) D.acc[t] = 0;
@@ -834,6 +838,7 @@ __device__ __forceinline__ void minimg(const SysBox& B, double& dx, double& dy, 
 
 // Exact short list, weights and coordination; species-bucketed bond list.
 __global__ __launch_bounds__(256) void k_short(Dev D, const DevParams* __restrict__ Pp) {
+  if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool live = i < D.n;
@@ -938,6 +943,7 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
 // REBO pair + bond order + torsion, one lane per bond (Alg. 1 and 2 merged).
 template <typename R>
 __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
+  if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   int n0 = D.bcount[0], n1 = D.bcount[1], n2 = D.bcount[2];
   n0 = min(n0, D.bcap); n1 = min(n1, D.bcap); n2 = min(n2, D.bcap);
@@ -1030,6 +1036,7 @@ __device__ __forceinline__ void lj_pair(const DevParams& P, int p, R r, R& V, R&
 // virial and the full force on its own atom.
 template <typename R>
 __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restrict__ Pp) {
+  if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   __shared__ int c_atom[LJ_BLOCK / WAVE][PCAP];
   __shared__ int c_code[LJ_BLOCK / WAVE][PCAP];
@@ -1177,6 +1184,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
 // the path atoms of C_ij and, where 0 < t_b < 1, the b* neighbourhood.
 template <typename R>
 __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
+  if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   __shared__ int seg_start[NSEG + 1];
   if (threadIdx.x == 0) {
@@ -1939,3 +1947,5 @@ int airebo_stats(airebo_ctx_t c, int64_t* out) {
 }
 
 }  // extern "C"
+
+#include "surrogate.hip"

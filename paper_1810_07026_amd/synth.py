@@ -892,3 +892,26 @@ def batch_cached(nsys=512, seed=SEED0 + 3):
         d["meta"] = {k: v for k, v in d["meta"].items() if k != "families"}
         return d
     return cached(f"batch_{nsys}_s{seed}", make)
+
+
+# ---- seeded initial weights of the surrogate networks (training inputs) ----
+# One network: W1 [64][112], b1 [64], W2 [64][64], b2, W3 [64][64], b3, w4 [64], b4 [1].
+NN_LAYOUT = (("W1", (64, 112)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64, 64)), ("b3", (64,)),
+             ("w4", (64,)), ("b4", (1,)))
+NN_NPAR = sum(int(np.prod(s)) for _, s in NN_LAYOUT)
+
+
+def nn_init_weights(nmodels, seed):
+    """LeCun-normal weight matrices (std 1/sqrt(fan in)) and zero biases for
+    each ensemble member and centre species: float32 [nmodels][2][15617]."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((nmodels, 2, NN_NPAR), np.float32)
+    for m in range(nmodels):
+        for sp in range(2):
+            off = 0
+            for name, shape in NN_LAYOUT:
+                k = int(np.prod(shape))
+                if name[0] in "Ww":
+                    out[m, sp, off:off + k] = rng.normal(0.0, 1.0 / math.sqrt(shape[-1]), k)
+                off += k
+    return out
