@@ -59,7 +59,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["pe_melt_32k", "hybrid_1m", "batch512"], default="pe_melt_32k")
+    ap.add_argument("--workload", choices=["pe_melt_32k", "hybrid_1m", "batch512", "surrogate_1m"],
+                    default="pe_melt_32k")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision and surrogate timings beside the FP64 line")
+    ap.add_argument("--form-steps", type=int, default=200)
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -84,6 +88,8 @@ def main():
 
     if args.workload == "batch512":
         return bench_batch(args)
+    if args.workload == "surrogate_1m":
+        return bench_surrogate(args)
     log("bench: generating workload")
     d = synth.pe_melt() if args.workload == "pe_melt_32k" else synth.hybrid_1m()
     n = len(d["species"])
@@ -173,6 +179,10 @@ def main():
             ferr = {"force_rms_err_eVA": float(math.sqrt(((fgs - fo) ** 2).sum(1).mean())),
                     "force_rel_err_max": float(np.abs(fgs - fo).max() / rms), "sampled_atoms": len(sel)}
 
+    forms = None
+    if not args.no_forms and args.workload == "pe_melt_32k":
+        forms = measure_forms(d, x0, args, value, fo if ferr is not None and n <= 100000 else None)
+
     out = {
         "metric": "AIREBO atom-steps/s on 1 GPU",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -192,7 +202,148 @@ def main():
         "energy_drift": {"slope_eV_per_atom_per_ps": slope, "max_rel": maxrel, "rebuilds": rebuilds},
         "work": {k: st[k] for k in ("lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds")},
         "kernels_us": {k: round(v["avg_us"], 3) for k, v in kern.items()},
+        "forms": forms,
     }
+    print(json.dumps(out))
+
+
+def force_err(f, fo):
+    f = np.asarray(f, float)
+    rms = math.sqrt((fo ** 2).sum(1).mean())
+    e = math.sqrt(((f - fo) ** 2).sum(1).mean())
+    return {"force_rms_err_eVA": e, "force_rel_rms_err": e / rms}
+
+
+def timed_nve(run, n, steps, warmup):
+    """atom-steps/s of run(nsteps) after a warm-up call (device-synchronised)."""
+    import torch
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    extra = run(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return n * steps / sec, 1e3 * sec / steps, extra
+
+
+def measure_forms(d, x0, args, fp64_value, fo):
+    """Mixed precision and surrogate on the same system and start state as
+    the FP64 line: atom-steps/s of NVE and force RMS error against the CPU
+    oracle (when it was evaluated) or the FP64 GPU forces."""
+    import torch
+    from paper_1810_07026_amd import airebo, surrogate
+    s, box, per = d["species"], d["box"], d["periodic"]
+    n = len(s)
+    v0 = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+    ctx = airebo.Context()
+    ref_kind = "cpu_oracle"
+    if fo is None:
+        fo = ctx.compute(x0, s, box, per)[1].cpu().numpy()
+        ref_kind = "fp64_gpu"
+    forms = {"reference": ref_kind, "steps": args.form_steps}
+    # mixed precision
+    ctxm = airebo.Context(precision=airebo.MIXED)
+    xm, vm = x0.clone(), v0.clone()
+    val, ms, _ = timed_nve(lambda k: ctxm.nve(xm, vm, s, box, per, nsteps=k, thermo_every=0), n, args.form_steps,
+                           args.warmup)
+    fm = ctxm.compute(x0, s, box, per)[1].cpu().numpy()
+    forms["mixed"] = dict(force_err(fm, fo), value=val, ms_per_step=ms, speedup_vs_fp64=val / fp64_value)
+    log(f"bench: mixed {val:.4g} atom-steps/s, force rel rms err {forms['mixed']['force_rel_rms_err']:.3g}")
+    # learned surrogate
+    if not os.path.exists(surrogate.WEIGHTS):
+        forms["surrogate"] = {"error": "no trained weights (python -m paper_1810_07026_amd.surrogate train)"}
+        return forms
+    nn = airebo.Surrogate(path=surrogate.WEIGHTS)
+    e, f, _, sp, info = nn.compute(ctx, x0, s, box, per, threshold=1e30, want_spread=True)
+    sur = dict(force_err(f.cpu().numpy(), fo), threshold_eVA=surrogate.THRESHOLD,
+               max_spread_eVA=info["max_spread"], atoms_above_threshold=int((sp > surrogate.THRESHOLD).sum()))
+    for key, thr in (("with_fallback", surrogate.THRESHOLD), ("no_fallback", 1e30)):
+        xs, vs = x0.clone(), v0.clone()
+        val, ms, fb = timed_nve(lambda k: nn.nve(ctx, xs, vs, s, box, per, nsteps=k, thermo_every=0,
+                                                 threshold=thr)[1], n, args.form_steps, args.warmup)
+        sur[key] = {"value": val, "ms_per_step": ms, "speedup_vs_fp64": val / fp64_value,
+                    "fallback_steps": fb, "fallback_rate": fb / args.form_steps}
+        log(f"bench: surrogate ({key}) {val:.4g} atom-steps/s, fallbacks {fb}/{args.form_steps}")
+    forms["surrogate"] = sur
+    return forms
+
+
+def bench_surrogate(args):
+    """Learned surrogate on a ~1e6-atom polyethylene melt (the 32,012-atom melt
+    tiled 3 x 3 x 3 = 864,324 atoms, fresh 300 K velocities, decorrelated by
+    untimed mixed-precision NVE), against AIREBO FP64 and mixed on the same
+    state; force errors against the FP64 GPU forces on every atom and
+    against the CPU oracle on sampled atoms."""
+    import torch
+    from paper_1810_07026_amd import airebo, surrogate, synth
+    d = synth.tile(synth.pe_melt(), (3, 3, 3))
+    s, box, per = d["species"], d["box"], d["periodic"]
+    n = len(s)
+    rng = np.random.default_rng(1810070266)
+    x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(synth.maxwell_velocities(s, 300.0, rng), dtype=torch.float64, device="cuda")
+    ctx = airebo.Context()
+    ctxm = airebo.Context(precision=airebo.MIXED)
+    log(f"bench: surrogate workload n={n}; decorrelating replicas ({args.warmup} mixed NVE steps, untimed)")
+    ctxm.nve(x, v, s, box, per, nsteps=max(args.warmup, 100), thermo_every=0)
+    torch.cuda.synchronize()
+    x0, v0 = x.clone(), v.clone()
+    e64, f64, _ = ctx.compute(x0, s, box, per)
+    f64 = f64.cpu().numpy()
+    nn = airebo.Surrogate(path=surrogate.WEIGHTS)
+    err = surrogate.force_error(nn, ctx, x0, s, box, per, f64)
+    fm = ctxm.compute(x0, s, box, per)[1].cpu().numpy()
+    steps = args.steps
+    res = {}
+    for key, run in (
+            ("fp64", lambda k: ctx.nve(x, v, s, box, per, nsteps=k, thermo_every=0)),
+            ("mixed", lambda k: ctxm.nve(x, v, s, box, per, nsteps=k, thermo_every=0)),
+            ("surrogate_with_fallback", lambda k: nn.nve(ctx, x, v, s, box, per, nsteps=k, thermo_every=0,
+                                                         threshold=surrogate.THRESHOLD)[1]),
+            ("surrogate_no_fallback", lambda k: nn.nve(ctx, x, v, s, box, per, nsteps=k, thermo_every=0,
+                                                       threshold=1e30)[1])):
+        x.copy_(x0)
+        v.copy_(v0)
+        val, ms, extra = timed_nve(run, n, steps, 5)
+        res[key] = {"value": val, "ms_per_step": ms}
+        if key.startswith("surrogate"):
+            res[key]["fallback_steps"] = extra
+        log(f"bench: {key} {val:.4g} atom-steps/s ({ms:.3f} ms/step)")
+    for k in res:
+        res[k]["speedup_vs_fp64"] = res[k]["value"] / res["fp64"]["value"]
+    # per-kernel device time of the surrogate step
+    x.copy_(x0)
+    v.copy_(v0)
+    prof = nn.profile_nve(ctx, x, v, s, box, per, nsteps=5, threshold=1e30)
+    kern = {k: round(1e3 * ms / c, 2) for k, (ms, c) in prof.items() if c and k.startswith("nn")}
+    # CPU oracle on sampled atoms
+    cpu = None
+    acc_or = None
+    if not args.no_cpu_baseline:
+        from oracle.oracle import Oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        sel = np.sort(rng.choice(n, 2048, replace=False)).astype(np.int32)
+        xh = x0.cpu().numpy()
+        t2 = time.perf_counter()
+        _, fo, _ = Oracle(nthreads=threads).compute(xh, s, box, per, sel=sel)
+        t3 = time.perf_counter()
+        fo = fo[sel]
+        fn = nn.compute(ctx, x0, s, box, per, threshold=1e30)[1].cpu().numpy()[sel]
+        acc_or = {"surrogate": force_err(fn, fo), "fp64_gpu": force_err(f64[sel], fo),
+                  "mixed_gpu": force_err(fm[sel], fo), "sampled_atoms": len(sel)}
+        cpu = {"value": len(sel) / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"exact FP64 AIREBO forces on {len(sel)} random atoms of the {n}-atom melt, "
+                         f"{t3 - t2:.1f} s"}
+    out = {"metric": "AIREBO atom-steps/s on 1 GPU", "value": res["surrogate_with_fallback"]["value"],
+           "unit": "atom-steps/s", "n_gpus": 1, "steps": steps, "warmup": 5,
+           "ms_per_step": res["surrogate_with_fallback"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic (seeded generators)",
+           "config": {"workload": f"learned surrogate (4-member ensemble, fallback at {surrogate.THRESHOLD} eV/A) on "
+                                  f"a polyethylene melt of {n} atoms (106 x C100H202 tiled 3x3x3, "
+                                  f"{box[0]:.1f} A periodic cube, 300 K), NVE dt 0.5 fs", "n_atoms": n},
+           "forms": res, "surrogate_error_vs_fp64_gpu": err,
+           "mixed_error_vs_fp64_gpu": force_err(fm, f64), "accuracy_vs_oracle": acc_or,
+           "cpu_baseline": cpu, "kernels_us": kern}
     print(json.dumps(out))
 
 

@@ -183,12 +183,13 @@ const char* airebo_kernel_name(int k);
  *
  * E_far is the LJ pair term of the context's parameters (with its outer
  * cutoff switch) times a cubic switch that rises from 0 at 5 A to 1 at 6 A.
- * It has no C_ij and no bond-order switch, and is evaluated in FP64.
+ * It has no C_ij and no bond-order switch.  It is evaluated in FP32 on
+ * FP64 pair vectors, with FP64 sums.
  *
  * Every call takes the AIREBO context whose neighbour lists and integrator
  * it uses.  Both objects must live on the same device.  Box rules and
  * errors are those of the context.  AIREBO_E_CAPACITY is returned when an
- * atom has more than 256 neighbours within 6 A or more than 48 within
+ * atom has more than 192 neighbours within 6 A or more than 48 within
  * 3.5 A.  A surrogate object is not thread safe.
  * ------------------------------------------------------------------------ */
 typedef struct airebo_nn* airebo_nn_t;

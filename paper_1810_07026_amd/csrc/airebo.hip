@@ -68,12 +68,12 @@ constexpr int NSLOT = 64;
 constexpr int NSEG = 64, QSTRIDE = 32;
 // kernel ids for per-kernel timing
 enum { K_LOAD, K_BIN, K_SCAN, K_FILL, K_BUILD, K_BUILD_DONE, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
-       K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_FAR,
+       K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_PACK,
        K_NN_ENS, K_NN_DECIDE, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {
     "k_load", "k_bin", "k_scan", "k_fill", "k_build", "k_build_done", "k_zero", "k_short", "k_bond",
     "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo", "nn_zero", "nn_order", "nn_desc",
-    "nn_mlp", "nn_desc_force", "nn_far", "nn_ens", "nn_decide"};
+    "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
        S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_N = 16 };

@@ -36,7 +36,7 @@ constexpr int HID = 64;
 constexpr int NM_MAX = 4;
 constexpr float RAD_CUT = 6.0f, ANG_CUT = 3.5f;
 constexpr double FAR0 = 5.0, FAR1 = 6.0;
-constexpr int MAXNB = 256;      // neighbours within RAD_CUT kept per atom
+constexpr int MAXNB = 192;      // neighbours within RAD_CUT kept per atom
 constexpr int MAXANG = 48;      // neighbours within ANG_CUT
 // parameter block of one species network (floats)
 constexpr int OW1 = 0, OB1 = OW1 + HID * DIM, OW2 = OB1 + HID, OB2 = OW2 + HID * HID, OW3 = OB2 + HID,
@@ -93,34 +93,59 @@ __device__ __forceinline__ float reduce_scatter64(float (&v)[64]) {
   return v[0];
 }
 
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 struct NbList {              // neighbours of one atom, staged in LDS by its wavefront
   int n, na;
   float dx[MAXNB], dy[MAXNB], dz[MAXNB], r[MAXNB];
   int j[MAXNB];
   signed char s[MAXNB];
   signed char aidx[MAXNB];   // index among the angular neighbours, or -1
-  unsigned char ang[MAXANG]; // slot of each angular neighbour
+  // angular neighbours (r < ANG_CUT): unit vector, length, cutoff value,
+  // h_e = fc'(r)/r - 2 eta_e fc(r) and exp(-eta_e r^2) for eta_e = 0.005, 0.05
+  float ux[MAXANG], uy[MAXANG], uz[MAXANG], ar[MAXANG], afc[MAXANG], ah0[MAXANG], ah1[MAXANG], ae0[MAXANG],
+      ae1[MAXANG];
+  int aj[MAXANG];            // atom of each angular neighbour
+  signed char as[MAXANG];    // its species
+};
+
+// Far-field pair sums of one lane: energy (half per side), force on the
+// centre, virial (half per side).
+struct FarAcc {
+  float e, f[3], W[6];
 };
 
 // Stage the neighbours of atom i within RAD_CUT (image-resolved, from the LJ
-// list, in list order) in LDS.  One wavefront.
-__device__ void stage_nb(const Dev& D, int i, NbList& nb) {
+// list, in list order) in LDS, with the per-neighbour factors of the angular
+// terms.  One wavefront.  With a far-field accumulator, the same pass adds
+// the far-field pair term of every list entry beyond FAR0 (FP32 arithmetic on
+// the FP64 pair vector).
+__device__ void stage_nb(const Dev& D, int i, NbList& nb, const DevParams* P = nullptr, FarAcc* far = nullptr) {
   int lane = threadIdx.x & (WAVE - 1);
   unsigned long long below = lanes_below();
   double4 xi = D.x[i];
+  int si = __double2int_rn(xi.w) == 0 ? 0 : 1;
   const SysBox& B = box_of(D, i);
   int nl = min(D.lj_n[i], D.lj_cap);
   int cnt = 0, cna = 0;
+  // the next block of entries and positions is loaded while this one is used
+  const unsigned* list = D.lj_e + (size_t)i * D.lj_cap;
+  unsigned ent_n = lane < nl ? list[lane] : 0u;
+  double4 xj_n = lane < nl ? D.x[ent_n & 0x7FFFFFFu] : xi;
   for (int base = 0; base < nl; base += WAVE) {
     int e = base + lane;
     bool ok = false, oka = false;
     float dx = 0, dy = 0, dz = 0, r = 0;
     int j = 0, sj = 0;
+    unsigned ent = ent_n;
+    double4 xj = xj_n;
+    if (e + WAVE < nl) {
+      ent_n = list[e + WAVE];
+      xj_n = D.x[ent_n & 0x7FFFFFFu];
+    }
     if (e < nl) {
-      unsigned ent = D.lj_e[(size_t)i * D.lj_cap + e];
       j = (int)(ent & 0x7FFFFFFu);
       int code = (int)(ent >> 27);
-      double4 xj = D.x[j];
       double ddx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
       double ddy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
       double ddz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
@@ -129,6 +154,20 @@ __device__ void stage_nb(const Dev& D, int i, NbList& nb) {
       oka = r2 < (double)ANG_CUT * ANG_CUT;
       dx = (float)ddx; dy = (float)ddy; dz = (float)ddz; r = (float)sqrt(r2);
       sj = __double2int_rn(xj.w) == 0 ? 0 : 1;   // invalid codes are reported by k_load
+      if (far) {
+        int p = si + sj;
+        if (r2 > FAR0 * FAR0 && r2 < P->rc2[p]) {
+          float V, dV, ds;
+          lj_pair<float>(*P, p, r, V, dV);
+          float sw = 1.0f - Sw((r - (float)FAR0) * (float)(1.0 / (FAR1 - FAR0)), ds);
+          ds = -ds * (float)(1.0 / (FAR1 - FAR0));
+          float gr = (ds * V + sw * dV) * frcp(r);   // (dE_pair/dr) / r
+          far->e += 0.5f * sw * V;
+          far->f[0] += gr * dx; far->f[1] += gr * dy; far->f[2] += gr * dz;
+          far->W[0] -= 0.5f * gr * dx * dx; far->W[1] -= 0.5f * gr * dy * dy; far->W[2] -= 0.5f * gr * dz * dz;
+          far->W[3] -= 0.5f * gr * dx * dy; far->W[4] -= 0.5f * gr * dx * dz; far->W[5] -= 0.5f * gr * dy * dz;
+        }
+      }
     }
     unsigned long long m = __ballot(ok);
     unsigned long long ma = __ballot(oka);
@@ -139,7 +178,19 @@ __device__ void stage_nb(const Dev& D, int i, NbList& nb) {
       nb.s[pos] = (signed char)sj;
       bool a = oka && posa < MAXANG;
       nb.aidx[pos] = a ? (signed char)posa : (signed char)-1;
-      if (a) nb.ang[posa] = (unsigned char)pos;
+      if (a) {
+        float ir = frcp(r), dfc;
+        float fc = fcut(r, ANG_CUT, dfc);
+        nb.ux[posa] = dx * ir; nb.uy[posa] = dy * ir; nb.uz[posa] = dz * ir;
+        nb.ar[posa] = r;
+        nb.afc[posa] = fc;
+        nb.ah0[posa] = dfc * ir - 2.0f * 0.005f * fc;
+        nb.ah1[posa] = dfc * ir - 2.0f * 0.05f * fc;
+        nb.ae0[posa] = __expf(-0.005f * r * r);
+        nb.ae1[posa] = __expf(-0.05f * r * r);
+        nb.aj[posa] = j;
+        nb.as[posa] = (signed char)sj;
+      }
     }
     cnt += __popcll(m);
     cna += __popcll(ma);
@@ -164,21 +215,6 @@ __device__ __forceinline__ void tri_decode(int p, int na, int& a, int& b) {
   b = p - start(r) + r + 1;
 }
 
-// Geometry of one angular triplet j-i-k (u = x_j - x_i, v = x_k - x_i).
-struct Trip {
-  float ux, uy, uz, vx, vy, vz, rj, rk, cs, fj, fk, dfj, dfk, e[2];
-};
-__device__ __forceinline__ void trip_geom(const NbList& nb, int qa, int qb, Trip& T) {
-  T.ux = nb.dx[qa]; T.uy = nb.dy[qa]; T.uz = nb.dz[qa];
-  T.vx = nb.dx[qb]; T.vy = nb.dy[qb]; T.vz = nb.dz[qb];
-  T.rj = nb.r[qa]; T.rk = nb.r[qb];
-  T.cs = (T.ux * T.vx + T.uy * T.vy + T.uz * T.vz) / (T.rj * T.rk);
-  T.fj = fcut(T.rj, ANG_CUT, T.dfj);
-  T.fk = fcut(T.rk, ANG_CUT, T.dfk);
-  float s2 = T.rj * T.rj + T.rk * T.rk;
-  T.e[0] = __expf(-0.005f * s2);
-  T.e[1] = __expf(-0.05f * s2);
-}
 // (1 + lam c)^zeta and its derivative in c for zeta = 1, 2, 4, 8.
 __device__ __forceinline__ void ang_pows(float base, float lam, float (&P)[4], float (&dP)[4]) {
   float b2 = base * base, b4 = b2 * b2;
@@ -186,6 +222,31 @@ __device__ __forceinline__ void ang_pows(float base, float lam, float (&P)[4], f
   dP[0] = lam; dP[1] = 2.0f * lam * base; dP[2] = 4.0f * lam * b2 * base; dP[3] = 8.0f * lam * b4 * b2 * base;
 }
 __device__ __forceinline__ float ang_pre(int zi) { return zi == 0 ? 1.0f : (zi == 1 ? 0.5f : (zi == 2 ? 0.125f : 0.0078125f)); }
+
+// Angular factors of the neighbour pair (a, b): cos theta, the products
+// pe_c = 2^(1-zeta) exp(-eta_e (r_a^2 + r_b^2)) times (1 + lam cos)^zeta (w2)
+// and times its cos-derivative (w1), feature c = 4 zi + 2 li + ei.
+struct PairAng {
+  float cs, w1[NANG], w2[NANG];
+};
+__device__ __forceinline__ void pair_ang(const NbList& nb, int a, int b, PairAng& Q) {
+  Q.cs = nb.ux[a] * nb.ux[b] + nb.uy[a] * nb.uy[b] + nb.uz[a] * nb.uz[b];
+  float E[2] = {nb.ae0[a] * nb.ae0[b], nb.ae1[a] * nb.ae1[b]};
+  float P[2][4], dP[2][4];
+  ang_pows(1.0f + Q.cs, 1.0f, P[0], dP[0]);
+  ang_pows(1.0f - Q.cs, -1.0f, P[1], dP[1]);
+#pragma unroll
+  for (int zi = 0; zi < 4; ++zi)
+#pragma unroll
+    for (int li = 0; li < 2; ++li)
+#pragma unroll
+      for (int ei = 0; ei < 2; ++ei) {
+        int c = 4 * zi + 2 * li + ei;
+        float pe = ang_pre(zi) * E[ei];
+        Q.w1[c] = pe * dP[li][zi];
+        Q.w2[c] = pe * P[li][zi];
+      }
+}
 
 // Descriptors (MODE 0) or their Jacobian-vector product with w [n][3]
 // (MODE 1): out[i][f] = sum_a dG_if/dx_a . w_a.  One wavefront per atom.
@@ -206,19 +267,20 @@ __global__ __launch_bounds__(256) void k_desc(Dev D, float* __restrict__ out, co
   for (int q = lane; q < nb.n; q += WAVE) {
     float r = nb.r[q], dfc;
     float fcv = fcut(r, RAD_CUT, dfc);
-    bool c0 = nb.s[q] == 0;
+    float w0 = nb.s[q] == 0 ? 1.0f : 0.0f, w1 = 1.0f - w0;
     float proj = 0.0f;
     if (MODE == 1) {
       int j = nb.j[q];
-      proj = (nb.dx[q] * (w[3 * j] - wi0) + nb.dy[q] * (w[3 * j + 1] - wi1) + nb.dz[q] * (w[3 * j + 2] - wi2)) / r;
+      proj = (nb.dx[q] * (w[3 * j] - wi0) + nb.dy[q] * (w[3 * j + 1] - wi1) + nb.dz[q] * (w[3 * j + 2] - wi2)) *
+             frcp(r);
     }
 #pragma unroll
     for (int m = 0; m < NRAD; ++m) {
       float t = r - (0.8f + m * RAD_H);
       float g = __expf(-RAD_ETA * t * t);
       float val = MODE == 0 ? g * fcv : g * (fcv * (-2.0f * RAD_ETA * t) + dfc) * proj;
-      v[m] += c0 ? val : 0.0f;
-      v[NRAD + m] += c0 ? 0.0f : val;
+      v[m] += w0 * val;
+      v[NRAD + m] += w1 * val;
     }
   }
   float tot = reduce_scatter64(v);
@@ -230,171 +292,229 @@ __global__ __launch_bounds__(256) void k_desc(Dev D, float* __restrict__ out, co
   for (int p = lane; p < npair; p += WAVE) {
     int a, b;
     tri_decode(p, na, a, b);
-    int qa = nb.ang[a], qb = nb.ang[b];
-    int t = nb.s[qa] + nb.s[qb];
-    Trip T;
-    trip_geom(nb, qa, qb, T);
-    float Acos = 0, Bu = 0, Bv = 0;   // JVP pieces: dcos, u . a_j, v . a_k
+    int t = nb.as[a] + nb.as[b];
+    float t0 = t == 0 ? 1.0f : 0.0f, t1 = t == 1 ? 1.0f : 0.0f, t2 = t == 2 ? 1.0f : 0.0f;
+    PairAng Q;
+    pair_ang(nb, a, b, Q);
+    float ff = nb.afc[a] * nb.afc[b];
+    float A = 0, Ba = 0, Bb = 0;   // JVP pieces
     if (MODE == 1) {
-      int j = nb.j[qa], k = nb.j[qb];
-      float ajx = w[3 * j] - wi0, ajy = w[3 * j + 1] - wi1, ajz = w[3 * j + 2] - wi2;
-      float akx = w[3 * k] - wi0, aky = w[3 * k + 1] - wi1, akz = w[3 * k + 2] - wi2;
-      float irr = 1.0f / (T.rj * T.rk), irj2 = 1.0f / (T.rj * T.rj), irk2 = 1.0f / (T.rk * T.rk);
-      Bu = T.ux * ajx + T.uy * ajy + T.uz * ajz;
-      Bv = T.vx * akx + T.vy * aky + T.vz * akz;
-      Acos = (T.vx * ajx + T.vy * ajy + T.vz * ajz + T.ux * akx + T.uy * aky + T.uz * akz) * irr -
-             T.cs * (Bu * irj2 + Bv * irk2);
+      int ja = nb.aj[a], jb = nb.aj[b];
+      float ajx = w[3 * ja] - wi0, ajy = w[3 * ja + 1] - wi1, ajz = w[3 * ja + 2] - wi2;
+      float akx = w[3 * jb] - wi0, aky = w[3 * jb + 1] - wi1, akz = w[3 * jb + 2] - wi2;
+      float ua_j = nb.ux[a] * ajx + nb.uy[a] * ajy + nb.uz[a] * ajz;   // u_a . a_j / r_a
+      float ub_j = nb.ux[b] * ajx + nb.uy[b] * ajy + nb.uz[b] * ajz;
+      float ua_k = nb.ux[a] * akx + nb.uy[a] * aky + nb.uz[a] * akz;
+      float ub_k = nb.ux[b] * akx + nb.uy[b] * aky + nb.uz[b] * akz;   // u_b . a_k / r_b
+      A = ff * ((ub_j - Q.cs * ua_j) * frcp(nb.ar[a]) + (ua_k - Q.cs * ub_k) * frcp(nb.ar[b]));
+      Ba = nb.afc[b] * nb.ar[a] * ua_j;
+      Bb = nb.afc[a] * nb.ar[b] * ub_k;
     }
 #pragma unroll
-    for (int li = 0; li < 2; ++li) {
-      float lam = li ? -1.0f : 1.0f;
-      float P[4], dP[4];
-      ang_pows(1.0f + lam * T.cs, lam, P, dP);
-#pragma unroll
-      for (int zi = 0; zi < 4; ++zi)
-#pragma unroll
-        for (int ei = 0; ei < 2; ++ei) {
-          int c = 4 * zi + 2 * li + ei;
-          float eta = ei ? 0.05f : 0.005f;
-          float pe = ang_pre(zi) * T.e[ei];
-          float val;
-          if (MODE == 0) {
-            val = pe * P[zi] * T.fj * T.fk;
-          } else {
-            val = pe * (dP[zi] * T.fj * T.fk * Acos +
-                        P[zi] * (T.fk * (T.dfj / T.rj - 2.0f * eta * T.fj) * Bu +
-                                 T.fj * (T.dfk / T.rk - 2.0f * eta * T.fk) * Bv));
-          }
-          v[c] += t == 0 ? val : 0.0f;
-          v[16 + c] += t == 1 ? val : 0.0f;
-          v[32 + c] += t == 2 ? val : 0.0f;
-        }
+    for (int c = 0; c < NANG; ++c) {
+      float val;
+      if (MODE == 0) {
+        val = Q.w2[c] * ff;
+      } else {
+        int ei = c & 1;
+        float ha = ei ? nb.ah1[a] : nb.ah0[a], hb = ei ? nb.ah1[b] : nb.ah0[b];
+        val = Q.w1[c] * A + Q.w2[c] * (ha * Ba + hb * Bb);
+      }
+      v[c] += t0 * val;
+      v[16 + c] += t1 * val;
+      v[32 + c] += t2 * val;
     }
   }
   tot = reduce_scatter64(v);
   if (lane < 3 * NANG) out[(size_t)i * DIM + 2 * NRAD + lane] = tot;
 }
 
-// Descriptor vector-Jacobian product: F[m][a] -= sum_{i,f} g[m][i][f] dG_if/dx_a
-// for nm sets g ([nm][n][DIM]); F ([nm][n][3], FP32) must start at zero.  The
-// virial of the mean over the sets, the sum over contributions of
-// (x_a - x_i) (x) F_a, is added to acc[slot][N_VIR..].  One wavefront per
-// centre atom i: contributions to a neighbour are summed in LDS first, then
-// added to it with one atomic per component and set.
-__global__ __launch_bounds__(256) void k_desc_force(Dev D, const float* __restrict__ g, int nm,
-                                                    float* __restrict__ F, double* __restrict__ acc) {
-  __shared__ NbList nbs[4];
-  __shared__ float gs[4][NM_MAX][DIM];
-  __shared__ float fq[4][NM_MAX][MAXANG][3];
-  int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+// Descriptor vector-Jacobian product: F[m][a] = -sum_{i,f} g[m][i][f] dG_if/dx_a
+// for nm sets g ([nm][n][DIM], complete before the launch); F ([nm][n][3],
+// FP32) must start at zero.  The
+// virial of the mean over the sets (sum over contributions of
+// (x_a - x_i) (x) F_a) goes to acc[slot][N_VIR..].  One wavefront per centre
+// atom i.
+//   angular: lane per neighbour pair (a, b) forms dE/du_a and dE/du_b and
+//     writes them to LDS slots; then lane per leg a sums the slots of its
+//     pairs (no atomics);
+//     and adds each leg's force to its atom (one atomic per component and
+//     set);
+//   radial: gathered from both ends of each pair (the neighbour's dE/dG
+//     slice is read from memory), no atomics.
+// The centre's own force is a wavefront sum.
+// With FAR, the same pass over the LJ list evaluates the far-field term into
+// Ff [n][3] and acc.
+// One wavefront per block: the centre atom is wave-uniform, so its dE/dG rows
+// are read with scalar loads (no LDS staging).
+template <bool FAR>
+__global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __restrict__ Pp, const float* __restrict__ g,
+                                                     int nm, float* __restrict__ F, double* __restrict__ Ff,
+                                                     double* __restrict__ acc) {
+  __shared__ NbList nb;
+  __shared__ float pdu[NM_MAX][3][WAVE];   // dE/du_a of each pair of the current block of pairs
+  __shared__ float pdv[NM_MAX][3][WAVE];   // dE/du_b
+  int lane = threadIdx.x;
+  const int i = blockIdx.x;
+  if (i >= D.n) return;
   float W[6] = {0, 0, 0, 0, 0, 0};
-  if (i < D.n) {
-    NbList& nb = nbs[wv];
-    stage_nb(D, i, nb);
-    for (int m = 0; m < nm; ++m)
-      for (int f = lane; f < DIM; f += WAVE) gs[wv][m][f] = g[((size_t)m * D.n + i) * DIM + f];
-    for (int k = lane; k < NM_MAX * MAXANG * 3; k += WAVE) (&fq[wv][0][0][0])[k] = 0.0f;
-    wave_sync();
-    const float inm = 1.0f / nm;
-    float fi[NM_MAX][3] = {};
-    // angular: lane per neighbour pair; forces on the legs summed in LDS
-    int na = nb.na, npair = na * (na - 1) / 2;
-    for (int p = lane; p < npair; p += WAVE) {
+  FarAcc far = {0, {0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+  stage_nb(D, i, nb, Pp, FAR ? &far : nullptr);
+  const float inm = 1.0f / nm;
+  const size_t mstride = (size_t)D.n * DIM;
+  const float* gi = g + (size_t)i * DIM;   // row of model m: gi + m * mstride
+  float fi[NM_MAX][3] = {};
+  float lf[NM_MAX][3] = {};   // force on leg `lane` (lane < na)
+  int na = nb.na, npair = na * (na - 1) / 2;
+  auto start = [&](int q) { return q * na - q * (q + 1) / 2; };
+  // ---- angular: lane per pair, then lane per leg
+  for (int base = 0; base < npair; base += WAVE) {
+    int p = base + lane;
+    if (p < npair) {
       int a, b;
       tri_decode(p, na, a, b);
-      int qa = nb.ang[a], qb = nb.ang[b];
-      int t = nb.s[qa] + nb.s[qb];
-      Trip T;
-      trip_geom(nb, qa, qb, T);
-      float Ac[NM_MAX] = {}, Bu[NM_MAX] = {}, Bv[NM_MAX] = {};
-#pragma unroll
-      for (int li = 0; li < 2; ++li) {
-        float lam = li ? -1.0f : 1.0f;
-        float P[4], dP[4];
-        ang_pows(1.0f + lam * T.cs, lam, P, dP);
-#pragma unroll
-        for (int zi = 0; zi < 4; ++zi)
-#pragma unroll
-          for (int ei = 0; ei < 2; ++ei) {
-            int c = 4 * zi + 2 * li + ei;
-            float eta = ei ? 0.05f : 0.005f;
-            float pe = ang_pre(zi) * T.e[ei];
-            float a0 = pe * dP[zi] * T.fj * T.fk;
-            float b0 = pe * P[zi] * T.fk * (T.dfj / T.rj - 2.0f * eta * T.fj);
-            float c0 = pe * P[zi] * T.fj * (T.dfk / T.rk - 2.0f * eta * T.fk);
-#pragma unroll
-            for (int m = 0; m < NM_MAX; ++m)
-              if (m < nm) {
-                float gv = gs[wv][m][2 * NRAD + t * NANG + c];
-                Ac[m] += gv * a0; Bu[m] += gv * b0; Bv[m] += gv * c0;
-              }
-          }
-      }
-      float irr = 1.0f / (T.rj * T.rk), irj2 = 1.0f / (T.rj * T.rj), irk2 = 1.0f / (T.rk * T.rk);
+      int t = nb.as[a] + nb.as[b];
+      PairAng Q;
+      pair_ang(nb, a, b, Q);
+      float fa = nb.afc[a], fb = nb.afc[b], ra = nb.ar[a], rb = nb.ar[b];
+      float ira = frcp(ra), irb = frcp(rb);
+      float uax = nb.ux[a], uay = nb.uy[a], uaz = nb.uz[a], ubx = nb.ux[b], uby = nb.uy[b], ubz = nb.uz[b];
+      float ha0 = nb.ah0[a], ha1 = nb.ah1[a], hb0 = nb.ah0[b], hb1 = nb.ah1[b];
 #pragma unroll
       for (int m = 0; m < NM_MAX; ++m)
         if (m < nm) {
-          // dE/du and dE/dv
-          float gux = Ac[m] * (T.vx * irr - T.cs * T.ux * irj2) + Bu[m] * T.ux;
-          float guy = Ac[m] * (T.vy * irr - T.cs * T.uy * irj2) + Bu[m] * T.uy;
-          float guz = Ac[m] * (T.vz * irr - T.cs * T.uz * irj2) + Bu[m] * T.uz;
-          float gvx = Ac[m] * (T.ux * irr - T.cs * T.vx * irk2) + Bv[m] * T.vx;
-          float gvy = Ac[m] * (T.uy * irr - T.cs * T.vy * irk2) + Bv[m] * T.vy;
-          float gvz = Ac[m] * (T.uz * irr - T.cs * T.vz * irk2) + Bv[m] * T.vz;
+          const float* ga = gi + m * mstride + 2 * NRAD;
+          float S1 = 0, S20 = 0, S21 = 0;
+#pragma unroll
+          for (int c = 0; c < NANG; ++c) {
+            float gc = t == 0 ? ga[c] : (t == 1 ? ga[NANG + c] : ga[2 * NANG + c]);
+            S1 += gc * Q.w1[c];
+            if (c & 1) S21 += gc * Q.w2[c]; else S20 += gc * Q.w2[c];
+          }
+          float Ac = fa * fb * S1;
+          float Ba = fb * (ha0 * S20 + ha1 * S21) * ra;
+          float Bb = fa * (hb0 * S20 + hb1 * S21) * rb;
+          // dE/du_a and dE/du_b (u = vector from the centre to the neighbour)
+          float ca = Ac * ira, cb = Ac * irb;
+          float gux = ca * (ubx - Q.cs * uax) + Ba * uax;
+          float guy = ca * (uby - Q.cs * uay) + Ba * uay;
+          float guz = ca * (ubz - Q.cs * uaz) + Ba * uaz;
+          float gvx = cb * (uax - Q.cs * ubx) + Bb * ubx;
+          float gvy = cb * (uay - Q.cs * uby) + Bb * uby;
+          float gvz = cb * (uaz - Q.cs * ubz) + Bb * ubz;
           fi[m][0] += gux + gvx; fi[m][1] += guy + gvy; fi[m][2] += guz + gvz;
-          atomicAdd(&fq[wv][m][a][0], -gux); atomicAdd(&fq[wv][m][a][1], -guy); atomicAdd(&fq[wv][m][a][2], -guz);
-          atomicAdd(&fq[wv][m][b][0], -gvx); atomicAdd(&fq[wv][m][b][1], -gvy); atomicAdd(&fq[wv][m][b][2], -gvz);
-          W[0] -= inm * (T.ux * gux + T.vx * gvx);
-          W[1] -= inm * (T.uy * guy + T.vy * gvy);
-          W[2] -= inm * (T.uz * guz + T.vz * gvz);
-          W[3] -= inm * (T.ux * guy + T.vx * gvy);
-          W[4] -= inm * (T.ux * guz + T.vx * gvz);
-          W[5] -= inm * (T.uy * guz + T.vy * gvz);
+          pdu[m][0][lane] = -gux; pdu[m][1][lane] = -guy; pdu[m][2][lane] = -guz;
+          pdv[m][0][lane] = -gvx; pdv[m][1][lane] = -gvy; pdv[m][2][lane] = -gvz;
+          W[0] -= inm * (ra * uax * gux + rb * ubx * gvx);
+          W[1] -= inm * (ra * uay * guy + rb * uby * gvy);
+          W[2] -= inm * (ra * uaz * guz + rb * ubz * gvz);
+          W[3] -= inm * (ra * uax * guy + rb * ubx * gvy);
+          W[4] -= inm * (ra * uax * guz + rb * ubx * gvz);
+          W[5] -= inm * (ra * uay * guz + rb * uby * gvz);
         }
     }
     wave_sync();
-    // radial: lane per neighbour; add the angular sums and scatter once
-    for (int q = lane; q < nb.n; q += WAVE) {
-      float r = nb.r[q], dfc;
-      float fcv = fcut(r, RAD_CUT, dfc);
-      int sp = nb.s[q], j = nb.j[q], ai = nb.aidx[q];
-      float de[NM_MAX] = {};
-#pragma unroll
-      for (int mm = 0; mm < NRAD; ++mm) {
-        float t = r - (0.8f + mm * RAD_H);
-        float gg = __expf(-RAD_ETA * t * t);
-        float dg = gg * (fcv * (-2.0f * RAD_ETA * t) + dfc);
+    if (lane < na) {
+      // pairs (lane, b): contiguous slots of row `lane`
+      int a = lane;
+      int s0 = start(a);
+      int lo = max(s0, base), hi = min(s0 + na - 1 - a, min(base + WAVE, npair));
+      for (int q = lo; q < hi; ++q)
 #pragma unroll
         for (int m = 0; m < NM_MAX; ++m)
-          if (m < nm) de[m] += gs[wv][m][sp * NRAD + mm] * dg;
-      }
-      float ux = nb.dx[q] / r, uy = nb.dy[q] / r, uz = nb.dz[q] / r;
+          if (m < nm) {
+            lf[m][0] += pdu[m][0][q - base]; lf[m][1] += pdu[m][1][q - base]; lf[m][2] += pdu[m][2][q - base];
+          }
+      // pairs (r, lane), r < lane: one slot in each row r
+      int ra_, rb_, re_, rf_;
+      tri_decode(base, na, ra_, rb_);
+      tri_decode(min(base + WAVE, npair) - 1, na, re_, rf_);
+      for (int r = ra_; r <= re_ && r < a; ++r) {
+        int q = start(r) + a - r - 1;
+        if (q >= base && q < base + WAVE && q < npair)
 #pragma unroll
-      for (int m = 0; m < NM_MAX; ++m)
-        if (m < nm) {
-          float fx = -de[m] * ux, fy = -de[m] * uy, fz = -de[m] * uz;   // radial force on j
-          fi[m][0] -= fx; fi[m][1] -= fy; fi[m][2] -= fz;
-          W[0] += inm * nb.dx[q] * fx; W[1] += inm * nb.dy[q] * fy; W[2] += inm * nb.dz[q] * fz;
-          W[3] += inm * nb.dx[q] * fy; W[4] += inm * nb.dx[q] * fz; W[5] += inm * nb.dy[q] * fz;
-          if (ai >= 0) { fx += fq[wv][m][ai][0]; fy += fq[wv][m][ai][1]; fz += fq[wv][m][ai][2]; }
-          float* Fj = F + ((size_t)m * D.n + j) * 3;
-          atomicAdd(Fj, fx); atomicAdd(Fj + 1, fy); atomicAdd(Fj + 2, fz);
-        }
+          for (int m = 0; m < NM_MAX; ++m)
+            if (m < nm) {
+              lf[m][0] += pdv[m][0][q - base]; lf[m][1] += pdv[m][1][q - base]; lf[m][2] += pdv[m][2][q - base];
+            }
+      }
     }
+    wave_sync();
+  }
+  // angular legs: force on each leg atom, one atomic per component and set
+  if (lane < na) {
+    int ja = nb.aj[lane];
 #pragma unroll
     for (int m = 0; m < NM_MAX; ++m)
-      if (m < nm)
-        for (int c = 0; c < 3; ++c) {
-          float s = fi[m][c];
-          for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-          if (lane == 0) atomicAdd(&F[((size_t)m * D.n + i) * 3 + c], s);
+      if (m < nm) {
+        float* Fj = F + ((size_t)m * D.n + ja) * 3;
+        atomicAdd(Fj, lf[m][0]); atomicAdd(Fj + 1, lf[m][1]); atomicAdd(Fj + 2, lf[m][2]);
+      }
+  }
+  // ---- radial, gathered: lane per neighbour j.  Both E_i (through G_i[s_j])
+  // and E_j (through G_j[s_i]) depend on r_ij; every pair is visited from
+  // both ends, and each end applies the full pair force to its own atom and
+  // half of the pair virial.
+  const int si = __double2int_rn(D.x[i].w) == 0 ? 0 : 1;
+  for (int q = lane; q < nb.n; q += WAVE) {
+    float r = nb.r[q], dfc;
+    float fcv = fcut(r, RAD_CUT, dfc);
+    int sp = nb.s[q], j = nb.j[q];
+    float dg[NRAD];
+#pragma unroll
+    for (int k = 0; k < NRAD; ++k) {
+      float t = r - (0.8f + k * RAD_H);
+      dg[k] = __expf(-RAD_ETA * t * t) * (fcv * (-2.0f * RAD_ETA * t) + dfc);
+    }
+    float ir = frcp(r);
+    float ux = nb.dx[q] * ir, uy = nb.dy[q] * ir, uz = nb.dz[q] * ir;
+#pragma unroll
+    for (int m = 0; m < NM_MAX; ++m)
+      if (m < nm) {
+        const float* gm = gi + m * mstride;                                     // centre, scalar loads
+        const float* gj = g + m * mstride + (size_t)j * DIM + si * NRAD;       // neighbour, vector loads
+        float de = 0;
+#pragma unroll
+        for (int k4 = 0; k4 < NRAD / 4; ++k4) {
+          float4 v = *reinterpret_cast<const float4*>(gj + 4 * k4);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            int kk = 4 * k4 + k;
+            float own = sp ? gm[NRAD + kk] : gm[kk];
+            float oth = k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+            de += (own + oth) * dg[kk];
+          }
         }
+        // dE/dr_ij > 0 pulls i towards j: F_i = +dE/dr u
+        fi[m][0] += de * ux; fi[m][1] += de * uy; fi[m][2] += de * uz;
+        float h = -0.5f * inm * de;   // half pair virial: d (x) F_j with F_j = -dE/dr u
+        W[0] += h * nb.dx[q] * ux; W[1] += h * nb.dy[q] * uy; W[2] += h * nb.dz[q] * uz;
+        W[3] += h * nb.dx[q] * uy; W[4] += h * nb.dx[q] * uz; W[5] += h * nb.dy[q] * uz;
+      }
+  }
+#pragma unroll
+  for (int m = 0; m < NM_MAX; ++m)
+    if (m < nm)
+      for (int c = 0; c < 3; ++c) {
+        float s = fi[m][c];
+        for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) atomicAdd(&F[((size_t)m * D.n + i) * 3 + c], s);
+      }
+  int slot = (blockIdx.x & (NSLOT - 1)) * N_A;
+  if (FAR) {
+    for (int c = 0; c < 3; ++c) {
+      double s = far.f[c];
+      for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      if (lane == 0) Ff[3 * i + c] = s;
+    }
+    double s = far.e;
+    for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0 && s != 0) atomic_add(&acc[slot + N_EFAR], s);
   }
   for (int c = 0; c < 6; ++c) {
-    double s = W[c];
+    double s = (double)W[c] + (double)far.W[c];
     for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && s != 0) atomic_add(&acc[(blockIdx.x & (NSLOT - 1)) * N_A + N_VIR + c], s);
+    if (lane == 0 && s != 0) atomic_add(&acc[slot + N_VIR + c], s);
   }
 }
 
@@ -607,16 +727,27 @@ __device__ __forceinline__ void tile_fwd_bwd(const NNArgs& A, const NetLDS& N, T
   wave_sync();
 }
 
+// BF16 images of every (model, species) network in the LDS layout, built
+// once per weight update; inference blocks copy their image linearly.
+__global__ void k_pack(const float* __restrict__ params, NetLDS* __restrict__ out) {
+  load_net(out[blockIdx.x], params + (size_t)blockIdx.x * NPAR, threadIdx.x, blockDim.x);
+}
+
 // Inference: grid (blocks, 2 nm), blockIdx.y = 2 model + species; each block
-// stages that network once and its waves walk the species' tiles.
-constexpr int MLP_WAVES = 4;
-__global__ __launch_bounds__(64 * MLP_WAVES) void k_mlp(NNArgs A) {
+// copies that network's image into LDS once and its waves walk the species'
+// tiles.
+constexpr int MLP_WAVES = 8;
+__global__ __launch_bounds__(64 * MLP_WAVES) void k_mlp(NNArgs A, const NetLDS* __restrict__ packed) {
   __shared__ NetLDS N;
   __shared__ TileLDS Ts[MLP_WAVES];
   int model = blockIdx.y >> 1, sp = blockIdx.y & 1;
   int ntile = (A.cnt[sp] + 15) / 16;
   if ((int)blockIdx.x * MLP_WAVES >= ntile) return;   // whole block
-  load_net(N, A.params + ((size_t)model * 2 + sp) * NPAR, threadIdx.x, blockDim.x);
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(packed + blockIdx.y);
+    uint4* dst = reinterpret_cast<uint4*>(&N);
+    for (int k = threadIdx.x; k < (int)(sizeof(NetLDS) / 16); k += blockDim.x) dst[k] = src[k];
+  }
   __syncthreads();
   int wv = threadIdx.x / WAVE;
   for (int tile = blockIdx.x * MLP_WAVES + wv; tile < ntile; tile += gridDim.x * MLP_WAVES) {
@@ -812,55 +943,6 @@ __global__ void k_order(const Dev D, int* __restrict__ order, int* __restrict__ 
   int p0 = wave_append(&cnt[0], live && sp == 0, 1);
   int p1 = wave_append(&cnt[1], live && sp == 1, 1);
   if (live) order[(size_t)sp * D.n + (sp == 0 ? p0 : p1)] = i;
-}
-
-// Far-field pair term: for r in (FAR0, r_c), s(r) V_LJ(r) with s rising from
-// 0 at FAR0 to 1 at FAR1 (cubic).  One wavefront per atom over its full LJ
-// list; half the energy and virial per side, the force on its own atom.
-__global__ __launch_bounds__(256) void k_far(Dev D, const DevParams* __restrict__ Pp, double* __restrict__ Ff,
-                                             double* __restrict__ acc) {
-  const DevParams& P = *Pp;
-  int lane = threadIdx.x & (WAVE - 1);
-  int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  double e = 0, f[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
-  if (i < D.n) {
-    double4 xi = D.x[i];
-    int si = __double2int_rn(xi.w) == 0 ? 0 : 1;
-    const SysBox& B = box_of(D, i);
-    int nl = min(D.lj_n[i], D.lj_cap);
-    for (int e0 = lane; e0 < nl; e0 += WAVE) {
-      unsigned ent = D.lj_e[(size_t)i * D.lj_cap + e0];
-      int j = (int)(ent & 0x7FFFFFFu), code = (int)(ent >> 27);
-      double4 xj = D.x[j];
-      double dx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
-      double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
-      double dz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
-      double r2 = dx * dx + dy * dy + dz * dz;
-      int p = si + (__double2int_rn(xj.w) == 0 ? 0 : 1);
-      if (r2 >= P.rc2[p] || r2 <= FAR0 * FAR0) continue;
-      double r = sqrt(r2), V, dV;
-      lj_pair<double>(P, p, r, V, dV);
-      double ds;
-      double s = 1.0 - Sw((r - FAR0) / (FAR1 - FAR0), ds);
-      ds = -ds / (FAR1 - FAR0);
-      e += 0.5 * s * V;
-      double gr = (ds * V + s * dV) / r;   // (dE_pair/dr) / r
-      f[0] += gr * dx; f[1] += gr * dy; f[2] += gr * dz;
-      W[0] -= 0.5 * gr * dx * dx; W[1] -= 0.5 * gr * dy * dy; W[2] -= 0.5 * gr * dz * dz;
-      W[3] -= 0.5 * gr * dx * dy; W[4] -= 0.5 * gr * dx * dz; W[5] -= 0.5 * gr * dy * dz;
-    }
-  }
-  for (int c = 0; c < 3; ++c) {
-    double s = f[c];
-    for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && i < D.n) Ff[3 * i + c] = s;
-  }
-  double v7[7] = {e, W[0], W[1], W[2], W[3], W[4], W[5]};
-  for (int q = 0; q < 7; ++q) {
-    double s = v7[q];
-    for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && s != 0) atomic_add(&acc[(blockIdx.x & (NSLOT - 1)) * N_A + (q == 0 ? N_EFAR : N_VIR + q - 1)], s);
-  }
 }
 
 // Ensemble: mean force (plus far field) into F, per-atom spread (RMS over
@@ -1069,6 +1151,8 @@ struct airebo_nn {
   size_t cord = 0, ccnt = 0, cskip = 0;
   unsigned* maxbits = nullptr;
   size_t cmax = 0;
+  NetLDS* packed = nullptr;   // [nm][2] BF16 images for inference
+  bool stale = true;          // images out of date after a weight update
 };
 
 namespace {
@@ -1132,13 +1216,15 @@ void nn_core(airebo_ctx* c, airebo_nn* m, hipStream_t s) {
   LAUNCH(c, K_NN_ZERO, k_zero_small, dim3(1), dim3(64), s, m->cnt, m->maxbits);
   LAUNCH(c, K_NN_ORDER, k_order, dim3(blocks(n, 256)), dim3(256), s, D, m->order, m->cnt);
   LAUNCH(c, K_NN_DESC, k_desc<0>, dim3(blocks((int64_t)n * WAVE, 256)), dim3(256), s, D, m->G, (const float*)nullptr);
+  if (m->stale) {
+    LAUNCH(c, K_NN_PACK, k_pack, dim3(2 * m->nm), dim3(256), s, (const float*)m->params, m->packed);
+    m->stale = false;
+  }
   NNArgs a = nn_args(m, n);
-  int gx = std::max(1, std::min(blocks(n, 16 * MLP_WAVES), 256));
-  LAUNCH(c, K_NN_MLP, k_mlp, dim3(gx, 2 * m->nm), dim3(64 * MLP_WAVES), s, a);
-  LAUNCH(c, K_NN_FORCE, k_desc_force, dim3(blocks((int64_t)n * WAVE, 256)), dim3(256), s, D, (const float*)m->dEdG,
-         m->nm, m->Fm, m->acc);
-  LAUNCH(c, K_NN_FAR, k_far, dim3(blocks((int64_t)n * WAVE, 256)), dim3(256), s, D, (const DevParams*)c->dP, m->Ff,
-         m->acc);
+  int gx = std::max(1, std::min(blocks(blocks(n, 16), 2 * MLP_WAVES), 256));
+  LAUNCH(c, K_NN_MLP, k_mlp, dim3(gx, 2 * m->nm), dim3(64 * MLP_WAVES), s, a, (const NetLDS*)m->packed);
+  LAUNCH(c, K_NN_FORCE, k_desc_force<true>, dim3(n), dim3(WAVE), s, D,
+         (const DevParams*)c->dP, (const float*)m->dEdG, m->nm, m->Fm, m->Ff, m->acc);
   LAUNCH(c, K_NN_ENS, k_ens, dim3(blocks(n, 256)), dim3(256), s, n, m->nm, (const float*)m->Fm, (const double*)m->Ff,
          (const float*)m->Eat, D.F, m->spread, m->maxbits, m->acc);
 }
@@ -1194,7 +1280,7 @@ int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species,
       c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + 64, 1u << 16);
       continue;
     }
-    if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 256 neighbours within 6 A or 48 within 3.5 A");
+    if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 192 neighbours within 6 A or 48 within 3.5 A");
     return check_flags(c, flags);
   }
   return fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established");
@@ -1222,6 +1308,8 @@ int airebo_nn_create(int32_t nmodels, int32_t device, airebo_nn_t* out) {
   rc |= grow(m->mean, c4, DIM);
   rc |= grow(m->istd, c5, DIM);
   rc |= grow(m->shift, c6, 2);
+  size_t c7 = 0;
+  rc |= grow(m->packed, c7, (size_t)nmodels * 2);
   if (rc) { airebo_nn_free(m); return AIREBO_E_DEVICE; }
   m->h_mean.assign(DIM, 0.0f);
   m->h_istd.assign(DIM, 1.0f);
@@ -1246,7 +1334,7 @@ void airebo_nn_free(airebo_nn_t m) {
   if (!m) return;
   void* ptrs[] = {m->params, m->grad, m->m1, m->m2, m->mean, m->istd, m->shift, m->G, m->dEdG, m->U, m->Eat,
                   m->Fm, m->Wres, m->spread, m->dE, m->Ff, m->acc, m->out, m->loss, m->mom, m->fin, m->vir,
-                  m->order, m->cnt, m->skip, m->maxbits};
+                  m->order, m->cnt, m->skip, m->maxbits, m->packed};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -1269,6 +1357,7 @@ int airebo_nn_set_params(airebo_nn_t m, const float* host) {
     if (!std::isfinite(host[k])) return fail(AIREBO_E_ARG, "non-finite weight");
   HIPCHK(hipSetDevice(m->device));
   HIPCHK(hipMemcpy(m->params, host, sizeof(float) * np, hipMemcpyHostToDevice));
+  m->stale = true;
   m->adam_t = 0;
   std::vector<float> zeros(np, 0.0f);
   HIPCHK(hipMemcpy(m->m1, zeros.data(), np * 4, hipMemcpyHostToDevice));
@@ -1379,8 +1468,8 @@ int airebo_nn_descriptor_vjp(airebo_nn_t m, airebo_ctx_t c, int64_t n, const dou
     size_t nF = (size_t)nsets * n * 3;
     hipLaunchKernelGGL(k_fill, dim3(std::min<int64_t>(blocks((int64_t)nF, 256), 4096)), dim3(256), 0, s, F, nF);
     hipLaunchKernelGGL(k_fill_d, dim3(blocks(NSLOT * N_A, 256)), dim3(256), 0, s, m->acc, (size_t)NSLOT * N_A);
-    hipLaunchKernelGGL(k_desc_force, dim3(blocks((int64_t)n * WAVE, 256)), dim3(256), 0, s, D, g, (int)nsets, F,
-                       m->acc);
+    hipLaunchKernelGGL(k_desc_force<false>, dim3(n), dim3(WAVE), 0, s, D,
+                       (const DevParams*)c->dP, g, (int)nsets, F, (double*)nullptr, m->acc);
     hipLaunchKernelGGL(k_vir_out, dim3(1), dim3(64), 0, s, (const double*)m->acc, virial);
     return 0;
   });
@@ -1456,6 +1545,7 @@ int airebo_nn_adam(airebo_nn_t m, double lr, double beta1, double beta2, double 
                      (const float*)m->grad, m->m1, m->m2, (float)lr, (float)beta1, (float)beta2, (float)eps,
                      (float)c1, (float)c2);
   HIPCHK(hipGetLastError());
+  m->stale = true;
   return 0;
 }
 
@@ -1552,7 +1642,7 @@ int airebo_nn_nve(airebo_nn_t m, airebo_ctx_t c, int64_t n, double* pos, double*
   HIPCHK(hipStreamSynchronize(s));
   if (fallbacks) *fallbacks = (int64_t)c->host_stats[S_FALLBACK];
   if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded during NVE");
-  if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 256 neighbours within 6 A or 48 within 3.5 A");
+  if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 192 neighbours within 6 A or 48 within 3.5 A");
   return check_flags(c, flags);
 }
 

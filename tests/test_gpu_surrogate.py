@@ -13,7 +13,9 @@ Tolerances:
     relative to the RMS of the reference, bound 2e-2.
   - The weight gradient chains up to 12 products (bound 4.7e-2).  It is
     checked as a relative L2 error per member, bound 5e-2.
-  - The far field and the AIREBO fallback are FP64 (1e-10).
+  - The far field is FP32 arithmetic on FP64 pair vectors with FP64 sums
+    (1e-6 of the largest force and of the energy).  The AIREBO fallback is
+    FP64 (1e-12).
 """
 import os
 import tempfile
@@ -131,17 +133,19 @@ def test_descriptor_vjp(lib, ctx, name):
     assert np.abs(W - Wr).max() <= 1e-4 * np.abs(Wr).max()
 
 
-def test_far_field_fp64(lib, ctx):
-    """Zero network weights: the forces and energy are the far field alone (FP64)."""
+def test_far_field(lib, ctx):
+    """Zero network weights: the forces and energy are the far field alone."""
     x, s, box, per = SYS["pe_small"]
     nn = lib.Surrogate(nmodels=2)
     e, f, w, _, info = nn.compute(ctx, x, s, box, per, threshold=1e30)
     ref = sr.evaluate(sr.Model(np.zeros((2, 2, sr.NPAR)), np.zeros(sr.DIM), np.ones(sr.DIM), 1.0, [0.0, 0.0]),
                       x, s, box, per, LJ, want_virial=True)
     assert info["fallback"] == 0.0
-    assert info["E_far"] == pytest.approx(ref["E_far"], rel=1e-10)
-    assert np.abs(f.cpu().numpy() - ref["F_far"]).max() <= 1e-10 * np.abs(ref["F_far"]).max()
-    assert np.abs(w.cpu().numpy() - ref["virial"]).max() <= 1e-10 * np.abs(ref["virial"]).max()
+    print("far field: E", info["E_far"], ref["E_far"], "max |dF|", np.abs(f.cpu().numpy() - ref["F_far"]).max(),
+          "max |F|", np.abs(ref["F_far"]).max())
+    assert info["E_far"] == pytest.approx(ref["E_far"], rel=1e-6)
+    assert np.abs(f.cpu().numpy() - ref["F_far"]).max() <= 1e-6 * np.abs(ref["F_far"]).max()
+    assert np.abs(w.cpu().numpy() - ref["virial"]).max() <= 1e-6 * np.abs(ref["virial"]).max()
 
 
 @pytest.mark.parametrize("name", ["cluster_periodic", "pe_small"])
