@@ -51,6 +51,9 @@ namespace airebo {
 constexpr int SCAP = 8;    // short (REBO) neighbours per atom
 constexpr int ICAP = 48;   // intermediate-list entries per atom
 constexpr int PCAP = 64;   // path-map candidates per atom (LDS, per wavefront)
+constexpr int HCAP = 128;  // slots of the per-wavefront candidate lookup (2 x PCAP)
+static_assert(PCAP == 64, "one path candidate per lane when the lookup is filled");
+__device__ __forceinline__ int hslot(int a) { return (int)(((unsigned)a * 2654435761u) >> 25); }   // 7 bits
 constexpr int LJ_BLOCK = 256;
 constexpr int WAVE = 64;
 
@@ -1042,6 +1045,11 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
   __shared__ int c_code[LJ_BLOCK / WAVE][PCAP];
   __shared__ int c_k[LJ_BLOCK / WAVE][PCAP];
   __shared__ double c_prod[LJ_BLOCK / WAVE][PCAP];
+  // candidate lookup by atom: open addressing; the value packs the product's
+  // bits (low 6 cleared) above 63 - candidate index, so an atomic max keeps
+  // the largest product and, on ties, the first candidate
+  __shared__ int h_key[LJ_BLOCK / WAVE][HCAP];
+  __shared__ unsigned long long h_val[LJ_BLOCK / WAVE][HCAP];
   int lane = threadIdx.x & (WAVE - 1);
   int wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -1113,6 +1121,22 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
       }
       if (ncand > PCAP && lane == 0) atomicOr(D.flags, F_OV_PATH);
       ncand = min(ncand, PCAP);
+      for (int k = lane; k < HCAP; k += WAVE) { h_key[wv][k] = -1; h_val[wv][k] = 0ull; }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < ncand) {   // PCAP == WAVE: one candidate per lane
+        int a = c_atom[wv][lane];
+        unsigned long long v = ((unsigned long long)__double_as_longlong(c_prod[wv][lane]) & ~63ull) |
+                               (unsigned long long)(63 - lane);
+        int h = hslot(a);
+        for (int probe = 0; probe < HCAP; ++probe) {
+          int old = atomicCAS(&h_key[wv][h], -1, a);
+          if (old == -1 || old == a) { atomicMax(&h_val[wv][h], v); break; }
+          h = (h + 1) & (HCAP - 1);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
     // ---- pair loop
     int nl = min(D.lj_n[i], D.lj_cap);
@@ -1136,8 +1160,18 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
           bool plain = true;
           if (r < P.r_conn) {
             double prod = 0.0;
-            for (int c = 0; c < ncand; ++c)
-              if (c_atom[wv][c] == j && c_prod[wv][c] > prod) { prod = c_prod[wv][c]; pcode = c_code[wv][c]; }
+            int h = hslot(j);
+            for (int probe = 0; probe < HCAP; ++probe) {
+              int key = h_key[wv][h];
+              if (key == j) {
+                int c = 63 - (int)(h_val[wv][h] & 63ull);
+                prod = c_prod[wv][c];
+                pcode = c_code[wv][c];
+                break;
+              }
+              if (key < 0) break;
+              h = (h + 1) & (HCAP - 1);
+            }
             if (prod >= 1.0) {
               if (i < j) ++n_c0;
               plain = false;
@@ -1715,7 +1749,10 @@ void launch_forces(airebo_ctx* c, hipStream_t s) {
     else LAUNCH(c, K_BOND, k_bond<double>, dim3(nb), dim3(bblk), sb, D, P, mask);
   }
   if (mask & AIREBO_TERM_LJ) {
-    dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK)), gq(std::min(blocks(D.n, qblk), 4096));
+    dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
+    // one lane per expected deferred pair (about 3 per atom in dense melts), so
+    // that the latency-bound b* work is spread over many wavefronts
+    dim3 gq(std::min(blocks(4 * (int64_t)D.n, qblk), 16384));
     if (mixed) {
       LAUNCH(c, K_LJ, k_lj<float>, glj, dim3(LJ_BLOCK), s, D, P);
       LAUNCH(c, K_BSTAR, k_bstar<float>, gq, dim3(qblk), s, D, P);
