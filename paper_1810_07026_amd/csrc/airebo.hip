@@ -1352,15 +1352,23 @@ __global__ void k_finish(Dev D, double* energy, double* virial) {
 constexpr double FTM = 1.0 / 103.642691;   // eV / (A amu) -> A / fs^2
 constexpr double KB = 8.617333262e-5;
 
+// First half kick and drift; the forces used here are then zeroed together
+// with the step's accumulators, bond counters and queue counters (the force
+// chain of a step that starts here needs no separate zeroing).
 __global__ void k_kick_drift(Dev D, double* vel, double m0, double m1, double dt, double half_skin2) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NSLOT * A_N) D.acc[i] = 0;
+  if (D.nsys > 1)
+    for (int k = i; k < D.nsys * A_N; k += gridDim.x * blockDim.x) D.sys_acc[k] = 0;
+  if (i < 3) D.bcount[i] = 0;
+  if (i < NSEG) D.qcount[i * QSTRIDE] = 0;
   if (i >= D.n) return;
   double4 x = D.x[i];
   double im = FTM / (__double2int_rn(x.w) == 0 ? m0 : m1);
   double v[3];
   for (int c = 0; c < 3; ++c) v[c] = vel[3 * i + c] + 0.5 * dt * D.F[3 * i + c] * im;
   x.x += dt * v[0]; x.y += dt * v[1]; x.z += dt * v[2];
-  for (int c = 0; c < 3; ++c) vel[3 * i + c] = v[c];
+  for (int c = 0; c < 3; ++c) { vel[3 * i + c] = v[c]; D.F[3 * i + c] = 0; }
   D.x[i] = x;
   double4 xr = D.xref[i];
   double ddx = x.x - xr.x, ddy = x.y - xr.y, ddz = x.z - xr.z;
@@ -1721,11 +1729,13 @@ void launch_rebuild(airebo_ctx* c, hipStream_t s) {
 }
 
 // Launch one force evaluation on the current positions.
-void launch_forces(airebo_ctx* c, hipStream_t s) {
+// zero = false when the step's k_kick_drift has already zeroed the forces and
+// accumulators.
+void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
   Dev& D = c->D;
   const DevParams* P = c->dP;
   int mask = c->opt.term_mask;
-  LAUNCH(c, K_ZERO, k_zero,
+  if (zero) LAUNCH(c, K_ZERO, k_zero,
          dim3(std::min(std::max({blocks(3 * (int64_t)D.n, 256), NSLOT * A_N / 256, blocks((int64_t)D.nsys * A_N, 256)}),
                        4096)),
          dim3(256), s, D);
@@ -1843,6 +1853,8 @@ int nve_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, 
   int nrows = every > 0 ? (int)(nsteps / every) + 1 : 0;
   double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
   int tb = std::min(1024, std::max(64, ((nsys + 63) / 64) * 64));
+  // k_kick_drift also zeroes the accumulators: cover NSLOT * A_N threads
+  int kd_blocks = std::max(blocks(n, 256), blocks(NSLOT * A_N, 256));
   hipError_t err = hipSuccess;
   auto body = [&](bool first) {
     if (first) {
@@ -1858,10 +1870,9 @@ int nve_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, 
       hipLaunchKernelGGL(k_thermo, dim3(1), dim3(tb), 0, s, D, thermo, (int)every, nrows);
       return;
     }
-    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt,
-           half_skin2);
+    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(kd_blocks), dim3(256), s, D, vel, mass[0], mass[1], dt, half_skin2);
     launch_rebuild(c, s);
-    launch_forces(c, s);
+    launch_forces(c, s, false);
     LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt);
     LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(tb), s, D, thermo, (int)every, nrows);
   };
@@ -1873,27 +1884,74 @@ int nve_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, 
     for (int64_t k = 0; k < nsteps; ++k) body(false);
     HIPCHK(hipStreamSynchronize(s));
   }
-  // capture one step into a graph and replay it
+  // One step is captured into a graph and replayed in chunks.  Before each
+  // chunk the state (positions, velocities, step counter, statistics) is
+  // copied aside on the device; when a rebuild overflows the LJ list during
+  // the chunk, the state is restored, the list capacity grows by half, the
+  // step is captured again and the chunk is repeated.
+  constexpr int64_t CHUNK = 256;
+  if (c->prof) nsteps = 0;
+  double4* xsave = nullptr;
+  double* vsave = nullptr;
+  unsigned long long* ssave = nullptr;   // [S_N] statistics, then the step counter
+  if (nsteps > 0) {
+    err = hipMalloc((void**)&xsave, sizeof(double4) * n);
+    if (err == hipSuccess) err = hipMalloc((void**)&vsave, sizeof(double) * 3 * n);
+    if (err == hipSuccess) err = hipMalloc((void**)&ssave, sizeof(unsigned long long) * (S_N + 1));
+  }
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cs = nullptr;
-  if (!c->prof) err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (c->prof) nsteps = 0;
-  if (err == hipSuccess && cs) err = hipStreamSynchronize(s);
-  if (err == hipSuccess && cs) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (err == hipSuccess && cs) {
+  auto capture = [&]() -> hipError_t {
+    if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
+    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
     hipStream_t keep = s;
     s = cs;
     body(false);
     s = keep;
-    err = hipStreamEndCapture(cs, &graph);
+    e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    return e;
+  };
+  int regrow = 0;
+  if (nsteps > 0 && err == hipSuccess) err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (nsteps > 0 && err == hipSuccess) err = hipStreamSynchronize(s);
+  if (nsteps > 0 && err == hipSuccess) err = capture();
+  for (int64_t done = 0; done < nsteps && err == hipSuccess;) {
+    int64_t k = std::min(CHUNK, nsteps - done);
+    err = hipMemcpyAsync(xsave, c->x, sizeof(double4) * n, hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess) err = hipMemcpyAsync(vsave, vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(ssave, c->stats, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess) err = hipMemcpyAsync(ssave + S_N, c->step, sizeof(int), hipMemcpyDeviceToDevice, cs);
+    for (int64_t q = 0; q < k && err == hipSuccess; ++q) err = hipGraphLaunch(exec, cs);
+    int fl = 0;
+    if (err == hipSuccess) err = hipMemcpyAsync(&fl, c->flags, sizeof(int), hipMemcpyDeviceToHost, cs);
+    if (err == hipSuccess) err = hipStreamSynchronize(cs);
+    if (err != hipSuccess) break;
+    if (!(fl & F_OV_LJ)) { done += k; continue; }
+    if (++regrow > 6 || c->lj_cap >= (1 << 16)) break;   // reported below
+    c->lj_cap = std::min(c->lj_cap + c->lj_cap / 2 + 32, 1 << 16);
+    int rc2 = setup(c, nsys, off, boxes, pers, cs);
+    if (rc2) { err = hipErrorOutOfMemory; break; }
+    D.F = c->F;
+    err = hipMemcpyAsync(c->x, xsave, sizeof(double4) * n, hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess) err = hipMemcpyAsync(vel, vsave, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(c->stats, ssave, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess) err = hipMemcpyAsync(c->step, ssave + S_N, sizeof(int), hipMemcpyDeviceToDevice, cs);
+    if (err == hipSuccess) hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, cs, D, F_REBUILD);
+    if (err == hipSuccess) err = hipStreamSynchronize(cs);
+    if (err == hipSuccess) err = capture();
   }
-  if (err == hipSuccess && cs) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) err = hipGraphLaunch(exec, cs);
-  if (err == hipSuccess && cs) err = hipStreamSynchronize(cs);
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cs) (void)hipStreamDestroy(cs);
+  if (xsave) (void)hipFree(xsave);
+  if (vsave) (void)hipFree(vsave);
+  if (ssave) (void)hipFree(ssave);
   if (err != hipSuccess) {
     (void)hipFree(scratch);
     return fail(AIREBO_E_DEVICE, std::string("nve: ") + hipGetErrorString(err));

@@ -1595,8 +1595,8 @@ int airebo_nn_nve(airebo_nn_t m, airebo_ctx_t c, int64_t n, double* pos, double*
       hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
       return;
     }
-    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt,
-           half_skin2);
+    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(std::max(blocks(n, 256), blocks(NSLOT * A_N, 256))), dim3(256), s, D,
+           vel, mass[0], mass[1], dt, half_skin2);
     launch_rebuild(c, s);
     nn_step(c, m, thr, s);
     LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt);

@@ -842,9 +842,12 @@ def _molecule(family, rng):
     return diamond_cluster(float(rng.uniform(2.5, 3.8)))
 
 
-def molecular_box(family, n_target, rng, density=0.05, min_side=13.0, min_dist=2.6, tries=200):
+def molecular_box(family, n_target, rng, density=0.05, min_side=13.0, min_dist=2.6, tries=200, image_gap=4.0):
     """Molecules of one family at random positions and orientations in a
-    periodic cube of side max((n/density)^(1/3), min_side) until ~n_target atoms."""
+    periodic cube of side max((n/density)^(1/3), min_side, d + image_gap)
+    until ~n_target atoms, d being the first molecule's diameter.  Later
+    molecules wider than side - image_gap are rejected, so that no molecule
+    can reach its own periodic image whatever its orientation."""
     L = max((n_target / density) ** (1.0 / 3.0), min_side)
     box = np.array([L, L, L])
     X = np.zeros((0, 3))
@@ -855,10 +858,14 @@ def molecular_box(family, n_target, rng, density=0.05, min_side=13.0, min_dist=2
         if len(S) + len(s) > 1.1 * n_target and len(S) > 0:
             fails += 1
             continue
+        diam = math.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1).max())
+        if diam > L - image_gap:
+            if len(S) > 0:
+                fails += 1
+                continue
+            L = diam + image_gap
+            box = np.array([L, L, L])
         x = (x - x.mean(0)) @ _random_rotation(rng).T + rng.uniform(0, L, 3)
-        if np.ptp(x, axis=0).max() > L - min_dist:
-            fails += 1
-            continue
         if len(S):
             d = x[:, None, :] - X[None, :, :]
             d -= box * np.round(d / box)
@@ -891,7 +898,7 @@ def batch_cached(nsys=512, seed=SEED0 + 3):
         d = batch_systems(nsys, seed=seed)
         d["meta"] = {k: v for k, v in d["meta"].items() if k != "families"}
         return d
-    return cached(f"batch_{nsys}_s{seed}", make)
+    return cached(f"batch_{nsys}_s{seed}_r2", make)   # r2: boxes sized by molecule diameter
 
 
 # ---- seeded initial weights of the surrogate networks (training inputs) ----
