@@ -569,20 +569,24 @@ def ethylene(cc=1.33):
 
 
 def graphene_flake(nx, ny, cc=1.42):
-    """Rectangular graphene patch with H on every two-fold carbon."""
-    a1 = np.array([cc * math.sqrt(3), 0, 0])
-    a2 = np.array([cc * math.sqrt(3) / 2, cc * 1.5, 0])
+    """Parallelogram of nx x ny fused hexagons (a polycyclic aromatic
+    hydrocarbon; 2 x 2 is pyrene C16H10), H on every two-fold carbon.
+
+    Built as the union of the rings' vertices, so every carbon lies on a
+    ring and has two or three carbon neighbours: no bare chain ends."""
+    a = cc * math.sqrt(3)
+    A1 = np.array([a, 0.0, 0.0])
+    A2 = np.array([a / 2, 1.5 * cc, 0.0])
     pts = []
     for i in range(nx):
         for j in range(ny):
-            o = i * a1 + j * a2 - (j // 2) * a1
-            pts.append(o)
-            pts.append(o + np.array([0, cc, 0]))
+            c = i * A1 + j * A2
+            for m in range(6):
+                t = math.pi / 6 + m * math.pi / 3
+                p = c + cc * np.array([math.cos(t), math.sin(t), 0.0])
+                if not any(np.linalg.norm(p - q) < 0.1 for q in pts):
+                    pts.append(p)
     C = np.array(pts)
-    d = np.linalg.norm(C[:, None] - C[None], axis=2)
-    deg = ((d > 0.1) & (d < cc * 1.1)).sum(1)
-    keep = deg >= 2
-    C = C[keep]
     d = np.linalg.norm(C[:, None] - C[None], axis=2)
     xs, ss = [*C], [0] * len(C)
     for i in range(len(C)):
@@ -807,8 +811,11 @@ FAMILIES = ("linear_alkane", "branched_alkane", "aromatic", "graphene_flake", "d
 
 
 def _clean(x, s):
-    """True when every pair closer than the REBO range is a proper bond:
-    C-C 1.3-1.6 A, C-H 1.0-1.15 A, and no H-H pair below 1.7 A."""
+    """True when every pair closer than the REBO range is a proper bond
+    (C-C 1.3-1.6 A, C-H 1.0-1.15 A, no H-H pair below 1.7 A) and every
+    atom is saturated: each H has one bonded neighbour and each C three
+    (sp2) or four (sp3).  A bare carbon is a radical that reacts in the
+    first picoseconds of dynamics."""
     d = np.linalg.norm(x[:, None] - x[None], axis=2)
     iu = np.triu_indices(len(s), 1)
     dd, a, b = d[iu], s[iu[0]], s[iu[1]]
@@ -817,7 +824,13 @@ def _clean(x, s):
     cc = (a == 0) & (b == 0)
     bad = (hh & (dd < 1.7)) | (ch & ((dd < 1.0) | ((dd > 1.15) & (dd < 1.8)))) | \
           (cc & ((dd < 1.3) | ((dd > 1.6) & (dd < 2.0))))
-    return not bad.any()
+    if bad.any():
+        return False
+    sa, sb = s[:, None], s[None, :]
+    bonded = np.where((sa == 0) & (sb == 0), d < 1.6, np.where(sa + sb == 1, d < 1.15, False))
+    np.fill_diagonal(bonded, False)
+    deg = bonded.sum(1)
+    return bool(np.all(deg[s == 1] == 1) and np.all((deg[s == 0] >= 3) & (deg[s == 0] <= 4)))
 
 
 def molecule(family, rng, tries=400):
@@ -898,7 +911,7 @@ def batch_cached(nsys=512, seed=SEED0 + 3):
         d = batch_systems(nsys, seed=seed)
         d["meta"] = {k: v for k, v in d["meta"].items() if k != "families"}
         return d
-    return cached(f"batch_{nsys}_s{seed}_r2", make)   # r2: boxes sized by molecule diameter
+    return cached(f"batch_{nsys}_s{seed}_r3", make)   # r3: saturated molecules only
 
 
 # ---- seeded initial weights of the surrogate networks (training inputs) ----
