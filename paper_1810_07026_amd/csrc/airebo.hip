@@ -100,7 +100,7 @@ struct Dev {
   double skin, rlist2[3], rint2[3];
   double4* x;        // positions (w = species) since the last build
   double4* xref;     // positions at the last build
-  double4* xsort;    // positions ordered by cell (list build only)
+  float4* xsort;     // FP32 positions ordered by cell (list build only)
   int* cell_of;
   int* cell_count;
   int* cell_start;
@@ -612,43 +612,72 @@ __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> r
   }
 }
 
+// Forward state of one bond order, kept for its reverse pass.
+template <typename R>
+struct BondFwd {
+  EndF<R> ei, ej;
+  R rlam, Fij, Fji, dFc, Tv, dTa, dTb, dTc, Sdh;
+  int si, sj;
+  bool dh;
+};
+
+// Bond order b_ij, forward pass only; fills the state of the reverse pass.
+template <typename R>
+__device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar,
+                            BondFwd<R>& f, int* st) {
+  int si = __double2int_rn(D.x[i].w), sj = __double2int_rn(D.x[j].w);
+  int p = si + sj;
+  f.si = si; f.sj = sj;
+  f.rlam = (bstar && P.bstar_use_R1) ? (R)P.R1[p] : r;
+  V3<R> rji = -rij;
+  end_fwd(P, D, i, si, j, sj, rij, r, f.rlam, f.ei, st);
+  end_fwd(P, D, j, sj, i, si, rji, r, f.rlam, f.ej, st);
+  R Nconj = (R)1 + f.ei.conj * f.ei.conj + f.ej.conj * f.ej.conj;
+  R dFa, dFb;
+  R pirc;
+  bool swap = (p == 1 && si == 1);   // C-H table takes the carbon side first
+  int tF = p == 0 ? TRI_FCC : (p == 1 ? TRI_FCH : TRI_FHH);
+  if (!swap) { pirc = tricubic(P, tF, f.ei.N, f.ej.N, Nconj, dFa, dFb, f.dFc, st); f.Fij = dFa; f.Fji = dFb; }
+  else { pirc = tricubic(P, tF, f.ej.N, f.ei.N, Nconj, dFa, dFb, f.dFc, st); f.Fij = dFb; f.Fji = dFa; }
+  f.Tv = 0; f.dTa = 0; f.dTb = 0; f.dTc = 0; f.Sdh = 0;
+  f.dh = false;
+  if (p == 0) {
+    f.Tv = tricubic(P, TRI_TCC, f.ei.N, f.ej.N, Nconj, f.dTa, f.dTb, f.dTc, st);
+    f.dh = f.Tv != (R)0 || f.dTa != (R)0 || f.dTb != (R)0 || f.dTc != (R)0;
+    if (f.dh) {
+      V3<R> dummy = {0, 0, 0};
+      R Et = 0, Gwij = 0;
+      Acc none;   // forward only: nothing is accumulated
+      none.st[0] = none.st[1] = 0;
+      dihedral(P, D, i, j, rij, r, (R)0, false, false, (R)0, f.Sdh, Et, dummy, Gwij, none);
+    }
+  }
+  return (R)0.5 * (f.ei.p + f.ej.p) + pirc + f.Tv * f.Sdh;
+}
+
+// Reverse pass of a bond order for dE/db = Gb, from its forward state.
+template <typename R>
+__device__ void bond_order_rev(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar,
+                               const BondFwd<R>& f, R Gb, V3<R>& gij, Acc& acc) {
+  R GNij = Gb * (f.Fij + f.Sdh * f.dTa), GNji = Gb * (f.Fji + f.Sdh * f.dTb), GNc = Gb * (f.dFc + f.Sdh * f.dTc);
+  if (f.dh) {
+    R s2 = 0, Et = 0, Gwij = 0;
+    dihedral(P, D, i, j, rij, r, (R)0, false, true, Gb * f.Tv, s2, Et, gij, Gwij, acc);
+  }
+  V3<R> gi = {0, 0, 0}, gj = {0, 0, 0};
+  V3<R> rji = -rij;
+  end_rev(P, D, i, f.si, j, f.sj, rij, r, f.rlam, bstar, f.ei, (R)0.5 * Gb, GNij, GNc * (R)2 * f.ei.conj, gi, acc);
+  end_rev(P, D, j, f.sj, i, f.si, rji, r, f.rlam, bstar, f.ej, (R)0.5 * Gb, GNji, GNc * (R)2 * f.ej.conj, gj, acc);
+  gij = gij + gi - gj;
+}
+
 // Complete bond order (value and, with rev, its reverse pass for dE/db = Gb).
 template <typename R>
 __device__ R bond_order(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar, bool rev, R Gb,
                         V3<R>& gij, Acc& acc) {
-  int si = __double2int_rn(D.x[i].w), sj = __double2int_rn(D.x[j].w);
-  int p = si + sj;
-  R rlam = (bstar && P.bstar_use_R1) ? (R)P.R1[p] : r;
-  EndF<R> ei, ej;
-  V3<R> rji = -rij;
-  end_fwd(P, D, i, si, j, sj, rij, r, rlam, ei, acc.st);
-  end_fwd(P, D, j, sj, i, si, rji, r, rlam, ej, acc.st);
-  R Nconj = (R)1 + ei.conj * ei.conj + ej.conj * ej.conj;
-  R dFa, dFb, dFc;
-  R pirc;
-  bool swap = (p == 1 && si == 1);   // C-H table takes the carbon side first
-  int tF = p == 0 ? TRI_FCC : (p == 1 ? TRI_FCH : TRI_FHH);
-  R Fij, Fji;
-  if (!swap) { pirc = tricubic(P, tF, ei.N, ej.N, Nconj, dFa, dFb, dFc, acc.st); Fij = dFa; Fji = dFb; }
-  else { pirc = tricubic(P, tF, ej.N, ei.N, Nconj, dFa, dFb, dFc, acc.st); Fij = dFb; Fji = dFa; }
-  R Tv = 0, dTa = 0, dTb = 0, dTc = 0, Sdh = 0, Et = 0, Gwij = 0;
-  bool dh = false;
-  if (p == 0) {
-    Tv = tricubic(P, TRI_TCC, ei.N, ej.N, Nconj, dTa, dTb, dTc, acc.st);
-    dh = Tv != (R)0 || dTa != (R)0 || dTb != (R)0 || dTc != (R)0;
-    if (dh) { V3<R> dummy = {0, 0, 0}; dihedral(P, D, i, j, rij, r, (R)0, false, false, (R)0, Sdh, Et, dummy, Gwij, acc); }
-  }
-  R b = (R)0.5 * (ei.p + ej.p) + pirc + Tv * Sdh;
-  if (!rev) return b;
-  R GNij = Gb * (Fij + Sdh * dTa), GNji = Gb * (Fji + Sdh * dTb), GNc = Gb * (dFc + Sdh * dTc);
-  if (dh) {
-    R s2 = 0;
-    dihedral(P, D, i, j, rij, r, (R)0, false, true, Gb * Tv, s2, Et, gij, Gwij, acc);
-  }
-  V3<R> gi = {0, 0, 0}, gj = {0, 0, 0};
-  end_rev(P, D, i, si, j, sj, rij, r, rlam, bstar, ei, (R)0.5 * Gb, GNij, GNc * (R)2 * ei.conj, gi, acc);
-  end_rev(P, D, j, sj, i, si, rji, r, rlam, bstar, ej, (R)0.5 * Gb, GNji, GNc * (R)2 * ej.conj, gj, acc);
-  gij = gij + gi - gj;
+  BondFwd<R> f;
+  R b = bond_order_fwd(P, D, i, j, rij, r, bstar, f, acc.st);
+  if (rev) bond_order_rev(P, D, i, j, rij, r, bstar, f, Gb, gij, acc);
   return b;
 }
 
@@ -738,25 +767,37 @@ __global__ void k_fill(Dev D) {
   if (i >= D.n) return;
   int slot = atomicAdd(&D.cell_cursor[D.cell_of[i]], 1);
   D.cell_atoms[slot] = i;
-  D.xsort[slot] = D.x[i];
+  double4 x = D.x[i];
+  D.xsort[slot] = make_float4((float)x.x, (float)x.y, (float)x.z, (float)x.w);
 }
 
 // One wavefront per atom: full LJ list (cutoff + skin, with image shift code)
 // and intermediate REBO list (R2 + skin), compacted with wave ballots.
+// The candidates of the 27 neighbour cells form one stream (each lane finds
+// its cell by a binary search over the per-cell prefix counts in LDS); the
+// atom index and FP32 position of the next block of 64 candidates are
+// loaded while this block is tested.  The FP32 test uses cutoffs enlarged by
+// 1e-3 A, far above its rounding error (~1e-4 A at 500 A coordinates), so
+// both lists contain every pair within the exact cutoffs; every consumer
+// tests distances again in FP64.
 __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restrict__ Pp) {
   if (!(*D.flags & F_REBUILD)) return;
+  __shared__ int s_pre[4][28];        // first stream index of each cell (28th: total)
+  __shared__ int s_start[4][27];      // first slot of the cell in the cell-ordered arrays
+  __shared__ unsigned s_code[4][27];  // image shift code of the cell
   int lane = threadIdx.x & (WAVE - 1);
+  int wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   if (i >= D.n) return;
   double4 xi = D.x[i];
   int si = __double2int_rn(xi.w);
   const SysBox& B = box_of(D, i);
-  int ci[3] = {cell_coord(xi.x, B.invL[0], B.nc[0]), cell_coord(xi.y, B.invL[1], B.nc[1]),
-               cell_coord(xi.z, B.invL[2], B.nc[2])};
-  int nlj = 0, nin = 0;
-  unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-  for (int o = 0; o < 27; ++o) {
-    int off[3] = {o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1};
+  int cnt = 0, start = 0;
+  unsigned code = 13;
+  if (lane < 27) {
+    int ci[3] = {cell_coord(xi.x, B.invL[0], B.nc[0]), cell_coord(xi.y, B.invL[1], B.nc[1]),
+                 cell_coord(xi.z, B.invL[2], B.nc[2])};
+    int off[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
     int cc[3], sh[3];
     bool skip = false;
     for (int c = 0; c < 3; ++c) {
@@ -771,38 +812,88 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
         if (t < 0 || t >= B.nc[c]) skip = true;
       }
     }
-    if (skip) continue;
-    int cell = B.cell_off + (cc[0] * B.nc[1] + cc[1]) * B.nc[2] + cc[2];
-    int start = D.cell_start[cell], cnt = D.cell_start[cell + 1] - start;
-    unsigned code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
-    double shx = sh[0] * B.L[0], shy = sh[1] * B.L[1], shz = sh[2] * B.L[2];
-    for (int base = 0; base < cnt; base += WAVE) {
-      int idx = base + lane;
-      bool ok_lj = false, ok_in = false;
-      int j = -1;
-      if (idx < cnt) {
-        j = D.cell_atoms[start + idx];
-        double4 xj = D.xsort[start + idx];
-        double dx = xj.x + shx - xi.x, dy = xj.y + shy - xi.y, dz = xj.z + shz - xi.z;
-        double r2 = dx * dx + dy * dy + dz * dz;
-        int p = si + __double2int_rn(xj.w);
-        bool self = (j == i) && code == 13;
-        ok_lj = !self && r2 < D.rlist2[p];
-        ok_in = !self && r2 < D.rint2[p];
-      }
-      unsigned long long m = __ballot(ok_lj);
-      if (ok_lj) {
-        int pos = nlj + __popcll(m & below);
-        if (pos < D.lj_cap) D.lj_e[(size_t)i * D.lj_cap + pos] = (unsigned)j | (code << 27);
-      }
-      nlj += __popcll(m);
-      m = __ballot(ok_in);
-      if (ok_in) {
-        int pos = nin + __popcll(m & below);
-        if (pos < ICAP) D.in_e[i * ICAP + pos] = j;
-      }
-      nin += __popcll(m);
+    code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
+    if (!skip) {
+      int cell = B.cell_off + (cc[0] * B.nc[1] + cc[1]) * B.nc[2] + cc[2];
+      start = D.cell_start[cell];
+      cnt = D.cell_start[cell + 1] - start;
     }
+  }
+  int incl = cnt;
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane < 27) { s_pre[wv][lane] = incl - cnt; s_start[wv][lane] = start; s_code[wv][lane] = code; }
+  if (lane == 27) s_pre[wv][27] = incl;   // lanes >= 27 add nothing: the total
+  int total = __shfl(incl, 27);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // stream position v -> slot in the cell-ordered arrays and shift code
+  auto locate = [&](int v, int& slot, unsigned& cd) {
+    int lo = 0, hi = 27;   // s_pre[lo] <= v < s_pre[hi]
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (s_pre[wv][mid] <= v) lo = mid; else hi = mid;
+    }
+    slot = s_start[wv][lo] + (v - s_pre[wv][lo]);
+    cd = s_code[wv][lo];
+  };
+  float rlf[3], rif[3];
+  for (int p = 0; p < 3; ++p) {
+    float a = (float)sqrt(D.rlist2[p]) + 1e-3f, b = (float)sqrt(D.rint2[p]) + 1e-3f;
+    rlf[p] = a * a;
+    rif[p] = b * b;
+  }
+  float xix = (float)xi.x, xiy = (float)xi.y, xiz = (float)xi.z;
+  float Lx = (float)B.L[0], Ly = (float)B.L[1], Lz = (float)B.L[2];
+  int nlj = 0, nin = 0;
+  unsigned long long below = lanes_below();
+  int j_n = -1;
+  float4 x_n = make_float4(0.f, 0.f, 0.f, 0.f);
+  unsigned c_n = 13;
+  if (lane < total) {
+    int slot;
+    locate(lane, slot, c_n);
+    j_n = D.cell_atoms[slot];
+    x_n = D.xsort[slot];
+  }
+  for (int base = 0; base < total; base += WAVE) {
+    int v = base + lane;
+    int j = j_n;
+    float4 xj = x_n;
+    unsigned cd = c_n;
+    if (v + WAVE < total) {
+      int slot;
+      locate(v + WAVE, slot, c_n);
+      j_n = D.cell_atoms[slot];
+      x_n = D.xsort[slot];
+    }
+    bool ok_lj = false, ok_in = false;
+    if (v < total) {
+      float dx = xj.x + (float)((int)(cd / 9) - 1) * Lx - xix;
+      float dy = xj.y + (float)((int)((cd / 3) % 3) - 1) * Ly - xiy;
+      float dz = xj.z + (float)((int)(cd % 3) - 1) * Lz - xiz;
+      float r2 = dx * dx + dy * dy + dz * dz;
+      int p = si + (xj.w != 0.0f ? 1 : 0);
+      float rl = p == 0 ? rlf[0] : (p == 1 ? rlf[1] : rlf[2]);
+      float ri = p == 0 ? rif[0] : (p == 1 ? rif[1] : rif[2]);
+      bool self = (j == i) && cd == 13;
+      ok_lj = !self && r2 < rl;
+      ok_in = !self && r2 < ri;
+    }
+    unsigned long long m = __ballot(ok_lj);
+    if (ok_lj) {
+      int pos = nlj + __popcll(m & below);
+      if (pos < D.lj_cap) D.lj_e[(size_t)i * D.lj_cap + pos] = (unsigned)j | (cd << 27);
+    }
+    nlj += __popcll(m);
+    m = __ballot(ok_in);
+    if (ok_in) {
+      int pos = nin + __popcll(m & below);
+      if (pos < ICAP) D.in_e[i * ICAP + pos] = j;
+    }
+    nin += __popcll(m);
   }
   if (lane == 0) {
     D.lj_n[i] = nlj;            // unclamped; readers clamp to lj_cap
@@ -1024,6 +1115,27 @@ __device__ __forceinline__ void lj_pair(const DevParams& P, int p, R r, R& V, R&
   dV = dv * S + v * dS * isw;
 }
 
+// Append the n (<= 2 WAVE) deferred pairs staged in LDS by one wavefront to
+// the queue segment of its block: one reservation, coalesced stores.
+// Returns 0 (the staging buffer is empty again).
+__device__ __forceinline__ int flush_deferred(const Dev& D, int4* buf, int n) {
+  int lane = threadIdx.x & (WAVE - 1);
+  int seg = blockIdx.x & (NSEG - 1);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  int base = 0;
+  if (lane == 0) base = atomicAdd(D.qcount + seg * QSTRIDE, n);
+  base = __shfl(base, 0);
+  for (int k = lane; k < n; k += WAVE) {
+    int slot = base + k;
+    if (slot < D.qcap) D.q[(size_t)seg * D.qcap + slot] = buf[k];
+    else atomicOr(D.flags, F_OV_QUEUE);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return 0;
+}
+
 // LJ term (Alg. 3), one wavefront per atom over its full list.
 //
 // The wavefront first maps every atom reachable from i over at most three
@@ -1050,6 +1162,10 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
   // the largest product and, on ties, the first candidate
   __shared__ int h_key[LJ_BLOCK / WAVE][HCAP];
   __shared__ unsigned long long h_val[LJ_BLOCK / WAVE][HCAP];
+  // deferred pairs of the wavefront, appended to the queue in one reservation
+  // when WAVE more might not fit and at the end
+  __shared__ int4 dq[LJ_BLOCK / WAVE][2 * WAVE];
+  int ndq = 0;
   int lane = threadIdx.x & (WAVE - 1);
   int wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -1138,14 +1254,18 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
-    // ---- pair loop
+    // ---- pair loop; the list entries of the next block of 64 are loaded
+    // while this block is evaluated
     int nl = min(D.lj_n[i], D.lj_cap);
+    const unsigned* list = D.lj_e + (size_t)i * D.lj_cap;
+    unsigned ent_n = lane < nl ? list[lane] : 0u;
     for (int base = 0; base < nl; base += WAVE) {
       int e0 = base + lane;
       bool push = false;
       int j = 0, code = 0, pcode = 0;
+      unsigned ent = ent_n;
+      if (e0 + WAVE < nl) ent_n = list[e0 + WAVE];
       if (e0 < nl) {
-        unsigned ent = D.lj_e[(size_t)i * D.lj_cap + e0];
         j = (int)(ent & 0x7FFFFFFu);
         code = (int)(ent >> 27);
         double4 xj = D.x[j];
@@ -1193,15 +1313,15 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restr
           }
         }
       }
-      // deferred pairs: one queue reservation per wavefront
-      int seg = blockIdx.x & (NSEG - 1);
-      int slot = wave_append(D.qcount + seg * QSTRIDE, push, 1);
-      if (push) {
-        if (slot < D.qcap) D.q[(size_t)seg * D.qcap + slot] = make_int4(i, j, code, pcode);
-        else atomicOr(D.flags, F_OV_QUEUE);
-      }
+      // deferred pairs: staged in LDS, flushed when the next block might
+      // not fit
+      unsigned long long pm = __ballot(push);
+      if (push) dq[wv][ndq + __popcll(pm & below)] = make_int4(i, j, code, pcode);
+      ndq += __popcll(pm);
+      if (ndq > WAVE) ndq = flush_deferred(D, dq[wv], ndq);
     }
   }
+  if (ndq > 0) flush_deferred(D, dq[wv], ndq);
   // reduce the force on atom i across the wavefront
   for (int c = 0; c < 3; ++c) {
     double s = fi[c];
@@ -1265,8 +1385,9 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
     V3<R> rij = {(R)dx, (R)dy, (R)dz};
     V3<R> gij = {0, 0, 0};
     double Sb = 1.0, dSb = 0.0;
+    BondFwd<R> bf;
     if (Sr > 0.0) {
-      R bs = bond_order(P, D, i, j, rij, (R)r, true, false, (R)0, gij, acc);
+      R bs = bond_order_fwd(P, D, i, j, rij, (R)r, true, bf, acc.st);
       double inv_b = 1.0 / (P.bmax[p] - P.bmin[p]);
       Sb = Sw(((double)bs - P.bmin[p]) * inv_b, dSb);
       dSb *= inv_b;
@@ -1274,10 +1395,10 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
     double Qf = Sr * Sb + 1.0 - Sr;
     e += Qf * C * V;
     double Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
-    if (dSb != 0.0) {
+    if (dSb != 0.0) {   // the reverse pass reuses the forward state
       ++ndsb;
       R Gb = (R)(Sr * dSb * C * V);
-      bond_order(P, D, i, j, rij, (R)r, true, true, Gb, gij, acc);
+      bond_order_rev(P, D, i, j, rij, (R)r, true, bf, Gb, gij, acc);
     }
     if (prod > 0.0) path_grad<double>(D, pi, -Qf * V, 1.0, 1.0, acc);
     gij = gij + (R)(Gr / r) * rij;
@@ -1481,7 +1602,8 @@ struct airebo_ctx {
   int64_t n = 0;
   int lj_cap = 0;
   // buffers and capacities
-  double4 *x = nullptr, *xref = nullptr, *xsort = nullptr;
+  double4 *x = nullptr, *xref = nullptr;
+  float4* xsort = nullptr;
   size_t cx = 0, cxr = 0, cxs = 0;
   hipStream_t side = nullptr;     // second stream: bonded terms run beside the LJ chain
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -1741,35 +1863,38 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
          dim3(256), s, D);
   int sblk = c->opt.short_block ? c->opt.short_block : 128;
   LAUNCH(c, K_SHORT, k_short, dim3(blocks(D.n, sblk)), dim3(sblk), s, D, P);
-  // fork: the bonded kernel runs on the side stream beside the LJ chain (the
-  // profiler's per-kernel events keep everything on one stream)
-  bool fork = !c->prof && (mask & AIREBO_TERM_LJ) && (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION));
+  int bblk = c->opt.bond_block ? c->opt.bond_block : 64;
+  int nb = c->opt.bond_grid ? c->opt.bond_grid : std::min(blocks((int64_t)D.n * 2, bblk), 8192);
+  int qblk = c->opt.defer_block ? c->opt.defer_block : 64;
+  bool mixed = c->opt.precision == AIREBO_MIXED;
+  bool bonded = mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION);
+  if (mask & AIREBO_TERM_LJ) {
+    dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
+    if (mixed) LAUNCH(c, K_LJ, k_lj<float>, glj, dim3(LJ_BLOCK), s, D, P);
+    else LAUNCH(c, K_LJ, k_lj<double>, glj, dim3(LJ_BLOCK), s, D, P);
+  }
+  // The LJ kernel fills the device on its own (a wavefront per atom); the
+  // bonded kernel (a lane per bond) and the deferred b* pairs (a lane per
+  // pair) are both latency-bound at low occupancy, so they run side by side
+  // on two streams after it.  (The profiler's per-kernel events keep
+  // everything on one stream.)
+  bool fork = !c->prof && (mask & AIREBO_TERM_LJ) && bonded;
   hipStream_t sb = s;
   if (fork) {
     (void)hipEventRecord(c->ev_fork, s);
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     sb = c->side;
   }
-  int bblk = c->opt.bond_block ? c->opt.bond_block : 64;
-  int nb = c->opt.bond_grid ? c->opt.bond_grid : std::min(blocks((int64_t)D.n * 2, bblk), 8192);
-  int qblk = c->opt.defer_block ? c->opt.defer_block : 64;
-  bool mixed = c->opt.precision == AIREBO_MIXED;
-  if (mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION)) {
+  if (bonded) {
     if (mixed) LAUNCH(c, K_BOND, k_bond<float>, dim3(nb), dim3(bblk), sb, D, P, mask);
     else LAUNCH(c, K_BOND, k_bond<double>, dim3(nb), dim3(bblk), sb, D, P, mask);
   }
   if (mask & AIREBO_TERM_LJ) {
-    dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
     // one lane per expected deferred pair (about 3 per atom in dense melts), so
     // that the latency-bound b* work is spread over many wavefronts
     dim3 gq(std::min(blocks(4 * (int64_t)D.n, qblk), 16384));
-    if (mixed) {
-      LAUNCH(c, K_LJ, k_lj<float>, glj, dim3(LJ_BLOCK), s, D, P);
-      LAUNCH(c, K_BSTAR, k_bstar<float>, gq, dim3(qblk), s, D, P);
-    } else {
-      LAUNCH(c, K_LJ, k_lj<double>, glj, dim3(LJ_BLOCK), s, D, P);
-      LAUNCH(c, K_BSTAR, k_bstar<double>, gq, dim3(qblk), s, D, P);
-    }
+    if (mixed) LAUNCH(c, K_BSTAR, k_bstar<float>, gq, dim3(qblk), s, D, P);
+    else LAUNCH(c, K_BSTAR, k_bstar<double>, gq, dim3(qblk), s, D, P);
   }
   if (fork) {
     (void)hipEventRecord(c->ev_join, c->side);
