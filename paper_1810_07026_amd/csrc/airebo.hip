@@ -566,6 +566,7 @@ __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> r
     V3<R> a = cross(rij, rik);
     R na2 = dot(a, a);
     int sk = __double2int_rn(D.x[k].w);
+    V3<R> gik_sum = {0, 0, 0};   // dE/dr_ik summed over l (one force update per k)
     for (int u = 0; u < nj; ++u) {
       int l = D.sj[j * SCAP + u];
       if (l == i || l == k) continue;
@@ -606,9 +607,10 @@ __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> r
       V3<R> gjl = cross(Gb, rij) + (Gwjl * dwjl / rjl_l) * rjl + Gcj * (ijl * rji - (cj / (rjl_l * rjl_l)) * rjl);
       gij = gij + cross(rik, Ga) + cross(rjl, Gb) + Gci * (iik * rik - (ci / (r * r)) * rij);
       gij = gij - Gcj * (ijl * rjl - (cj / (r * r)) * rji);
-      acc.vec(i, k, rik, gik);
+      gik_sum = gik_sum + gik;
       acc.vec(j, l, rjl, gjl);
     }
+    if (rev) acc.vec(i, k, rik, gik_sum);
   }
 }
 
@@ -656,11 +658,13 @@ __device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R
 }
 
 // Reverse pass of a bond order for dE/db = Gb, from its forward state.
+// With dihedral_done, the caller takes the pi^dh part of the dihedral loop
+// (dE/dSdh = Gb T_ij) together with its own pass over the same loop.
 template <typename R>
 __device__ void bond_order_rev(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar,
-                               const BondFwd<R>& f, R Gb, V3<R>& gij, Acc& acc) {
+                               const BondFwd<R>& f, R Gb, V3<R>& gij, Acc& acc, bool dihedral_done = false) {
   R GNij = Gb * (f.Fij + f.Sdh * f.dTa), GNji = Gb * (f.Fji + f.Sdh * f.dTb), GNc = Gb * (f.dFc + f.Sdh * f.dTc);
-  if (f.dh) {
+  if (f.dh && !dihedral_done) {
     R s2 = 0, Et = 0, Gwij = 0;
     dihedral(P, D, i, j, rij, r, (R)0, false, true, Gb * f.Tv, s2, Et, gij, Gwij, acc);
   }
@@ -669,16 +673,6 @@ __device__ void bond_order_rev(const DevParams& P, const Dev& D, int i, int j, V
   end_rev(P, D, i, f.si, j, f.sj, rij, r, f.rlam, bstar, f.ei, (R)0.5 * Gb, GNij, GNc * (R)2 * f.ei.conj, gi, acc);
   end_rev(P, D, j, f.sj, i, f.si, rji, r, f.rlam, bstar, f.ej, (R)0.5 * Gb, GNji, GNc * (R)2 * f.ej.conj, gj, acc);
   gij = gij + gi - gj;
-}
-
-// Complete bond order (value and, with rev, its reverse pass for dE/db = Gb).
-template <typename R>
-__device__ R bond_order(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar, bool rev, R Gb,
-                        V3<R>& gij, Acc& acc) {
-  BondFwd<R> f;
-  R b = bond_order_fwd(P, D, i, j, rij, r, bstar, f, acc.st);
-  if (rev) bond_order_rev(P, D, i, j, rij, r, bstar, f, Gb, gij, acc);
-  return b;
 }
 
 // ---------------------------------------------------------------------------
@@ -1062,6 +1056,8 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
     for (int c = 0; c < 6; ++c) W0[c] = acc.W[c];
     V3<R> gij = {0, 0, 0};
     R Gr = 0;
+    const bool tors = (mask & AIREBO_TERM_TORSION) && p == 0;
+    R GSdh = 0;   // dE/d(pi^dh dihedral sum), taken in the torsion's pass over the same loop
     if (mask & AIREBO_TERM_REBO) {
       R ea = (R)P.alpha[p];
       R eR = xexp(-ea * r) * (R)P.A[p];
@@ -1075,13 +1071,16 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
         dVA -= (R)P.beta[p][m] * t;
       }
       R Gb = -wij * VA;
-      R b = bond_order(P, D, i, j, rij, r, false, true, Gb, gij, acc);
+      BondFwd<R> bf;
+      R b = bond_order_fwd(P, D, i, j, rij, r, false, bf, acc.st);
+      bond_order_rev(P, D, i, j, rij, r, false, bf, Gb, gij, acc, tors);
+      if (tors && bf.dh) GSdh = Gb * bf.Tv;
       er += (double)(wij * (VR - b * VA));
       Gr += dwij * (VR - b * VA) + wij * (dVR - b * dVA);
     }
-    if ((mask & AIREBO_TERM_TORSION) && p == 0) {
+    if (tors) {
       R Sdh = 0, Et = 0, Gwij = 0;
-      dihedral(P, D, i, j, rij, r, wij, true, true, (R)0, Sdh, Et, gij, Gwij, acc);
+      dihedral(P, D, i, j, rij, r, wij, true, true, GSdh, Sdh, Et, gij, Gwij, acc);
       et += (double)Et;
       Gr += Gwij * dwij;
     }
