@@ -1148,8 +1148,16 @@ __device__ __forceinline__ int flush_deferred(const Dev& D, int4* buf, int n) {
 // inside the S_r range) is deferred to a queue that k_defer evaluates in
 // full.  Each pair is seen from both ends: each end adds half the energy and
 // virial and the full force on its own atom.
+// Minimum waves per SIMD asked of the compiler for the LJ kernel: the FP32
+// instantiation fits six (80 VGPRs) without spilling; FP64 keeps five.
 template <typename R>
-__global__ __launch_bounds__(LJ_BLOCK) void k_lj(Dev D, const DevParams* __restrict__ Pp) {
+struct LjWaves {
+  static constexpr int value = std::is_same<R, float>::value ? 6 : 5;
+};
+
+template <typename R>
+__global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R>::value, 8))) void k_lj(
+    Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   __shared__ int c_atom[LJ_BLOCK / WAVE][PCAP];
