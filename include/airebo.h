@@ -64,7 +64,7 @@ typedef struct {
   int32_t bond_block;  /* threads per block of the bonded kernel: 64, 128 or 256 (64)  */
   int32_t bond_grid;   /* blocks of the bonded kernel's persistent grid (auto)        */
   int32_t defer_block; /* threads per block of the deferred-pair kernel: 64..256 (64) */
-  int32_t short_block; /* threads per block of the short-list kernel: 64..256 (128)   */
+  int32_t short_block; /* threads per block of the short-list kernel: 256, 512, 1024 (1024) */
   int32_t reserved[4];
 } airebo_options;
 

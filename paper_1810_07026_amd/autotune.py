@@ -21,7 +21,7 @@ CANDIDATES = {
     "bond_block": [64, 128, 256],
     "bond_grid": [0, 256, 512, 1024, 2048, 4096],
     "defer_block": [64, 128, 256],
-    "short_block": [64, 128, 256],
+    "short_block": [256, 512, 1024],
 }
 
 

@@ -925,61 +925,116 @@ __device__ __forceinline__ void minimg(const SysBox& B, double& dx, double& dy, 
 }
 
 // Exact short list, weights and coordination; species-bucketed bond list.
-__global__ __launch_bounds__(256) void k_short(Dev D, const DevParams* __restrict__ Pp) {
+__global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // SG lanes per atom: lane `sub` of the group takes intermediate entries
+  // sub, sub + SG, ...; the valid ones are compacted in entry order
+  constexpr int SG = 16;
+  static_assert(ICAP % SG == 0 && WAVE % SG == 0, "short-list groups");
+  int lane = threadIdx.x & (WAVE - 1);
+  int sub = lane & (SG - 1);
+  unsigned long long gmask = ((1ull << SG) - 1) << (lane & ~(SG - 1));
+  unsigned long long below = lanes_below();
+  int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / SG);
   bool live = i < D.n;
-  int cnt = 0;
-  int nb[3] = {0, 0, 0};
+  double4 xi = make_double4(0, 0, 0, 0);
+  int si = 0, m = 0;
   if (live) {
-  double4 xi = D.x[i];
-  int si = __double2int_rn(xi.w);
-  const SysBox& B = box_of(D, i);
-  int m = D.in_n[i];
-  double NC = 0, NH = 0;
-  for (int e = 0; e < m; ++e) {
-    int j = D.in_e[i * ICAP + e];
-    double4 xj = D.x[j];
-    double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-    minimg(B, dx, dy, dz);
-    double r2 = dx * dx + dy * dy + dz * dz;
-    int sj = __double2int_rn(xj.w);
-    int p = si + sj;
-    if (r2 >= P.R2[p] * P.R2[p]) continue;
-    double r = sqrt(r2), dw;
-    double w = cutw<double>(P, p, r, dw);
-    if (sj == 0) NC += w; else NH += w;
-    if (cnt < SCAP) {
-      D.sj[i * SCAP + cnt] = j;
-      D.sd[i * SCAP + cnt] = make_double4(dx, dy, dz, r);
-      D.sw[i * SCAP + cnt] = make_double2(w, dw);
-      if (j > i) nb[p]++;
+    xi = D.x[i];
+    si = __double2int_rn(xi.w);
+    m = D.in_n[i];
+  }
+  const SysBox& B = box_of(D, live ? i : 0);
+  int mmax = wave_max(m);
+  int cnt = 0;                // valid entries of atom i so far (uniform in the group)
+  double NC = 0, NH = 0;      // partial sums of this lane
+  int bpos[ICAP / SG], bcls[ICAP / SG];   // this lane's bonds j > i: slot and class (-1: none)
+#pragma unroll
+  for (int k = 0; k < ICAP / SG; ++k) {
+    bpos[k] = -1;
+    bcls[k] = 0;
+    if (k * SG >= mmax) continue;   // wave-uniform
+    int e = k * SG + sub;
+    bool ok = false;
+    int j = 0, p = 0;
+    double dx = 0, dy = 0, dz = 0, r = 0, w = 0, dw = 0;
+    if (live && e < m) {
+      j = D.in_e[i * ICAP + e];
+      double4 xj = D.x[j];
+      dx = xj.x - xi.x; dy = xj.y - xi.y; dz = xj.z - xi.z;
+      minimg(B, dx, dy, dz);
+      double r2 = dx * dx + dy * dy + dz * dz;
+      int sj = __double2int_rn(xj.w);
+      p = si + sj;
+      if (r2 < P.R2[p] * P.R2[p]) {
+        ok = true;
+        r = sqrt(r2);
+        w = cutw<double>(P, p, r, dw);
+        if (sj == 0) NC += w; else NH += w;
+      }
     }
-    ++cnt;
+    unsigned long long bal = __ballot(ok) & gmask;
+    if (ok) {
+      int pos = cnt + __popcll(bal & below);
+      if (pos < SCAP) {
+        D.sj[i * SCAP + pos] = j;
+        D.sd[i * SCAP + pos] = make_double4(dx, dy, dz, r);
+        D.sw[i * SCAP + pos] = make_double2(w, dw);
+        if (j > i) { bpos[k] = pos; bcls[k] = p; }
+      }
+    }
+    cnt += __popcll(bal);
   }
-  if (cnt > SCAP) atomicOr(D.flags, F_OV_SHORT);
-  D.sn[i] = min(cnt, SCAP);
-  D.NCt[i] = NC;
-  D.NHt[i] = NH;
+  for (int o = SG / 2; o > 0; o >>= 1) {
+    NC += __shfl_xor(NC, o);
+    NH += __shfl_xor(NH, o);
   }
-  // species-bucketed bond list: one atomic per wavefront and class
+  if (live && sub == 0) {
+    if (cnt > SCAP) atomicOr(D.flags, F_OV_SHORT);
+    D.sn[i] = min(cnt, SCAP);
+    D.NCt[i] = NC;
+    D.NHt[i] = NH;
+  }
+  // species-bucketed bond list: lane offsets by wave prefix sums, one LDS
+  // add per wavefront and class, one global reservation per block and class
+  // (same-address global atomics serialise: one per wavefront of 4 atoms
+  // cost more than the whole kernel)
+  __shared__ int s_cnt[3], s_base[3], s_max;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  int nb[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < ICAP / SG; ++k)
+    if (bpos[k] >= 0) nb[bcls[k]]++;
   int base[3];
-  for (int p = 0; p < 3; ++p) base[p] = wave_append(&D.bcount[p], nb[p] > 0, nb[p]);
-  if (live && (nb[0] | nb[1] | nb[2])) {
-    int si = __double2int_rn(D.x[i].w);
-    int n = D.sn[i];
-    for (int q = 0; q < n; ++q) {
-      int j = D.sj[i * SCAP + q];
-      if (j <= i) continue;
-      int p = si + __double2int_rn(D.x[j].w);
-      int b = base[p]++;
-      if (b < D.bcap) D.bonds[p * D.bcap + b] = make_int2(i, q);
-      else atomicOr(D.flags, F_OV_BOND);
+  for (int q = 0; q < 3; ++q) {
+    int incl = nb[q];
+    for (int o = 1; o < WAVE; o <<= 1) {
+      int u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
     }
+    int tot = __shfl(incl, WAVE - 1);
+    int wofs = 0;
+    if (lane == WAVE - 1 && tot) wofs = atomicAdd(&s_cnt[q], tot);
+    base[q] = __shfl(wofs, WAVE - 1) + incl - nb[q];
   }
-  int mx = wave_max(cnt);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && mx > 0) atomicMax(&D.stats[S_MAXSHORT], (unsigned long long)mx);
+  int mx = wave_max(cnt);   // largest short-list count, one global update per block
+  if (lane == 0 && mx > 0) atomicMax(&s_max, mx);
+  __syncthreads();
+  if (threadIdx.x < 3 && s_cnt[threadIdx.x] > 0) s_base[threadIdx.x] = atomicAdd(&D.bcount[threadIdx.x], s_cnt[threadIdx.x]);
+  if (threadIdx.x == 0 && s_max > 0) atomicMax(&D.stats[S_MAXSHORT], (unsigned long long)s_max);
+  __syncthreads();
+  for (int q = 0; q < 3; ++q) base[q] += s_base[q];
+#pragma unroll
+  for (int k = 0; k < ICAP / SG; ++k) {
+    if (bpos[k] < 0) continue;
+    int q = bcls[k];
+    int b = base[q]++;
+    if (b < D.bcap) D.bonds[q * D.bcap + b] = make_int2(i, bpos[k]);
+    else atomicOr(D.flags, F_OV_BOND);
+  }
 }
 
 // Atoms and bond slots along a path code starting at atom i.
@@ -1702,8 +1757,10 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
   if (o.term_mask < 0 || o.term_mask > 7) return fail(AIREBO_E_ARG, "bad term mask");
   if (o.lj_cap < 0) return fail(AIREBO_E_ARG, "bad lj_cap");
   auto okb = [](int b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; };
-  if (!okb(o.bond_block) || !okb(o.defer_block) || !okb(o.short_block) || o.bond_grid < 0)
-    return fail(AIREBO_E_ARG, "launch shapes must be 0 or 64, 128, 192, 256 threads");
+  auto oks = [](int b) { return b == 0 || b == 256 || b == 512 || b == 1024; };
+  if (!okb(o.bond_block) || !okb(o.defer_block) || !oks(o.short_block) || o.bond_grid < 0)
+    return fail(AIREBO_E_ARG, "launch shapes: bond and deferred blocks 0 or 64, 128, 192, 256 threads; "
+                              "short-list block 0 or 256, 512, 1024 threads");
   airebo_ctx* c = new airebo_ctx();
   c->opt = o;
   std::vector<double> tri((size_t)TRI_N * kTriCells * kTriCoef);
@@ -1868,8 +1925,8 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
          dim3(std::min(std::max({blocks(3 * (int64_t)D.n, 256), NSLOT * A_N / 256, blocks((int64_t)D.nsys * A_N, 256)}),
                        4096)),
          dim3(256), s, D);
-  int sblk = c->opt.short_block ? c->opt.short_block : 128;
-  LAUNCH(c, K_SHORT, k_short, dim3(blocks(D.n, sblk)), dim3(sblk), s, D, P);
+  int sblk = c->opt.short_block ? c->opt.short_block : 1024;
+  LAUNCH(c, K_SHORT, k_short, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), s, D, P);   // 16 lanes per atom
   int bblk = c->opt.bond_block ? c->opt.bond_block : 64;
   int nb = c->opt.bond_grid ? c->opt.bond_grid : std::min(blocks((int64_t)D.n * 2, bblk), 8192);
   int qblk = c->opt.defer_block ? c->opt.defer_block : 64;
