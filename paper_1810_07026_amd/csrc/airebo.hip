@@ -767,18 +767,20 @@ __global__ void k_fill(Dev D) {
 
 // One wavefront per atom: full LJ list (cutoff + skin, with image shift code)
 // and intermediate REBO list (R2 + skin), compacted with wave ballots.
-// The candidates of the 27 neighbour cells form one stream (each lane finds
-// its cell by a binary search over the per-cell prefix counts in LDS); the
-// atom index and FP32 position of the next block of 64 candidates are
-// loaded while this block is tested.  The FP32 test uses cutoffs enlarged by
-// 1e-3 A, far above its rounding error (~1e-4 A at 500 A coordinates), so
-// both lists contain every pair within the exact cutoffs; every consumer
-// tests distances again in FP64.
+// Cells are at least half the list cutoff, so the 5 x 5 x 5 cells around
+// the atom's own hold every candidate.  Their candidates form one stream
+// (each lane finds its cell by a binary search over the per-cell prefix
+// counts in LDS); the atom index and FP32 position of the next block of 64
+// candidates are loaded while this block is tested.  The FP32 test uses
+// cutoffs enlarged by 1e-3 A, far above its rounding error (~1e-4 A at 500 A
+// coordinates), so both lists contain every pair within the exact cutoffs;
+// every consumer tests distances again in FP64.
+constexpr int NSTEN = 125;   // cells of the stencil
 __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restrict__ Pp) {
   if (!(*D.flags & F_REBUILD)) return;
-  __shared__ int s_pre[4][28];        // first stream index of each cell (28th: total)
-  __shared__ int s_start[4][27];      // first slot of the cell in the cell-ordered arrays
-  __shared__ unsigned s_code[4][27];  // image shift code of the cell
+  __shared__ int s_pre[4][NSTEN + 1];       // first stream index of each cell (last: total)
+  __shared__ int s_start[4][NSTEN];         // first slot of the cell in the cell-ordered arrays
+  __shared__ unsigned s_code[4][NSTEN];     // image shift code of the cell
   int lane = threadIdx.x & (WAVE - 1);
   int wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
@@ -786,46 +788,51 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
   double4 xi = D.x[i];
   int si = __double2int_rn(xi.w);
   const SysBox& B = box_of(D, i);
-  int cnt = 0, start = 0;
-  unsigned code = 13;
-  if (lane < 27) {
-    int ci[3] = {cell_coord(xi.x, B.invL[0], B.nc[0]), cell_coord(xi.y, B.invL[1], B.nc[1]),
-                 cell_coord(xi.z, B.invL[2], B.nc[2])};
-    int off[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
-    int cc[3], sh[3];
-    bool skip = false;
-    for (int c = 0; c < 3; ++c) {
-      int t = ci[c] + off[c];
-      if (B.per[c]) {
-        sh[c] = t < 0 ? -1 : (t >= B.nc[c] ? 1 : 0);
-        cc[c] = t - sh[c] * B.nc[c];
-        if (cc[c] < 0 || cc[c] >= B.nc[c]) skip = true;   // nc == 1 wraps once only
-      } else {
-        sh[c] = 0;
-        cc[c] = t;
-        if (t < 0 || t >= B.nc[c]) skip = true;
+  int ci[3] = {cell_coord(xi.x, B.invL[0], B.nc[0]), cell_coord(xi.y, B.invL[1], B.nc[1]),
+               cell_coord(xi.z, B.invL[2], B.nc[2])};
+  int run = 0;   // candidates of the cells before this group of 64
+  for (int o0 = 0; o0 < NSTEN; o0 += WAVE) {
+    int o = o0 + lane;
+    int cnt = 0, start = 0;
+    unsigned code = 13;
+    if (o < NSTEN) {
+      int off[3] = {o / 25 - 2, (o / 5) % 5 - 2, o % 5 - 2};
+      int cc[3], sh[3];
+      bool skip = false;
+      for (int c = 0; c < 3; ++c) {
+        int u = ci[c] + off[c];
+        if (B.per[c]) {
+          sh[c] = u < 0 ? -1 : (u >= B.nc[c] ? 1 : 0);
+          cc[c] = u - sh[c] * B.nc[c];
+          if (cc[c] < 0 || cc[c] >= B.nc[c]) skip = true;   // small grids wrap once only
+        } else {
+          sh[c] = 0;
+          cc[c] = u;
+          if (u < 0 || u >= B.nc[c]) skip = true;
+        }
+      }
+      code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
+      if (!skip) {
+        int cell = B.cell_off + (cc[0] * B.nc[1] + cc[1]) * B.nc[2] + cc[2];
+        start = D.cell_start[cell];
+        cnt = D.cell_start[cell + 1] - start;
       }
     }
-    code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
-    if (!skip) {
-      int cell = B.cell_off + (cc[0] * B.nc[1] + cc[1]) * B.nc[2] + cc[2];
-      start = D.cell_start[cell];
-      cnt = D.cell_start[cell + 1] - start;
+    int incl = cnt;
+    for (int q = 1; q < WAVE; q <<= 1) {
+      int u = __shfl_up(incl, q);
+      if (lane >= q) incl += u;
     }
+    if (o < NSTEN) { s_pre[wv][o] = run + incl - cnt; s_start[wv][o] = start; s_code[wv][o] = code; }
+    run += __shfl(incl, WAVE - 1);
   }
-  int incl = cnt;
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
-  }
-  if (lane < 27) { s_pre[wv][lane] = incl - cnt; s_start[wv][lane] = start; s_code[wv][lane] = code; }
-  if (lane == 27) s_pre[wv][27] = incl;   // lanes >= 27 add nothing: the total
-  int total = __shfl(incl, 27);
+  if (lane == 0) s_pre[wv][NSTEN] = run;
+  int total = run;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   // stream position v -> slot in the cell-ordered arrays and shift code
   auto locate = [&](int v, int& slot, unsigned& cd) {
-    int lo = 0, hi = 27;   // s_pre[lo] <= v < s_pre[hi]
+    int lo = 0, hi = NSTEN;   // s_pre[lo] <= v < s_pre[hi]
     while (hi - lo > 1) {
       int mid = (lo + hi) >> 1;
       if (s_pre[wv][mid] <= v) lo = mid; else hi = mid;
@@ -1832,7 +1839,7 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
       B.per[d] = pers[3 * k + d] ? 1 : 0;
       if (B.per[d] && L < std::max({12.0, P.rc_max + c->opt.skin}))
         return fail(AIREBO_E_BOX, "periodic box side must be at least max(12 A, LJ cutoff + skin)");
-      B.nc[d] = std::min(std::max(1, (int)std::floor(L / rlist)), 1024);
+      B.nc[d] = std::min(std::max(1, (int)std::floor(L / (0.5 * rlist))), 1024);   // cells >= half the list cutoff
       nc_k *= B.nc[d];
     }
     B.cell_off = (int)ncell;
