@@ -1197,6 +1197,31 @@ __device__ __forceinline__ int flush_deferred(const Dev& D, int4* buf, int n) {
   return 0;
 }
 
+// The same LJ pair term from r^2, for plain pairs: energy V and
+// G = (dV/dr) / r.  One division (1 / r^2); the square root is taken only
+// inside the outer switching shell (rc - lj_sw < r < rc).
+template <typename R>
+__device__ __forceinline__ void lj_pair_r2(const DevParams& P, int p, R r2, R& V, R& G) {
+  R ir2 = (R)1 / r2;
+  R sg = (R)P.sigma[p];
+  R s2 = sg * sg * ir2;
+  R s6 = s2 * s2 * s2;
+  R e4 = (R)(4.0 * P.eps[p]);
+  R v = e4 * (s6 * s6 - s6);
+  R gv = e4 * ((R)-12 * s6 * s6 + (R)6 * s6) * ir2;
+  R r0 = (R)(P.rc[p] - P.lj_sw);
+  if (r2 > r0 * r0) {
+    R r = sqrt(r2);
+    R isw = (R)(1.0 / P.lj_sw), dS;
+    R S = Sw((r - r0) * isw, dS);
+    V = v * S;
+    G = gv * S + v * dS * isw / r;
+  } else {
+    V = v;
+    G = gv;
+  }
+}
+
 // LJ term (Alg. 3), one wavefront per atom over its full list.
 //
 // The wavefront first maps every atom reachable from i over at most three
@@ -1344,10 +1369,9 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
         double r2 = dx * dx + dy * dy + dz * dz;
         int p = si + __double2int_rn(xj.w);
         if (r2 < P.rc2[p]) {
-          double r = sqrt(r2);
           if (i < j) ++n_in;
           bool plain = true;
-          if (r < P.r_conn) {
+          if (r2 < P.r_conn * P.r_conn) {
             double prod = 0.0;
             int h = hslot(j);
             for (int probe = 0; probe < HCAP; ++probe) {
@@ -1364,21 +1388,21 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
             if (prod >= 1.0) {
               if (i < j) ++n_c0;
               plain = false;
-            } else if (prod > 0.0 || r < P.rljmax[p]) {
+            } else if (prod > 0.0 || r2 < P.rljmax[p] * P.rljmax[p]) {
               push = i < j;
               plain = false;
             }
           }
           if (plain) {
-            // pair arithmetic in R on the FP64 relative vector; FP64 accumulation
-            R rr = (R)r, V, dV;
-            lj_pair<R>(P, p, rr, V, dV);
-            e += 0.5 * (double)V;
-            R g = dV / rr;    // dE/dr_ij vector = g * d
+            // pair arithmetic in R on the FP64 relative vector; FP64
+            // accumulation (energy and virial halved once, at the end)
+            R V, g;
+            lj_pair_r2<R>(P, p, (R)r2, V, g);   // dE/dr_ij vector = g * d
+            e += (double)V;
             R fx = g * (R)dx, fy = g * (R)dy, fz = g * (R)dz;
             fi[0] += (double)fx; fi[1] += (double)fy; fi[2] += (double)fz;
-            W[0] -= 0.5 * (double)(fx * (R)dx); W[1] -= 0.5 * (double)(fy * (R)dy); W[2] -= 0.5 * (double)(fz * (R)dz);
-            W[3] -= 0.5 * (double)(fy * (R)dx); W[4] -= 0.5 * (double)(fz * (R)dx); W[5] -= 0.5 * (double)(fz * (R)dy);
+            W[0] += (double)(fx * (R)dx); W[1] += (double)(fy * (R)dy); W[2] += (double)(fz * (R)dz);
+            W[3] += (double)(fy * (R)dx); W[4] += (double)(fz * (R)dx); W[5] += (double)(fz * (R)dy);
           }
         }
       }
@@ -1397,7 +1421,9 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
     for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0 && i < D.n && s != 0) atomic_add(&D.F[3 * i + c], s);
   }
-  double v9[9] = {e, W[0], W[1], W[2], W[3], W[4], W[5], (double)n_in, (double)n_c0};
+  // each pair is seen from both ends: half the energy, minus half the virial
+  double v9[9] = {0.5 * e, -0.5 * W[0], -0.5 * W[1], -0.5 * W[2], -0.5 * W[3], -0.5 * W[4], -0.5 * W[5],
+                  (double)n_in, (double)n_c0};
   if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v9, A_ELJ, i < D.n);
   block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
 }
