@@ -1,0 +1,89 @@
+"""Parity at the benchmarked sizes, in the launch configuration bench.py times.
+
+* The 32,012-atom polyethylene melt (106 x C100H202, the headline workload):
+  GPU energy, every force and the virial against one full oracle evaluation,
+  FP64 at the FP64 bar and mixed precision at its own bar.
+* The 512-system batch (301,512 atoms) with the launch shapes the autotuner
+  cached for it: the smallest and the largest system of each family,
+  taken whole from the batched result, against the oracle on that system
+  alone, FP64 and mixed.
+
+Bars: the FP64 bar of the parity tests (energy 1e-12 relative, max force
+error 1e-10 of the RMS force, virial 1e-10 relative; only summation order
+and last-bit differences of the math libraries separate the two sides) and
+the mixed bar derived there (force 1e-4 of the RMS force, energy 1e-6).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1810_07026_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_E, TOL_F, TOL_W = 1e-12, 1e-10, 1e-10
+TOL_MIXED_F, TOL_MIXED_E = 1e-4, 1e-6
+
+
+def check(e, f, w, eo, fo, wo, fp64, label):
+    rms = math.sqrt((fo ** 2).sum(1).mean())
+    ferr = np.abs(f - fo).max() / rms
+    if fp64:
+        assert ferr <= TOL_F, (label, ferr)
+        for t in range(4):
+            assert abs(e[t] - eo[t]) <= TOL_E * max(abs(eo[t]), 1e-3 * abs(eo[0]), 1.0), (label, t, e, eo)
+        assert np.linalg.norm(w - wo) <= TOL_W * np.linalg.norm(wo) + 1e-12, (label, w, wo)
+    else:
+        assert ferr <= TOL_MIXED_F, (label, ferr)
+        assert abs(e[0] - eo[0]) <= TOL_MIXED_E * max(abs(eo[0]), 1.0), (label, e[0], eo[0])
+    return ferr
+
+
+@pytest.fixture(scope="module")
+def melt(oracle):
+    d = synth.pe_melt()
+    return d, oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_melt_32k_full(melt, prec):
+    from paper_1810_07026_amd import airebo
+    d, (eo, fo, wo) = melt
+    assert len(d["species"]) == 32012
+    ctx = airebo.Context(precision=airebo.FP64 if prec == "fp64" else airebo.MIXED)
+    try:
+        e, f, w = ctx.compute(d["x"], d["species"], d["box"], d["periodic"])
+        e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
+    finally:
+        ctx.close()
+    ferr = check(e, f, w, eo, fo, wo, prec == "fp64", f"melt {prec}")
+    print(f"melt 32k {prec}: max force error / RMS force {ferr:.3g}")
+    # Newton's third law over the whole periodic system
+    assert np.abs(f.sum(0)).max() <= 1e-9 * np.abs(f).sum()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_512_full(oracle, prec):
+    import torch
+    from paper_1810_07026_amd import airebo, autotune
+    d = synth.batch_cached(512)
+    n = int(d["sizes"].sum())
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    tune = autotune.lookup(autotune.workload_key(arch, n, 512, "mixed")) or {}
+    ctx = airebo.Context(precision=airebo.FP64 if prec == "fp64" else airebo.MIXED, tune=tune)
+    try:
+        e, f, w = ctx.batch_compute(d["x"], d["species"], d["sizes"], d["boxes"], d["periodic"])
+        e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
+    finally:
+        ctx.close()
+    off = np.concatenate([[0], np.cumsum(d["sizes"])])
+    for fam in range(len(synth.FAMILIES)):
+        ks = [k for k in range(512) if k % len(synth.FAMILIES) == fam]
+        # the smallest and the largest system of the family
+        for k in (min(ks, key=lambda q: d["sizes"][q]), max(ks, key=lambda q: d["sizes"][q])):
+            a, b = off[k], off[k + 1]
+            eo, fo, wo = oracle.compute(d["x"][a:b], d["species"][a:b], d["boxes"][k], d["periodic"][k])
+            ferr = check(e[k], f[a:b], w[k], eo, fo, wo, prec == "fp64", f"batch {prec} system {k}")
+            print(f"batch {prec} system {k} ({synth.FAMILIES[fam]}, {b - a} atoms): "
+                  f"max force error / RMS {ferr:.3g}")
