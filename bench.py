@@ -70,7 +70,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU; runs on several GPUs are not supported",
                           "n_gpus": max(args.gpus, world)}))
         sys.exit(2)
 

@@ -159,7 +159,7 @@ const char* airebo_kernel_name(int k);
 /* ------------------------------------------------------------------------
  * Learned surrogate.  Not part of the paper: an approximation of the
  * potential above (Sec. 2.1) by per-atom networks, with that potential as
- * its fallback and as the judge of its error.
+ * its fallback and as the reference for its error.
  *
  *   E = sum_i E_NN(G_i; s_i) + E_far
  *

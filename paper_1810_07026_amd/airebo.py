@@ -53,7 +53,7 @@ def load_library(path=LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise AireboError(-1, f"{path} is not built; run __graft_entry__.build()")
+        raise AireboError(-1, f"{path} is not built; run python -m paper_1810_07026_amd.build")
     L = ctypes.CDLL(path)
     vp, dp, ip = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p
     L.airebo_options_default.argtypes = [ctypes.POINTER(Options)]
