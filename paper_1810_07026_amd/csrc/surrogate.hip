@@ -345,8 +345,10 @@ __global__ __launch_bounds__(256) void k_desc(Dev D, float* __restrict__ out, co
 // The centre's own force is a wavefront sum.
 // With FAR, the same pass over the LJ list evaluates the far-field term into
 // Ff [n][3] and acc.
-// One wavefront per block: the centre atom is wave-uniform, so its dE/dG rows
-// are read with scalar loads (no LDS staging).
+// One wavefront per block.  The centre's dE/dG rows are staged in LDS: the
+// angular and radial terms index them by the species of the pair or the
+// neighbour, which differs between lanes (a per-lane select of global
+// addresses made every pair wait on its own loads: ~2/3 of the kernel).
 template <bool FAR>
 __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __restrict__ Pp, const float* __restrict__ g,
                                                      int nm, float* __restrict__ F, double* __restrict__ Ff,
@@ -354,15 +356,17 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
   __shared__ NbList nb;
   __shared__ float pdu[NM_MAX][3][WAVE];   // dE/du_a of each pair of the current block of pairs
   __shared__ float pdv[NM_MAX][3][WAVE];   // dE/du_b
+  __shared__ float gc[NM_MAX][DIM];        // the centre's dE/dG rows (read with per-lane indices)
   int lane = threadIdx.x;
   const int i = blockIdx.x;
   if (i >= D.n) return;
   float W[6] = {0, 0, 0, 0, 0, 0};
   FarAcc far = {0, {0, 0, 0}, {0, 0, 0, 0, 0, 0}};
-  stage_nb(D, i, nb, Pp, FAR ? &far : nullptr);
-  const float inm = 1.0f / nm;
   const size_t mstride = (size_t)D.n * DIM;
   const float* gi = g + (size_t)i * DIM;   // row of model m: gi + m * mstride
+  for (int k = lane; k < nm * DIM; k += WAVE) gc[k / DIM][k % DIM] = gi[(k / DIM) * mstride + k % DIM];
+  stage_nb(D, i, nb, Pp, FAR ? &far : nullptr);   // ends with a wavefront barrier
+  const float inm = 1.0f / nm;
   float fi[NM_MAX][3] = {};
   float lf[NM_MAX][3] = {};   // force on leg `lane` (lane < na)
   int na = nb.na, npair = na * (na - 1) / 2;
@@ -383,13 +387,13 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
 #pragma unroll
       for (int m = 0; m < NM_MAX; ++m)
         if (m < nm) {
-          const float* ga = gi + m * mstride + 2 * NRAD;
+          const float* ga = &gc[m][2 * NRAD + t * NANG];   // LDS, indexed by the pair's species sum
           float S1 = 0, S20 = 0, S21 = 0;
 #pragma unroll
           for (int c = 0; c < NANG; ++c) {
-            float gc = t == 0 ? ga[c] : (t == 1 ? ga[NANG + c] : ga[2 * NANG + c]);
-            S1 += gc * Q.w1[c];
-            if (c & 1) S21 += gc * Q.w2[c]; else S20 += gc * Q.w2[c];
+            float gv = ga[c];
+            S1 += gv * Q.w1[c];
+            if (c & 1) S21 += gv * Q.w2[c]; else S20 += gv * Q.w2[c];
           }
           float Ac = fa * fb * S1;
           float Ba = fb * (ha0 * S20 + ha1 * S21) * ra;
@@ -471,7 +475,7 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
 #pragma unroll
     for (int m = 0; m < NM_MAX; ++m)
       if (m < nm) {
-        const float* gm = gi + m * mstride;                                     // centre, scalar loads
+        const float* gm = &gc[m][sp * NRAD];                                    // centre, LDS
         const float* gj = g + m * mstride + (size_t)j * DIM + si * NRAD;       // neighbour, vector loads
         float de = 0;
 #pragma unroll
@@ -480,7 +484,7 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             int kk = 4 * k4 + k;
-            float own = sp ? gm[NRAD + kk] : gm[kk];
+            float own = gm[kk];
             float oth = k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
             de += (own + oth) * dg[kk];
           }
