@@ -354,8 +354,6 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
                                                      int nm, float* __restrict__ F, double* __restrict__ Ff,
                                                      double* __restrict__ acc) {
   __shared__ NbList nb;
-  __shared__ float pdu[NM_MAX][3][WAVE];   // dE/du_a of each pair of the current block of pairs
-  __shared__ float pdv[NM_MAX][3][WAVE];   // dE/du_b
   __shared__ float gc[NM_MAX][DIM];        // the centre's dE/dG rows (read with per-lane indices)
   int lane = threadIdx.x;
   const int i = blockIdx.x;
@@ -371,22 +369,38 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
   float lf[NM_MAX][3] = {};   // force on leg `lane` (lane < na)
   int na = nb.na, npair = na * (na - 1) / 2;
   auto start = [&](int q) { return q * na - q * (q + 1) / 2; };
-  // ---- angular: lane per pair, then lane per leg
+  // ---- angular: lane per pair (a, b), a < b, in blocks of 64 pairs.  The
+  // pairs of one row a are consecutive lanes: a segmented scan leaves the
+  // row's sum of -dE/du_a in its last lane, which leg lane a reads; each row
+  // of the block holds at most one pair (r, b) for a given b, read by leg
+  // lane b.  All in registers (shuffles), one set at a time.
   for (int base = 0; base < npair; base += WAVE) {
     int p = base + lane;
-    if (p < npair) {
-      int a, b;
-      tri_decode(p, na, a, b);
-      int t = nb.as[a] + nb.as[b];
-      PairAng Q;
-      pair_ang(nb, a, b, Q);
-      float fa = nb.afc[a], fb = nb.afc[b], ra = nb.ar[a], rb = nb.ar[b];
-      float ira = frcp(ra), irb = frcp(rb);
-      float uax = nb.ux[a], uay = nb.uy[a], uaz = nb.uz[a], ubx = nb.ux[b], uby = nb.uy[b], ubz = nb.uz[b];
-      float ha0 = nb.ah0[a], ha1 = nb.ah1[a], hb0 = nb.ah0[b], hb1 = nb.ah1[b];
+    bool live = p < npair;
+    int a = 0, b = 1;
+    if (live) tri_decode(p, na, a, b);
+    PairAng Q;
+    pair_ang(nb, a, b, Q);   // in range for every lane (a < b < na), used only when live
+    int t = nb.as[a] + nb.as[b];
+    float fa = nb.afc[a], fb = nb.afc[b], ra = nb.ar[a], rb = nb.ar[b];
+    float ira = frcp(ra), irb = frcp(rb);
+    float uax = nb.ux[a], uay = nb.uy[a], uaz = nb.uz[a], ubx = nb.ux[b], uby = nb.uy[b], ubz = nb.uz[b];
+    float ha0 = nb.ah0[a], ha1 = nb.ah1[a], hb0 = nb.ah0[b], hb1 = nb.ah1[b];
+    // block-uniform layout: first lane of this lane's row segment; for leg
+    // lane `lane`, the last lane of its row in the block; the rows present
+    int seg0 = live ? max(start(a), base) - base : lane;
+    int rs = start(lane);
+    int rlo = max(rs, base), rhi = min(rs + na - 1 - lane, min(base + WAVE, npair));
+    bool has_row = lane < na - 1 && rhi > rlo;
+    int row_src = has_row ? rhi - 1 - base : lane;
+    int r_first, r_last, dummy;
+    tri_decode(base, na, r_first, dummy);
+    tri_decode(min(base + WAVE, npair) - 1, na, r_last, dummy);
 #pragma unroll
-      for (int m = 0; m < NM_MAX; ++m)
-        if (m < nm) {
+    for (int m = 0; m < NM_MAX; ++m)
+      if (m < nm) {
+        float gux = 0, guy = 0, guz = 0, gvx = 0, gvy = 0, gvz = 0;
+        if (live) {
           const float* ga = &gc[m][2 * NRAD + t * NANG];   // LDS, indexed by the pair's species sum
           float S1 = 0, S20 = 0, S21 = 0;
 #pragma unroll
@@ -400,15 +414,13 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
           float Bb = fa * (hb0 * S20 + hb1 * S21) * rb;
           // dE/du_a and dE/du_b (u = vector from the centre to the neighbour)
           float ca = Ac * ira, cb = Ac * irb;
-          float gux = ca * (ubx - Q.cs * uax) + Ba * uax;
-          float guy = ca * (uby - Q.cs * uay) + Ba * uay;
-          float guz = ca * (ubz - Q.cs * uaz) + Ba * uaz;
-          float gvx = cb * (uax - Q.cs * ubx) + Bb * ubx;
-          float gvy = cb * (uay - Q.cs * uby) + Bb * uby;
-          float gvz = cb * (uaz - Q.cs * ubz) + Bb * ubz;
+          gux = ca * (ubx - Q.cs * uax) + Ba * uax;
+          guy = ca * (uby - Q.cs * uay) + Ba * uay;
+          guz = ca * (ubz - Q.cs * uaz) + Ba * uaz;
+          gvx = cb * (uax - Q.cs * ubx) + Bb * ubx;
+          gvy = cb * (uay - Q.cs * uby) + Bb * uby;
+          gvz = cb * (uaz - Q.cs * ubz) + Bb * ubz;
           fi[m][0] += gux + gvx; fi[m][1] += guy + gvy; fi[m][2] += guz + gvz;
-          pdu[m][0][lane] = -gux; pdu[m][1][lane] = -guy; pdu[m][2][lane] = -guz;
-          pdv[m][0][lane] = -gvx; pdv[m][1][lane] = -gvy; pdv[m][2][lane] = -gvz;
           W[0] -= inm * (ra * uax * gux + rb * ubx * gvx);
           W[1] -= inm * (ra * uay * guy + rb * uby * gvy);
           W[2] -= inm * (ra * uaz * guz + rb * ubz * gvz);
@@ -416,34 +428,25 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
           W[4] -= inm * (ra * uax * guz + rb * ubx * gvz);
           W[5] -= inm * (ra * uay * guz + rb * uby * gvz);
         }
-    }
-    wave_sync();
-    if (lane < na) {
-      // pairs (lane, b): contiguous slots of row `lane`
-      int a = lane;
-      int s0 = start(a);
-      int lo = max(s0, base), hi = min(s0 + na - 1 - a, min(base + WAVE, npair));
-      for (int q = lo; q < hi; ++q)
-#pragma unroll
-        for (int m = 0; m < NM_MAX; ++m)
-          if (m < nm) {
-            lf[m][0] += pdu[m][0][q - base]; lf[m][1] += pdu[m][1][q - base]; lf[m][2] += pdu[m][2][q - base];
-          }
-      // pairs (r, lane), r < lane: one slot in each row r
-      int ra_, rb_, re_, rf_;
-      tri_decode(base, na, ra_, rb_);
-      tri_decode(min(base + WAVE, npair) - 1, na, re_, rf_);
-      for (int r = ra_; r <= re_ && r < a; ++r) {
-        int q = start(r) + a - r - 1;
-        if (q >= base && q < base + WAVE && q < npair)
-#pragma unroll
-          for (int m = 0; m < NM_MAX; ++m)
-            if (m < nm) {
-              lf[m][0] += pdv[m][0][q - base]; lf[m][1] += pdv[m][1][q - base]; lf[m][2] += pdv[m][2][q - base];
-            }
+        // row sums of -dE/du_a: segmented inclusive scan
+        float sx = -gux, sy = -guy, sz = -guz;
+        for (int o = 1; o < WAVE; o <<= 1) {
+          float tx = __shfl_up(sx, o), ty = __shfl_up(sy, o), tz = __shfl_up(sz, o);
+          if (lane - o >= seg0) { sx += tx; sy += ty; sz += tz; }
+        }
+        {
+          float tx = __shfl(sx, row_src), ty = __shfl(sy, row_src), tz = __shfl(sz, row_src);
+          if (has_row) { lf[m][0] += tx; lf[m][1] += ty; lf[m][2] += tz; }
+        }
+        // column terms -dE/du_b: pair (r, lane) of each row r in the block
+        for (int r = r_first; r <= r_last; ++r) {
+          int q = start(r) + lane - r - 1;
+          bool ok = lane < na && lane > r && q >= base && q < base + WAVE && q < npair;
+          int src = ok ? q - base : lane;
+          float tx = __shfl(-gvx, src), ty = __shfl(-gvy, src), tz = __shfl(-gvz, src);
+          if (ok) { lf[m][0] += tx; lf[m][1] += ty; lf[m][2] += tz; }
+        }
       }
-    }
-    wave_sync();
   }
   // angular legs: force on each leg atom, one atomic per component and set
   if (lane < na) {
