@@ -10,7 +10,7 @@
 //
 // GPU design (one process, one device; everything stays in HBM):
 //   rebuild (when any atom moved more than half the skin):
-//     k_bin / k_scan / k_fill   counting sort of atoms into cells >= LJ cutoff + skin
+//     k_bin / k_scan / k_fill   counting sort of atoms into cells >= half of LJ cutoff + skin
 //     k_build                    one wavefront per atom: full LJ list (with image
 //                                shift codes) and the intermediate REBO list
 //                                (R2 + skin), both filled by wave-ballot compaction
