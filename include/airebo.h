@@ -51,6 +51,7 @@ enum { AIREBO_FP64 = 0, AIREBO_MIXED = 1 };
 enum { AIREBO_TERM_REBO = 1, AIREBO_TERM_LJ = 2, AIREBO_TERM_TORSION = 4, AIREBO_TERM_ALL = 7 };
 
 typedef struct airebo_ctx* airebo_ctx_t;
+typedef struct airebo_params_set* airebo_params_t;
 
 /* Run-time options.  Zero-initialise, then set what differs from the
  * defaults; airebo_options_default() fills the defaults. */
@@ -78,6 +79,23 @@ void airebo_options_default(airebo_options* opt);
 int airebo_ctx_create(const char* param_path, const airebo_options* opt, airebo_ctx_t* out);
 void airebo_ctx_free(airebo_ctx_t ctx);
 
+/* A validated parameter set held by the caller (the model of Sec. 2.1:
+ * every scalar and knot table of the parameter file), for contexts created
+ * without reading a file.
+ *   airebo_params_load   reads and validates a parameter file
+ *   airebo_params_parse  the same from the file's text in memory: text of
+ *                        len bytes, host, read only during the call
+ *   airebo_params_free   releases a set (NULL is accepted)
+ *   airebo_ctx_create_from_params
+ *                        a context from a set; the set is copied, so it
+ *                        may be freed afterwards
+ * Errors: AIREBO_E_ARG, AIREBO_E_PARAMS (with the failing record in the
+ * message), AIREBO_E_DEVICE. */
+int airebo_params_load(const char* param_path, airebo_params_t* out);
+int airebo_params_parse(const char* text, size_t len, airebo_params_t* out);
+void airebo_params_free(airebo_params_t params);
+int airebo_ctx_create_from_params(airebo_params_t params, const airebo_options* opt, airebo_ctx_t* out);
+
 /* Energy, forces and virial of one configuration (Sec. 2.1, Alg. 1-3).
  *   n        number of atoms (>= 0)
  *   pos      device [n][3] positions in A; any values (wrapped internally)
@@ -94,6 +112,14 @@ void airebo_ctx_free(airebo_ctx_t ctx);
  * AIREBO_E_DEVICE. */
 int airebo_compute(airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species, const double* box,
                    const int32_t* periodic, double* energy, double* forces, double* virial, void* stream);
+
+/* airebo_compute with host pointers: pos [n][3], species [n], energy [4],
+ * forces [n][3] and virial [6] all in host memory.  The inputs are copied to
+ * device buffers held by the context, the outputs back; the call returns
+ * when they are written (synchronous, on the null stream).  Errors as for
+ * airebo_compute. */
+int airebo_compute_host(airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species, const double* box,
+                        const int32_t* periodic, double* energy, double* forces, double* virial);
 
 /* Velocity-Verlet NVE (Sec. 2): nsteps steps of length dt_fs, updating pos
  * and vel (device [n][3], A and A/fs) in place; positions are wrapped into the
@@ -255,6 +281,13 @@ int airebo_nn_gradient(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double
                        double w_energy, double* loss, void* stream);
 /* One Adam step (bias-corrected) on every weight with the last gradient. */
 int airebo_nn_adam(airebo_nn_t nn, double lr, double beta1, double beta2, double eps, void* stream);
+/* One training step: airebo_nn_gradient on one labelled configuration,
+ * then airebo_nn_adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and
+ * learning rate lr.  loss[nmodels] (host) is the loss before the update.
+ * Synchronous. */
+int airebo_nn_train_step(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const int32_t* species,
+                         const double* box, const int32_t* periodic, const double* f_ref, double e_ref,
+                         double w_force, double w_energy, double lr, double* loss, void* stream);
 /* Velocity Verlet with surrogate forces.  Arguments are as for airebo_nve,
  * plus the fallback threshold (see airebo_nn_compute), which is checked every
  * step on the device.  *fallbacks (host, optional) returns the number of

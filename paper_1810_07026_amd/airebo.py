@@ -26,7 +26,9 @@ EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "ai
            "airebo_nn_get_params", "airebo_nn_get_grad", "airebo_nn_set_norm", "airebo_nn_get_norm",
            "airebo_nn_moments", "airebo_nn_descriptors", "airebo_nn_descriptor_jvp", "airebo_nn_descriptor_vjp",
            "airebo_nn_compute", "airebo_nn_gradient", "airebo_nn_adam", "airebo_nn_nve", "airebo_nn_profile_nve",
-           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check"]
+           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check",
+           "airebo_params_load", "airebo_params_parse", "airebo_params_free", "airebo_ctx_create_from_params",
+           "airebo_compute_host", "airebo_nn_train_step"]
 
 
 class AireboError(RuntimeError):
@@ -60,6 +62,18 @@ def load_library(path=LIB_PATH):
     L.airebo_options_default.restype = None
     L.airebo_ctx_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]
     L.airebo_ctx_create.restype = ctypes.c_int
+    L.airebo_params_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.airebo_params_load.restype = ctypes.c_int
+    L.airebo_params_parse.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]
+    L.airebo_params_parse.restype = ctypes.c_int
+    L.airebo_params_free.argtypes = [vp]
+    L.airebo_params_free.restype = None
+    L.airebo_ctx_create_from_params.argtypes = [vp, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]
+    L.airebo_ctx_create_from_params.restype = ctypes.c_int
+    hdp = ctypes.POINTER(ctypes.c_double)
+    L.airebo_compute_host.argtypes = [vp, ctypes.c_int64, hdp, ctypes.POINTER(ctypes.c_int32), hdp,
+                                      ctypes.POINTER(ctypes.c_int32), hdp, hdp, hdp]
+    L.airebo_compute_host.restype = ctypes.c_int
     L.airebo_ctx_free.argtypes = [vp]
     L.airebo_ctx_free.restype = None
     L.airebo_compute.argtypes = [vp, ctypes.c_int64, dp, ip, ctypes.POINTER(ctypes.c_double),
@@ -108,6 +122,7 @@ def load_library(path=LIB_PATH):
         "airebo_nn_compute": geo + [c_d, dp, dp, dp, dp, hd, vp],
         "airebo_nn_gradient": geo + [dp, c_d, c_d, c_d, hd, vp],
         "airebo_nn_adam": [vp, c_d, c_d, c_d, c_d, vp],
+        "airebo_nn_train_step": geo + [dp, c_d, c_d, c_d, c_d, hd, vp],
         "airebo_nn_nve": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_i64, c_i64, dp, c_d,
                           ctypes.POINTER(ctypes.c_int64), vp],
         "airebo_nn_profile_nve": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_i64, c_d,
@@ -136,8 +151,31 @@ def _host3(a, ctype):
     return arr
 
 
+class ParamSet:
+    """A validated AIREBO parameter set held on the host (airebo_params_*):
+    from a file path, or from the file's text with text=..."""
+
+    def __init__(self, path=DEFAULT_PARAMS, text=None):
+        self.L = load_library()
+        h = ctypes.c_void_p()
+        if text is not None:
+            b = text.encode() if isinstance(text, str) else bytes(text)
+            _check(self.L, self.L.airebo_params_parse(b, len(b), ctypes.byref(h)))
+        else:
+            _check(self.L, self.L.airebo_params_load(path.encode(), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.airebo_params_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
 class Context:
-    """One AIREBO evaluation context on one GPU."""
+    """One AIREBO evaluation context on one GPU (params: a file path or a ParamSet)."""
 
     def __init__(self, params=DEFAULT_PARAMS, precision=FP64, term_mask=TERM_ALL, skin=1.0, lj_cap=0, device=0,
                  tune=None):
@@ -154,7 +192,10 @@ class Context:
             setattr(o, k, int(v))
         self.tune = dict(tune or {})
         h = ctypes.c_void_p()
-        _check(self.L, self.L.airebo_ctx_create(params.encode(), ctypes.byref(o), ctypes.byref(h)))
+        if isinstance(params, ParamSet):
+            _check(self.L, self.L.airebo_ctx_create_from_params(params.h, ctypes.byref(o), ctypes.byref(h)))
+        else:
+            _check(self.L, self.L.airebo_ctx_create(params.encode(), ctypes.byref(o), ctypes.byref(h)))
         self.h = h
         self.device = torch.device("cuda", device)
 
@@ -174,6 +215,18 @@ class Context:
         import torch
         t = torch.as_tensor(a, dtype=dtype, device=self.device)
         return t.contiguous()
+
+    def compute_host(self, x, species, box, periodic=(1, 1, 1)):
+        """airebo_compute on host (numpy) arrays: energy [4], forces [n,3], virial [6] as numpy arrays."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        s = np.ascontiguousarray(species, dtype=np.int32)
+        n = len(s)
+        e, w, f = np.zeros(4), np.zeros(6), np.zeros((n, 3))
+        dpp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(self.L, self.L.airebo_compute_host(self.h, n, dpp(x), s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                  _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32),
+                                                  dpp(e), dpp(f), dpp(w)))
+        return e, f, w
 
     def compute(self, x, species, box, periodic=(1, 1, 1), out=None):
         """Energy [4] (total, REBO, LJ, torsion), forces [n,3], virial [6] as device tensors."""
@@ -417,6 +470,16 @@ class Surrogate:
         loss = (ctypes.c_double * self.nmodels)()
         _check(self.L, self.L.airebo_nn_gradient(*a, _p(f_ref), float(e_ref), float(w_force), float(w_energy),
                                                   loss, self._stream()))
+        return np.array(list(loss))
+
+    def train_step(self, ctx, x, species, box, f_ref, e_ref, w_force, w_energy, lr, periodic=(1, 1, 1)):
+        """airebo_nn_train_step: loss per member before one Adam step (beta1 0.9, beta2 0.999, eps 1e-8)."""
+        import torch
+        x, s, a = self._geo(ctx, x, species, box, periodic)
+        f_ref = torch.as_tensor(f_ref, dtype=torch.float64, device=self.device).reshape(-1, 3).contiguous()
+        loss = (ctypes.c_double * self.nmodels)()
+        _check(self.L, self.L.airebo_nn_train_step(*a, _p(f_ref), float(e_ref), float(w_force), float(w_energy),
+                                                    float(lr), loss, self._stream()))
         return np.array(list(loss))
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):

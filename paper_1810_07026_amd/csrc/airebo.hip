@@ -1734,6 +1734,10 @@ struct airebo_ctx {
   size_t c_fl = 0;
   int* step = nullptr;
   size_t c_stp = 0;
+  // device staging of airebo_compute_host
+  double* hx = nullptr;      // positions [3n], then energy [4], virial [6], forces [3n]
+  int* hs = nullptr;         // species [n]
+  size_t c_hx = 0, c_hs = 0;
   unsigned long long host_stats[S_N] = {};
   // batch description
   int ncell = 0;
@@ -1781,10 +1785,16 @@ void airebo_options_default(airebo_options* opt) {
   opt->device = 0;
 }
 
-int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t* out) {
-  if (!path || !out) return fail(AIREBO_E_ARG, "null argument");
-  airebo_options o;
-  if (opt) o = *opt; else airebo_options_default(&o);
+}  // extern "C"
+
+struct airebo_params_set {
+  DevParams P;
+  std::vector<double> tri;   // tricubic coefficients (host)
+};
+
+namespace {
+
+int check_options(const airebo_options& o) {
   if (!(o.skin > 0.0 && o.skin < 5.0)) return fail(AIREBO_E_ARG, "skin must be in (0, 5) A");
   if (o.precision != AIREBO_FP64 && o.precision != AIREBO_MIXED) return fail(AIREBO_E_ARG, "unknown precision");
   if (o.term_mask < 0 || o.term_mask > 7) return fail(AIREBO_E_ARG, "bad term mask");
@@ -1794,11 +1804,14 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
   if (!okb(o.bond_block) || !okb(o.defer_block) || !oks(o.short_block) || o.bond_grid < 0)
     return fail(AIREBO_E_ARG, "launch shapes: bond and deferred blocks 0 or 64, 128, 192, 256 threads; "
                               "short-list block 0 or 256, 512, 1024 threads");
+  return 0;
+}
+
+// A context from validated parameters: upload, streams, events.
+int ctx_create_impl(const DevParams& P, const std::vector<double>& tri, const airebo_options& o, airebo_ctx_t* out) {
   airebo_ctx* c = new airebo_ctx();
   c->opt = o;
-  std::vector<double> tri((size_t)TRI_N * kTriCells * kTriCoef);
-  std::string err;
-  if (!build_params(path, c->P, tri.data(), err)) { delete c; return fail(AIREBO_E_PARAMS, err); }
+  c->P = P;
   hipError_t e = hipSetDevice(o.device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->dtri, tri.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(c->dtri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -1817,6 +1830,55 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
   return 0;
 }
 
+}  // namespace
+
+extern "C" {
+
+int airebo_params_load(const char* path, airebo_params_t* out) {
+  if (!path || !out) return fail(AIREBO_E_ARG, "null argument");
+  auto* s = new airebo_params_set();
+  s->tri.resize((size_t)TRI_N * kTriCells * kTriCoef);
+  std::string err;
+  if (!build_params(path, s->P, s->tri.data(), err)) { delete s; return fail(AIREBO_E_PARAMS, err); }
+  *out = s;
+  return 0;
+}
+
+int airebo_params_parse(const char* text, size_t len, airebo_params_t* out) {
+  if (!text || !out) return fail(AIREBO_E_ARG, "null argument");
+  auto* s = new airebo_params_set();
+  s->tri.resize((size_t)TRI_N * kTriCells * kTriCoef);
+  std::string err;
+  if (!build_params_text(text, len, s->P, s->tri.data(), err)) { delete s; return fail(AIREBO_E_PARAMS, err); }
+  *out = s;
+  return 0;
+}
+
+void airebo_params_free(airebo_params_t params) { delete params; }
+
+int airebo_ctx_create_from_params(airebo_params_t params, const airebo_options* opt, airebo_ctx_t* out) {
+  if (!params || !out) return fail(AIREBO_E_ARG, "null argument");
+  airebo_options o;
+  if (opt) o = *opt; else airebo_options_default(&o);
+  int rc = check_options(o);
+  if (rc) return rc;
+  return ctx_create_impl(params->P, params->tri, o, out);
+}
+
+int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t* out) {
+  if (!path || !out) return fail(AIREBO_E_ARG, "null argument");
+  airebo_options o;
+  if (opt) o = *opt; else airebo_options_default(&o);
+  int rc = check_options(o);
+  if (rc) return rc;
+  airebo_params_t s = nullptr;
+  rc = airebo_params_load(path, &s);
+  if (rc) return rc;
+  rc = ctx_create_impl(s->P, s->tri, o, out);
+  airebo_params_free(s);
+  return rc;
+}
+
 void airebo_ctx_free(airebo_ctx_t c) {
   if (!c) return;
   if (c->side) (void)hipStreamDestroy(c->side);
@@ -1825,7 +1887,7 @@ void airebo_ctx_free(airebo_ctx_t c) {
   void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->xsort, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
                   c->cell_atoms, c->lj_n, c->lj_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
                   c->bcount, c->bonds, c->qcount, c->q, c->F, c->acc, c->dsys, c->atom_sys, c->sys_acc,
-                  c->stats, c->flags, c->step};
+                  c->stats, c->flags, c->step, c->hx, c->hs};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete c;
@@ -2199,6 +2261,30 @@ int airebo_compute(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* 
   if (n < 0) return fail(AIREBO_E_ARG, "n must be >= 0");
   int64_t off[2] = {0, n};
   return compute_impl(c, 1, off, box, periodic, pos, species, energy, forces, virial, stream);
+}
+
+int airebo_compute_host(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
+                        const int32_t* periodic, double* energy, double* forces, double* virial) {
+  if (!c || (n > 0 && (!pos || !species || !forces)) || !energy || !virial || !box || !periodic)
+    return fail(AIREBO_E_ARG, "null argument");
+  if (n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
+  HIPCHK(hipSetDevice(c->opt.device));
+  size_t N = (size_t)std::max<int64_t>(n, 1);
+  if (grow(c->hx, c->c_hx, 6 * N + 10) | grow(c->hs, c->c_hs, N)) return fail(AIREBO_E_DEVICE, "staging allocation");
+  double* dpos = c->hx;
+  double* dE = c->hx + 3 * N;
+  double* dW = dE + 4;
+  double* dF = dE + 10;
+  if (n > 0) {
+    HIPCHK(hipMemcpy(dpos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->hs, species, sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  }
+  int rc = airebo_compute(c, n, dpos, c->hs, box, periodic, dE, dF, dW, nullptr);
+  if (rc) return rc;
+  HIPCHK(hipMemcpy(energy, dE, sizeof(double) * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(virial, dW, sizeof(double) * 6, hipMemcpyDeviceToHost));
+  if (n > 0) HIPCHK(hipMemcpy(forces, dF, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+  return 0;
 }
 
 int airebo_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species, const double* box,

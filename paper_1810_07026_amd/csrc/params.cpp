@@ -61,26 +61,39 @@ bool make_gspline(const std::vector<std::vector<double>>& knots, GSpline& g, std
 }  // namespace
 
 bool build_params(const char* path, DevParams& P, double* tri, std::string& err) {
-  FILE* f = std::fopen(path, "r");
+  FILE* f = std::fopen(path, "rb");
   if (!f) { err = std::string("cannot open parameter file ") + path; return false; }
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  return build_params_text(text.data(), text.size(), P, tri, err);
+}
+
+bool build_params_text(const char* text, size_t len, DevParams& P, double* tri, std::string& err) {
   std::vector<Rec> recs;
-  char line[2048];
-  while (std::fgets(line, sizeof line, f)) {
-    if (char* h = std::strchr(line, '#')) *h = 0;
+  size_t pos = 0;
+  while (pos < len) {
+    size_t eol = pos;
+    while (eol < len && text[eol] != '\n') ++eol;
+    std::string line(text + pos, eol - pos);
+    pos = eol + 1;
+    size_t h = line.find('#');
+    if (h != std::string::npos) line.resize(h);
     char* save = nullptr;
-    char* tok = strtok_r(line, " \t\r\n", &save);
+    char* tok = strtok_r(&line[0], " \t\r\n", &save);
     if (!tok) continue;
     Rec r;
     r.key = tok;
     while ((tok = strtok_r(nullptr, " \t\r\n", &save))) {
       char* end = nullptr;
       double v = std::strtod(tok, &end);
-      if (end == tok || *end) { std::fclose(f); err = "non-numeric field in record " + r.key; return false; }
+      if (end == tok || *end) { err = "non-numeric field in record " + r.key; return false; }
       r.v.push_back(v);
     }
     recs.push_back(r);
   }
-  std::fclose(f);
 
   std::memset(&P, 0, sizeof P);
   std::map<std::string, double> sc;

@@ -53,5 +53,7 @@ struct DevParams {
 // Parse the parameter file and fill `P` (tri left null) and the host copy of
 // the tricubic coefficients (TRI_N * kTriCells * kTriCoef doubles).
 bool build_params(const char* path, DevParams& P, double* tri_host, std::string& err);
+// The same from the file's text in memory (len bytes).
+bool build_params_text(const char* text, size_t len, DevParams& P, double* tri_host, std::string& err);
 
 }  // namespace airebo

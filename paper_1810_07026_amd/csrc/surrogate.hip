@@ -1556,6 +1556,14 @@ int airebo_nn_adam(airebo_nn_t m, double lr, double beta1, double beta2, double 
   return 0;
 }
 
+int airebo_nn_train_step(airebo_nn_t m, airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species,
+                         const double* box, const int32_t* periodic, const double* f_ref, double e_ref,
+                         double w_force, double w_energy, double lr, double* loss, void* stream) {
+  int rc = airebo_nn_gradient(m, c, n, pos, species, box, periodic, f_ref, e_ref, w_force, w_energy, loss, stream);
+  if (rc) return rc;
+  return airebo_nn_adam(m, lr, 0.9, 0.999, 1e-8, stream);
+}
+
 int airebo_nn_nve(airebo_nn_t m, airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species,
                   const double* box, const int32_t* periodic, const double* mass, double dt, int64_t nsteps,
                   int64_t every, double* thermo, double threshold, int64_t* fallbacks, void* stream) {

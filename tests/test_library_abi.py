@@ -30,3 +30,22 @@ def test_options_default_on_cpu():
     L.airebo_options_default(ctypes.byref(o))
     assert o.precision == 0 and o.term_mask == 7 and abs(o.skin - 1.0) < 1e-15
     assert L.airebo_last_error() is not None
+
+
+def test_params_from_file_and_text_on_cpu():
+    """The parameter set parses on the host alone, from the file and from its
+    text; malformed text is rejected with the failing record named."""
+    import pytest
+    ps = airebo.ParamSet()
+    ps.close()
+    text = open(airebo.DEFAULT_PARAMS).read()
+    ps = airebo.ParamSet(text=text)
+    ps.close()
+    bad = text.replace("tors_eps_CCCC 0.3079", "tors_eps_CCCC 0.30x9")
+    assert bad != text
+    with pytest.raises(airebo.AireboError) as ex:
+        airebo.ParamSet(text=bad)
+    assert ex.value.code == -2 and "tors_eps_CCCC" in str(ex.value)
+    with pytest.raises(airebo.AireboError) as ex:
+        airebo.ParamSet(text="")
+    assert ex.value.code == -2
