@@ -50,6 +50,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +187,15 @@ def main():
             t3 = time.perf_counter()
             cpu = {"value": n / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
                    "sample": f"one full FP64 force evaluation (= one MD step) of the {n}-atom system, "
-                             f"{t3 - t2:.1f} s"}
+                             f"{t3 - t2:.1f} s", "host_cpu": host_cpu()}
+            # the same oracle on one thread, on a sample of atoms (every term touching them)
+            sel1 = np.sort(np.random.default_rng(1).choice(n, min(n, 2048), replace=False)).astype(np.int32)
+            t4 = time.perf_counter()
+            Oracle(nthreads=1).compute(xf_h, d["species"], box, per, sel=sel1)
+            t5 = time.perf_counter()
+            cpu["single_thread"] = {"value": len(sel1) / (t5 - t4), "unit": "atom-steps/s", "cores": 1,
+                                    "sample": f"exact FP64 forces on {len(sel1)} random atoms of the {n}-atom "
+                                              f"system, {t5 - t4:.1f} s"}
             rms = math.sqrt((fo ** 2).sum(1).mean())
             ferr = {"force_rms_err_eVA": float(math.sqrt(((fg - fo) ** 2).sum(1).mean())),
                     "force_rel_err_max": float(np.abs(fg - fo).max() / rms),
