@@ -73,8 +73,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["pe_melt_32k", "hybrid_1m", "batch512", "surrogate_1m"],
+    ap.add_argument("--workload", choices=["pe_melt_32k", "hybrid_1m", "batch512", "surrogate_1m", "conservation"],
                     default="pe_melt_32k")
+    ap.add_argument("--dt", type=float, default=0.5, help="time step in fs (conservation workload)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and surrogate timings beside the FP64 line")
     ap.add_argument("--form-steps", type=int, default=200)
@@ -100,6 +101,8 @@ def main():
         log(f"bench: copied {args.copy_calib_mb} MiB three times (counter calibration)")
         del a, b
 
+    if args.workload == "conservation":
+        return bench_conservation(args)
     if args.workload == "batch512":
         return bench_batch(args)
     if args.workload == "surrogate_1m":
@@ -379,6 +382,57 @@ def bench_surrogate(args):
            "forms": res, "surrogate_error_vs_fp64_gpu": err,
            "mixed_error_vs_fp64_gpu": force_err(fm, f64), "accuracy_vs_oracle": acc_or,
            "cpu_baseline": cpu, "kernels_us": kern}
+    print(json.dumps(out))
+
+
+def bench_conservation(args):
+    """Energy conservation over a long NVE run of the 32,012-atom melt (the
+    paper's precision study, Sec. 5): total energy every 1,000 steps, the run
+    split into calls of 100,000 steps so that progress is reported."""
+    import torch
+    from paper_1810_07026_amd import airebo, synth
+    d = synth.pe_melt()
+    s, box, per = d["species"], d["box"], d["periodic"]
+    n = len(s)
+    prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
+    ctx = airebo.Context(precision=prec)
+    x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+    every, chunk = 1000, 100000
+    rows = []
+    done = rebuilds = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < args.steps:
+        k = min(chunk, args.steps - done)
+        th = ctx.nve(x, v, s, box, per, dt=args.dt, nsteps=k, thermo_every=every).cpu().numpy()
+        rebuilds += int(ctx.stats()["rebuilds"])
+        th = th.reshape(th.shape[0], -1)
+        rows.append(th if done == 0 else th[1:])   # a later call's first row repeats the previous last
+        done += k
+        e = np.concatenate(rows)[:, 3]
+        log(f"bench: conservation {args.precision} dt {args.dt} fs: {done} steps, "
+            f"E_tot {e[-1]:.4f} eV, max |dE|/|E0| {np.abs(e - e[0]).max() / abs(e[0]):.3g}, "
+            f"{time.perf_counter() - t0:.0f} s")
+    sec = time.perf_counter() - t0
+    th = np.concatenate(rows)
+    e, temp = th[:, 3], th[:, 4]
+    rel = (e - e[0]) / abs(e[0])
+    t_ps = np.arange(len(e)) * every * args.dt * 1e-3
+    slope = float(np.polyfit(t_ps, e / n, 1)[0]) if len(e) > 2 else 0.0
+    out = {"metric": "AIREBO energy conservation (max relative total-energy deviation)",
+           "value": float(np.abs(rel).max()), "unit": "relative", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prec == airebo.FP64 else "f32+f64",
+           "data": "synthetic (seeded generators)",
+           "config": {"workload": f"polyethylene melt 106 x C100H202, {n} atoms, NVE {args.steps} steps of "
+                                  f"{args.dt} fs, {args.precision}", "n_atoms": n, "dt_fs": args.dt},
+           "atom_steps_per_s": n * args.steps / sec,
+           "energy": {"E0_eV": float(e[0]), "E_end_eV": float(e[-1]), "final_rel": float(rel[-1]),
+                      "rms_rel": float(np.sqrt((rel ** 2).mean())), "slope_eV_per_atom_per_ps": slope,
+                      "T_start_K": float(temp[0]), "T_end_K": float(temp[-1]),
+                      "rel_every_100k_steps": [float(r) for r in rel[::100]]},
+           "rebuilds": rebuilds}
     print(json.dumps(out))
 
 
