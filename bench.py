@@ -73,9 +73,12 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", choices=["pe_melt_32k", "hybrid_1m", "batch512", "surrogate_1m", "conservation"],
+    ap.add_argument("--workload", choices=["pe_melt_32k", "hybrid_1m", "cnt_bundle", "batch512", "surrogate_1m",
+                                           "conservation"],
                     default="pe_melt_32k")
     ap.add_argument("--dt", type=float, default=0.5, help="time step in fs (conservation workload)")
+    ap.add_argument("--system", choices=["pe_melt", "cnt_bundle"], default="pe_melt",
+                    help="system of the conservation workload")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and surrogate timings beside the FP64 line")
     ap.add_argument("--form-steps", type=int, default=200)
@@ -108,7 +111,8 @@ def main():
     if args.workload == "surrogate_1m":
         return bench_surrogate(args)
     log("bench: generating workload")
-    d = synth.pe_melt() if args.workload == "pe_melt_32k" else synth.hybrid_1m()
+    d = {"pe_melt_32k": synth.pe_melt, "hybrid_1m": synth.hybrid_1m,
+         "cnt_bundle": synth.nanotube_bundle}[args.workload]()
     n = len(d["species"])
     box, per = d["box"], d["periodic"]
     prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
@@ -172,7 +176,8 @@ def main():
         ach = work[cand] / avg_s
         roof = {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": ach / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": counter_traffic(cand, args.precision),
+                # the committed counter profile is of the melt workload
+                "traffic": counter_traffic(cand, args.precision) if args.workload == "pe_melt_32k" else None,
                 "flop_per_launch": work[cand], "avg_launch_us": kern[cand]["avg_us"]}
         log(f"bench: kernels {json.dumps({k: round(v['avg_us'], 2) for k, v in kern.items()})}")
 
@@ -229,6 +234,10 @@ def main():
         "config": {"workload": (f"polyethylene melt 106 x C100H202, {n} atoms, 0.85 g/cm^3, "
                                 f"{box[0]:.2f} A periodic cube, 300 K, NVE dt 0.5 fs, {args.precision}"
                                 if args.workload == "pe_melt_32k" else
+                                f"bundle of 16 (10,10) carbon nanotubes, {n} atoms, 3.4 A between walls, "
+                                f"box {box[0]:.1f} x {box[1]:.1f} x {box[2]:.1f} A periodic, 300 K, NVE dt 0.5 fs, "
+                                f"{args.precision}"
+                                if args.workload == "cnt_bundle" else
                                 f"hybrid {n} atoms: AB graphite 30 layers + H-terminated diamond (111) 31 bilayers "
                                 f"+ polyethylene melt slab, box {box[0]:.1f} x {box[1]:.1f} x {box[2]:.1f} A, "
                                 f"300 K, NVE dt 0.5 fs, {args.precision}"),
@@ -386,12 +395,13 @@ def bench_surrogate(args):
 
 
 def bench_conservation(args):
-    """Energy conservation over a long NVE run of the 32,012-atom melt (the
-    paper's precision study, Sec. 5): total energy every 1,000 steps, the run
-    split into calls of 100,000 steps so that progress is reported."""
+    """Energy conservation over a long NVE run of the 32,012-atom melt or the
+    nanotube bundle (the paper's precision study, Sec. 5): total energy every
+    1,000 steps, the run split into calls of 100,000 steps so that progress
+    is reported."""
     import torch
     from paper_1810_07026_amd import airebo, synth
-    d = synth.pe_melt()
+    d = synth.pe_melt() if args.system == "pe_melt" else synth.nanotube_bundle()
     s, box, per = d["species"], d["box"], d["periodic"]
     n = len(s)
     prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
@@ -425,8 +435,10 @@ def bench_conservation(args):
            "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if prec == airebo.FP64 else "f32+f64",
            "data": "synthetic (seeded generators)",
-           "config": {"workload": f"polyethylene melt 106 x C100H202, {n} atoms, NVE {args.steps} steps of "
-                                  f"{args.dt} fs, {args.precision}", "n_atoms": n, "dt_fs": args.dt},
+           "config": {"workload": ("polyethylene melt 106 x C100H202" if args.system == "pe_melt" else
+                                   "bundle of 16 (10,10) carbon nanotubes") +
+                                  f", {n} atoms, NVE {args.steps} steps of {args.dt} fs, {args.precision}",
+                      "n_atoms": n, "dt_fs": args.dt},
            "atom_steps_per_s": n * args.steps / sec,
            "energy": {"E0_eV": float(e[0]), "E_end_eV": float(e[-1]), "final_rel": float(rel[-1]),
                       "rms_rel": float(np.sqrt((rel ** 2).mean())), "slope_eV_per_atom_per_ps": slope,

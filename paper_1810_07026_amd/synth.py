@@ -597,6 +597,71 @@ def graphene_flake(nx, ny, cc=1.42):
     return np.array(xs), np.array(ss, np.int32)
 
 
+def nanotube(n, m, ncells, cc=1.42):
+    """Single-wall (n, m) carbon nanotube along z, ncells translational unit
+    cells long, periodic along its axis.
+
+    The graphene sheet (lattice constant a = sqrt(3) cc) is rolled so that
+    the chiral vector C = n a1 + m a2 becomes the circumference and the
+    translation vector T (the shortest lattice vector normal to C) the axis.
+    Returns (x [N, 3], species (all carbon), box, periodic) with the tube
+    centred in a box whose x and y sides leave 20 A of vacuum and are not
+    periodic, and whose z side is ncells |T|."""
+    a = cc * math.sqrt(3.0)
+    a1 = np.array([a * math.sqrt(3.0) / 2, a / 2])
+    a2 = np.array([a * math.sqrt(3.0) / 2, -a / 2])
+    basis = [np.zeros(2), (a1 + a2) / 3.0]
+    dr = math.gcd(2 * m + n, 2 * n + m)
+    t1, t2 = (2 * m + n) // dr, -(2 * n + m) // dr
+    C = n * a1 + m * a2
+    T = t1 * a1 + t2 * a2
+    Lc, Lt = float(np.linalg.norm(C)), float(np.linalg.norm(T))
+    per_cell = 4 * (n * n + n * m + m * m) // dr
+    pts = []
+    span = n + m + abs(t1) + abs(t2) + 2
+    for i in range(-span, span + 1):
+        for j in range(-span, span + 1):
+            for b in basis:
+                p = i * a1 + j * a2 + b
+                u = float(p @ C) / Lc ** 2          # fraction of the circumference
+                w = float(p @ T) / Lt ** 2          # fraction of the cell length
+                if -1e-9 <= u < 1 - 1e-9 and -1e-9 <= w < 1 - 1e-9:
+                    pts.append((u, w))
+    if len(pts) != per_cell:
+        raise RuntimeError(f"({n},{m}) unit cell: {len(pts)} atoms, expected {per_cell}")
+    R = Lc / (2 * math.pi)
+    L = ncells * Lt
+    side = 2 * R + 40.0
+    xs = []
+    for k in range(ncells):
+        for u, w in pts:
+            th = 2 * math.pi * u
+            xs.append([side / 2 + R * math.cos(th), side / 2 + R * math.sin(th), (w + k) * Lt])
+    x = np.array(xs)
+    return x, np.zeros(len(x), np.int32), np.array([side, side, L]), np.array([0, 0, 1], np.int32)
+
+
+def nanotube_bundle(n=10, m=10, ncells=40, nx=4, ny=4, gap=3.4, seed=SEED0 + 5, T=300.0):
+    """nx x ny parallel (n, m) nanotubes on a square lattice, gap A between
+    walls, in a box periodic in all three directions (the tubes infinite
+    along z); Maxwell velocities at T.  The default is 16 (10,10) tubes of
+    40 cells: 25,600 carbon atoms, 67.8 x 67.8 x 98.4 A."""
+    x0, s0, box0, _ = nanotube(n, m, ncells)
+    c0 = np.array([box0[0] / 2, box0[1] / 2, 0.0])
+    rad = float(np.linalg.norm(x0[0, :2] - c0[:2]))
+    pitch = 2 * rad + gap
+    xs = []
+    for i in range(nx):
+        for j in range(ny):
+            xs.append(x0 - c0 + np.array([(i + 0.5) * pitch, (j + 0.5) * pitch, 0.0]))
+    x = np.vstack(xs)
+    s = np.zeros(len(x), np.int32)
+    box = np.array([nx * pitch, ny * pitch, box0[2]])
+    v = maxwell_velocities(s, T, np.random.default_rng(seed))
+    return dict(x=x, species=s, v=v, box=box, periodic=np.ones(3, np.int32),
+                meta=dict(kind="nanotube_bundle", n=n, m=m, ncells=ncells, nx=nx, ny=ny, seed=seed))
+
+
 # ---------------------------------------------------------------------------
 # Crystalline slabs and the ~10^6-atom hybrid system
 # ---------------------------------------------------------------------------

@@ -227,3 +227,19 @@ def test_mixed_is_not_fp64(mixed_ctx, ctxs):
     f64 = run_gpu(ctxs[7], d)[1]
     diff = np.abs(f32 - f64).max() / math.sqrt((f64 ** 2).sum(1).mean())
     assert 1e-9 < diff < TOL_MIXED_F
+
+
+@pytest.mark.parametrize("nm", [(5, 5, 5), (10, 10, 5), (10, 0, 4)])
+def test_nanotube(ctxs, mixed_ctx, oracle, nm):
+    """Jittered single-wall nanotubes (armchair and zigzag), periodic along the
+    axis: all-sp2 carbon, where pi^dh (T_CC) and the explicit torsion are
+    live on every bond.  FP64 at the FP64 bar, mixed at its own."""
+    x, s, box, per = synth.nanotube(*nm)
+    d = dict(x=x + np.random.default_rng(sum(nm)).normal(scale=0.04, size=x.shape), species=s, box=box,
+             periodic=per)
+    ref = oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
+    compare(run_gpu(ctxs[7], d), ref, f"nanotube {nm}")
+    e, f, w = run_gpu(mixed_ctx, d)
+    rms = math.sqrt((ref[1] ** 2).sum(1).mean())
+    assert np.abs(f - ref[1]).max() / rms < TOL_MIXED_F
+    assert abs(e[0] - ref[0][0]) <= TOL_MIXED_E * abs(ref[0][0])

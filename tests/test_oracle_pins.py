@@ -254,6 +254,18 @@ def test_forces_fd_reactive(oracle, seed, mask):
     fd_check(oracle, x, s, BIG, NOPER, mask, atoms=range(0, 24, 3))
 
 
+@pytest.mark.parametrize("mask", [MASK_REBO, MASK_TORS, 7])
+def test_forces_fd_nanotube(oracle, mask):
+    """A jittered (5,5) nanotube, periodic along its axis: every carbon is
+    sp2, so the dihedral terms (pi^dh with T_CC, explicit torsion) that the
+    polyethylene melt barely touches carry the forces."""
+    x, s, box, per = synth.nanotube(5, 5, 5)
+    x = x + np.random.default_rng(3).normal(scale=0.05, size=x.shape)
+    e, _, _ = oracle.compute(x, s, box, per, mask=MASK_TORS)
+    assert abs(e[3]) > 1.0   # torsion energy present
+    fd_check(oracle, x, s, box, per, mask, atoms=[0, 17, 33, 64, 99])
+
+
 def test_forces_fd_pe_small(oracle):
     d = synth.pe_small(seed=7)
     x = d["x"] + np.random.default_rng(1).normal(scale=0.08, size=d["x"].shape)
