@@ -28,6 +28,8 @@ FP32_VALU_PEAK = 157.3e12
 # per REBO bond (bond order forward + reverse, pair term, torsion).
 FLOP_PER_LJ_PAIR = 60
 FLOP_PER_BOND = 4000
+# arithmetic type of the force evaluation per precision mode (the integrator is FP64)
+DTYPES = {"fp64": "f64", "mixed": "f32+f64", "single": "f32"}
 
 
 def counter_traffic(kernel, precision):
@@ -69,7 +71,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "single"], default="fp64")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -82,6 +84,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and surrogate timings beside the FP64 line")
     ap.add_argument("--form-steps", type=int, default=200)
+    ap.add_argument("--thermo-out", default="",
+                    help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds) to this text file")
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -115,7 +119,7 @@ def main():
          "cnt_bundle": synth.nanotube_bundle}[args.workload]()
     n = len(d["species"])
     box, per = d["box"], d["periodic"]
-    prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
+    prec = airebo.PRECISIONS[args.precision]
     ctx = airebo.Context(precision=prec)
     dev = torch.device("cuda", 0)
     x = torch.tensor(d["x"], dtype=torch.float64, device=dev)
@@ -229,7 +233,7 @@ def main():
         "metric": "AIREBO atom-steps/s on 1 GPU",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == airebo.FP64 else "f32+f64",
+        "vs_baseline": None, "dtype": DTYPES[args.precision],
         "data": "synthetic (seeded generators)",
         "config": {"workload": (f"polyethylene melt 106 x C100H202, {n} atoms, 0.85 g/cm^3, "
                                 f"{box[0]:.2f} A periodic cube, 300 K, NVE dt 0.5 fs, {args.precision}"
@@ -273,7 +277,7 @@ def timed_nve(run, n, steps, warmup):
 
 
 def measure_forms(d, x0, v0, args, fp64_value, fo):
-    """Mixed precision and surrogate on the same system as the FP64 line,
+    """Mixed and single precision and the surrogate on the same system as the FP64 line,
     from the state its timed run ended in: atom-steps/s of NVE and force RMS
     error against the CPU oracle (when it was evaluated) or the FP64 GPU
     forces at that state."""
@@ -287,14 +291,16 @@ def measure_forms(d, x0, v0, args, fp64_value, fo):
         fo = ctx.compute(x0, s, box, per)[1].cpu().numpy()
         ref_kind = "fp64_gpu"
     forms = {"reference": ref_kind, "steps": args.form_steps}
-    # mixed precision
-    ctxm = airebo.Context(precision=airebo.MIXED)
-    xm, vm = x0.clone(), v0.clone()
-    val, ms, _ = timed_nve(lambda k: ctxm.nve(xm, vm, s, box, per, nsteps=k, thermo_every=0), n, args.form_steps,
-                           args.warmup)
-    fm = ctxm.compute(x0, s, box, per)[1].cpu().numpy()
-    forms["mixed"] = dict(force_err(fm, fo), value=val, ms_per_step=ms, speedup_vs_fp64=val / fp64_value)
-    log(f"bench: mixed {val:.4g} atom-steps/s, force rel rms err {forms['mixed']['force_rel_rms_err']:.3g}")
+    # mixed and single precision
+    for name, prec in (("mixed", airebo.MIXED), ("single", airebo.SINGLE)):
+        ctxm = airebo.Context(precision=prec)
+        xm, vm = x0.clone(), v0.clone()
+        val, ms, _ = timed_nve(lambda k: ctxm.nve(xm, vm, s, box, per, nsteps=k, thermo_every=0), n,
+                               args.form_steps, args.warmup)
+        fm = ctxm.compute(x0, s, box, per)[1].cpu().numpy()
+        forms[name] = dict(force_err(fm, fo), value=val, ms_per_step=ms, speedup_vs_fp64=val / fp64_value)
+        log(f"bench: {name} {val:.4g} atom-steps/s, force rel rms err {forms[name]['force_rel_rms_err']:.3g}")
+        del ctxm
     # learned surrogate
     if not os.path.exists(surrogate.WEIGHTS):
         forms["surrogate"] = {"error": "no trained weights (python -m paper_1810_07026_amd.surrogate train)"}
@@ -404,7 +410,7 @@ def bench_conservation(args):
     d = synth.pe_melt() if args.system == "pe_melt" else synth.nanotube_bundle()
     s, box, per = d["species"], d["box"], d["periodic"]
     n = len(s)
-    prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
+    prec = airebo.PRECISIONS[args.precision]
     ctx = airebo.Context(precision=prec)
     x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
     v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
@@ -426,6 +432,8 @@ def bench_conservation(args):
             f"{time.perf_counter() - t0:.0f} s")
     sec = time.perf_counter() - t0
     th = np.concatenate(rows)
+    if args.thermo_out:
+        np.savetxt(args.thermo_out, th, fmt="%.10g", header="step PE_eV KE_eV Etot_eV T_K rebuilds")
     e, temp = th[:, 3], th[:, 4]
     rel = (e - e[0]) / abs(e[0])
     t_ps = np.arange(len(e)) * every * args.dt * 1e-3
@@ -433,7 +441,7 @@ def bench_conservation(args):
     out = {"metric": "AIREBO energy conservation (max relative total-energy deviation)",
            "value": float(np.abs(rel).max()), "unit": "relative", "n_gpus": 1, "steps": args.steps, "warmup": 0,
            "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": False, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64" if prec == airebo.FP64 else "f32+f64",
+           "vs_baseline": None, "dtype": DTYPES[args.precision],
            "data": "synthetic (seeded generators)",
            "config": {"workload": ("polyethylene melt 106 x C100H202" if args.system == "pe_melt" else
                                    "bundle of 16 (10,10) carbon nanotubes") +
@@ -454,7 +462,7 @@ def bench_batch(args):
     from paper_1810_07026_amd import airebo, synth
     d = synth.batch_cached(512)
     n = int(d["sizes"].sum())
-    prec = airebo.FP64 if args.precision == "fp64" else airebo.MIXED
+    prec = airebo.PRECISIONS[args.precision]
     tune = {}
     if args.tune and args.tune not in ("auto", "retune"):
         tune = json.loads(args.tune)
@@ -502,7 +510,7 @@ def bench_batch(args):
     out = {"metric": "AIREBO atom-steps/s on 1 GPU", "value": value, "unit": "atom-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == airebo.FP64 else "f32+f64", "data": "synthetic (seeded generators)",
+           "dtype": DTYPES[args.precision], "data": "synthetic (seeded generators)",
            "config": {"workload": f"batch of 512 systems, {n} atoms, sizes {int(d['sizes'].min())}-"
                                   f"{int(d['sizes'].max())}, five hydrocarbon families, own periodic boxes, "
                                   f"NVE dt 0.5 fs, {args.precision}", "n_atoms": n, "tune": tune},

@@ -47,7 +47,21 @@ enum {
   AIREBO_E_DEVICE = -7     /* a HIP runtime error (message carries the code)   */
 };
 
-enum { AIREBO_FP64 = 0, AIREBO_MIXED = 1 };
+/* Precision of the force evaluation (the integrator is FP64 in every mode).
+ * The paper names double, mixed and single modes (Sec. 4.4, Sec. 5.2) without
+ * defining them; here:
+ *   AIREBO_FP64    every operation in FP64.
+ *   AIREBO_MIXED   FP32 arithmetic of the pair, bond-order and LJ terms on
+ *                  relative vectors formed in FP64; a spline argument within
+ *                  1e-3 of a knot evaluated in FP64; FP64 accumulation of
+ *                  forces, energies and the virial.
+ *   AIREBO_SINGLE  FP32 throughout the force evaluation: relative vectors from
+ *                  positions rounded to FP32, bond weights, coordination
+ *                  numbers, all term arithmetic, and the force sums (FP32
+ *                  atomics); per-lane energy and virial sums are FP32 and are
+ *                  combined across lanes in FP64.  Forces are handed out as
+ *                  FP64 copies of the FP32 sums. */
+enum { AIREBO_FP64 = 0, AIREBO_MIXED = 1, AIREBO_SINGLE = 2 };
 enum { AIREBO_TERM_REBO = 1, AIREBO_TERM_LJ = 2, AIREBO_TERM_TORSION = 4, AIREBO_TERM_ALL = 7 };
 
 typedef struct airebo_ctx* airebo_ctx_t;
@@ -56,7 +70,7 @@ typedef struct airebo_params_set* airebo_params_t;
 /* Run-time options.  Zero-initialise, then set what differs from the
  * defaults; airebo_options_default() fills the defaults. */
 typedef struct {
-  int32_t precision;   /* AIREBO_FP64 (default) or AIREBO_MIXED                       */
+  int32_t precision;   /* AIREBO_FP64 (default), AIREBO_MIXED or AIREBO_SINGLE       */
   int32_t term_mask;   /* AIREBO_TERM_* bits; default AIREBO_TERM_ALL                  */
   double skin;         /* neighbour-list skin in A (default 1.0)                      */
   int32_t lj_cap;      /* LJ list entries per atom; 0 = automatic (grows on demand)   */

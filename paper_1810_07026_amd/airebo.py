@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libairebo.so")
 DEFAULT_PARAMS = os.path.join(HERE, "params", "airebo_ch.param")
 
-FP64, MIXED = 0, 1
+FP64, MIXED, SINGLE = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "single": SINGLE}
 TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
               "reserved7", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks"]

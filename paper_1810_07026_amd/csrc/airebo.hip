@@ -31,8 +31,10 @@
 //                                S_r range are deferred to a queue (Sec. 4.3)
 //     k_bstar                    one lane per queued pair: C_ij, b*, S_b, full
 //                                gradient
-//   Forces are accumulated with hardware FP64 atomics; energies and the virial by
-//   block reduction followed by one atomic per block.
+//   Forces are accumulated with hardware FP64 atomics (FP32 atomics into a
+//   separate array in single precision, folded into the FP64 forces by
+//   k_fold32); energies and the virial by block reduction followed by one
+//   atomic per block.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,6 +67,7 @@ enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16,
 enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_SPL = 13,
        A_SPL64 = 14, A_N = 16 };
 // mixed precision: a spline argument within this distance of a knot is evaluated in FP64
+// (single precision takes no such branch)
 constexpr double KNOT_DELTA = 1e-3;
 constexpr int NSLOT = 64;
 // deferred-pair queue: NSEG segments with separate counters (QSTRIDE ints apart)
@@ -72,11 +75,11 @@ constexpr int NSEG = 64, QSTRIDE = 32;
 // kernel ids for per-kernel timing
 enum { K_LOAD, K_BIN, K_SCAN, K_FILL, K_BUILD, K_BUILD_DONE, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
        K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_PACK,
-       K_NN_ENS, K_NN_DECIDE, K_COUNT };
+       K_NN_ENS, K_NN_DECIDE, K_FOLD32, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {
     "k_load", "k_bin", "k_scan", "k_fill", "k_build", "k_build_done", "k_zero", "k_short", "k_bond",
     "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo", "nn_zero", "nn_order", "nn_desc",
-    "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide"};
+    "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
        S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_N = 16 };
@@ -124,6 +127,7 @@ struct Dev {
   int* qcount;       // [NSEG * QSTRIDE]
   int4* q;           // (i, j, shift code, path code)
   double* F;         // forces [n][3]
+  float* F32;        // FP32 force sums [n][3], single precision only (folded into F, then cleared)
   double* acc;       // A_N accumulators
   unsigned long long* stats;
   int* flags;
@@ -155,6 +159,7 @@ __device__ __forceinline__ void xsincospi(double a, double* s, double* c) { sinc
 __device__ __forceinline__ void xsincospi(float a, float* s, float* c) { sincospif(a, s, c); }
 
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
 // REBO bond weight w(r) and dw/dr: 1 below R1, 0 above R2, half cosine between.
 template <typename R>
@@ -199,14 +204,14 @@ __device__ __forceinline__ R guard(const DevParams& P, R c, R& d) {
 
 // Quintic angular spline: value and d/dx.
 template <typename R>
-__device__ __forceinline__ R gspl(const GSpline& g, R x, R& d, int* st) {
+__device__ __forceinline__ R gspl(const GSpline& g, R x, R& d, int* st, double kd) {
   st[0]++;
   if constexpr (std::is_same<R, float>::value) {
     for (int m = 1; m + 1 < g.n; ++m)
-      if (fabs((double)x - g.x[m]) < KNOT_DELTA) {
+      if (fabs((double)x - g.x[m]) < kd) {
         st[1]++;
         double dd;
-        double v = gspl<double>(g, (double)x, dd, st + 2);
+        double v = gspl<double>(g, (double)x, dd, st + 2, kd);
         d = (float)dd;
         return (float)v;
       }
@@ -227,29 +232,29 @@ __device__ __forceinline__ R gspl(const GSpline& g, R x, R& d, int* st) {
 template <typename R>
 __device__ __forceinline__ R gfun(const DevParams& P, int sc, R c, R N, R& dc, R& dN, int* st) {
   dN = 0;
-  if (sc == 1) return gspl(P.gH, c, dc, st);
+  if (sc == 1) return gspl(P.gH, c, dc, st, P.knot_delta);
   R dG;
-  R G = gspl(P.gC, c, dG, st);
+  R G = gspl(P.gC, c, dG, st, P.knot_delta);
   dc = dG;
   if (c <= (R)P.gammaC.x[0]) return G;
   R dQ;
   R Qn = cosstep(N, P.gC_lo, P.gC_hi, dQ);
   if (Qn == (R)0 && dQ == (R)0) return G;
   R dgam;
-  R gam = gspl(P.gammaC, c, dgam, st);
+  R gam = gspl(P.gammaC, c, dgam, st, P.knot_delta);
   dc = dG + Qn * (dgam - dG);
   dN = dQ * (gam - G);
   return G + Qn * (gam - G);
 }
 // Bicubic P_{C s_j}(N^C, N^H) with partials.
 template <typename R>
-__device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx, R& dy, int* st) {
+__device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx, R& dy, int* st, double kd) {
   st[0]++;
   if constexpr (std::is_same<R, float>::value) {
-    if (fabs((double)x - rint((double)x)) < KNOT_DELTA || fabs((double)y - rint((double)y)) < KNOT_DELTA) {
+    if (fabs((double)x - rint((double)x)) < kd || fabs((double)y - rint((double)y)) < kd) {
       st[1]++;
       double ddx, ddy;
-      double v = bicubic<double>(Pc, (double)x, (double)y, ddx, ddy, st + 2);
+      double v = bicubic<double>(Pc, (double)x, (double)y, ddx, ddy, st + 2, kd);
       dx = (float)ddx;
       dy = (float)ddy;
       return (float)v;
@@ -278,8 +283,9 @@ template <typename R>
 __device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, R& dx, R& dy, R& dz, int* st) {
   st[0]++;
   if constexpr (std::is_same<R, float>::value) {
-    if (fabs((double)x - rint((double)x)) < KNOT_DELTA || fabs((double)y - rint((double)y)) < KNOT_DELTA ||
-        fabs((double)z - rint((double)z)) < KNOT_DELTA) {
+    const double kd = P.knot_delta;
+    if (fabs((double)x - rint((double)x)) < kd || fabs((double)y - rint((double)y)) < kd ||
+        fabs((double)z - rint((double)z)) < kd) {
       st[1]++;
       double ddx, ddy, ddz;
       double v = tricubic<double>(P, t, (double)x, (double)y, (double)z, ddx, ddy, ddz, st + 2);
@@ -322,33 +328,36 @@ __device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, 
 }
 
 // ---------------------------------------------------------------------------
-// Force / virial accumulation of one lane.  A gradient g = dE/dr_ab on the
-// relative vector r_ab = x_b - x_a gives F_a += g, F_b -= g and
-// W -= r_ab (x) g; the two atoms the lane owns are kept in registers.
+// Force / virial accumulation of one lane in type A (FP64, or FP32 in single
+// precision).  A gradient g = dE/dr_ab on the relative vector r_ab = x_b - x_a
+// gives F_a += g, F_b -= g and W -= r_ab (x) g; the two atoms the lane owns are
+// kept in registers.
 // ---------------------------------------------------------------------------
-struct Acc {
+template <typename A_>
+struct AccT {
+  using A = A_;
   int st[4];         // spline evaluations, of which in FP64 near a knot
   int i, j;
-  double fi[3], fj[3];
-  double W[6];
-  double* F;
-  __device__ void init(double* F_, int i_, int j_) {
+  A fi[3], fj[3];
+  A W[6];
+  A* F;
+  __device__ void init(A* F_, int i_, int j_) {
     F = F_; i = i_; j = j_;
     st[0] = st[1] = st[2] = st[3] = 0;
     for (int c = 0; c < 3; ++c) fi[c] = fj[c] = 0;
     for (int c = 0; c < 6; ++c) W[c] = 0;
   }
-  __device__ void force(int a, double gx, double gy, double gz) {
+  __device__ void force(int a, A gx, A gy, A gz) {
     if (a == i) { fi[0] += gx; fi[1] += gy; fi[2] += gz; }
     else if (a == j) { fj[0] += gx; fj[1] += gy; fj[2] += gz; }
     else { atomic_add(&F[3 * a], gx); atomic_add(&F[3 * a + 1], gy); atomic_add(&F[3 * a + 2], gz); }
   }
   template <typename R>
-  __device__ void vec(int a, int b, V3<R> r, V3<R> g, double scale = 1.0) {
-    double gx = scale * (double)g.x, gy = scale * (double)g.y, gz = scale * (double)g.z;
+  __device__ void vec(int a, int b, V3<R> r, V3<R> g, A scale = 1) {
+    A gx = scale * (A)g.x, gy = scale * (A)g.y, gz = scale * (A)g.z;
     force(a, gx, gy, gz);
     force(b, -gx, -gy, -gz);
-    double rx = r.x, ry = r.y, rz = r.z;
+    A rx = r.x, ry = r.y, rz = r.z;
     W[0] -= rx * gx; W[1] -= ry * gy; W[2] -= rz * gz;
     W[3] -= rx * gy; W[4] -= rx * gz; W[5] -= ry * gz;
   }
@@ -357,6 +366,11 @@ struct Acc {
     if (j >= 0) for (int c = 0; c < 3; ++c) if (fj[c] != 0) atomic_add(&F[3 * j + c], fj[c]);
   }
 };
+
+// Force array a kernel accumulates into: FP64, or the FP32 sums of single precision.
+template <typename A> __device__ __forceinline__ A* fbuf(const Dev& D);
+template <> __device__ __forceinline__ double* fbuf<double>(const Dev& D) { return D.F; }
+template <> __device__ __forceinline__ float* fbuf<float>(const Dev& D) { return D.F32; }
 
 // Block reduction of `nv` doubles per thread into global accumulators.
 template <int NV>
@@ -478,7 +492,7 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
     }
   }
   R Pv = 0, dPC = 0, dPH = 0;
-  if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH, st);
+  if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH, st, P.knot_delta);
   e.NC = NC; e.NH = NH; e.N = N; e.S = S; e.P = Pv; e.dPC = dPC; e.dPH = dPH;
   e.p = (R)1 / xsqrt((R)1 + S + Pv);
   e.conj = conj;
@@ -487,9 +501,9 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
 
 // Reverse pass of one end.  Gp = dE/dp, GN = dE/dN_co from outside the end,
 // Gconj = dE/d(conjugation sum of this end).  Returns dE/dr_co in gco.
-template <typename R>
+template <typename R, typename AC>
 __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, int so, V3<R> rco, R rlen, R rlam,
-                        bool bstar, const EndF<R>& e, R Gp, R GN, R Gconj, V3<R>& gco, Acc& acc) {
+                        bool bstar, const EndF<R>& e, R Gp, R GN, R Gconj, V3<R>& gco, AC& acc) {
   int n = D.sn[c];
   R GS = (R)-0.5 * e.p * e.p * e.p * Gp;
   R GNt = GN + GS * e.SdN;
@@ -547,9 +561,9 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
 // sums of the pi^dh term (1 - cos^2) w_ik w_jl s_i s_j and of the torsion
 // energy w_ik w_ij w_jl s_i s_j V(omega); with rev, the reverse pass given
 // GSdh = dE/d(sum) and the torsion's own derivatives.
-template <typename R>
+template <typename R, typename AC>
 __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, R wij, bool tors, bool rev,
-                         R GSdh, R& Sdh, R& Et, V3<R>& gij, R& Gwij, Acc& acc) {
+                         R GSdh, R& Sdh, R& Et, V3<R>& gij, R& Gwij, AC& acc) {
   int ni = D.sn[i], nj = D.sn[j];
   V3<R> rji = -rij;
   for (int q = 0; q < ni; ++q) {
@@ -649,7 +663,7 @@ __device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R
     if (f.dh) {
       V3<R> dummy = {0, 0, 0};
       R Et = 0, Gwij = 0;
-      Acc none;   // forward only: nothing is accumulated
+      AccT<double> none;   // forward only: nothing is accumulated
       none.st[0] = none.st[1] = 0;
       dihedral(P, D, i, j, rij, r, (R)0, false, false, (R)0, f.Sdh, Et, dummy, Gwij, none);
     }
@@ -660,9 +674,9 @@ __device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R
 // Reverse pass of a bond order for dE/db = Gb, from its forward state.
 // With dihedral_done, the caller takes the pi^dh part of the dihedral loop
 // (dE/dSdh = Gb T_ij) together with its own pass over the same loop.
-template <typename R>
+template <typename R, typename AC>
 __device__ void bond_order_rev(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar,
-                               const BondFwd<R>& f, R Gb, V3<R>& gij, Acc& acc, bool dihedral_done = false) {
+                               const BondFwd<R>& f, R Gb, V3<R>& gij, AC& acc, bool dihedral_done = false) {
   R GNij = Gb * (f.Fij + f.Sdh * f.dTa), GNji = Gb * (f.Fji + f.Sdh * f.dTb), GNc = Gb * (f.dFc + f.Sdh * f.dTc);
   if (f.dh && !dihedral_done) {
     R s2 = 0, Et = 0, Gwij = 0;
@@ -918,6 +932,8 @@ __global__ void k_zero(Dev D) {
   if (D.skip && *D.skip) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   for (int k = t; k < 3 * D.n; k += gridDim.x * blockDim.x) D.F[k] = 0;
+  if (D.F32)
+    for (int k = t; k < 3 * D.n; k += gridDim.x * blockDim.x) D.F32[k] = 0;
   if (t < NSLOT * A_N) D.acc[t] = 0;
   if (D.nsys > 1)
     for (int k = t; k < D.nsys * A_N; k += gridDim.x * blockDim.x) D.sys_acc[k] = 0;
@@ -925,14 +941,31 @@ __global__ void k_zero(Dev D) {
   if (t < NSEG) D.qcount[t * QSTRIDE] = 0;
 }
 
-__device__ __forceinline__ void minimg(const SysBox& B, double& dx, double& dy, double& dz) {
-  if (B.per[0]) dx -= B.L[0] * rint(dx * B.invL[0]);
-  if (B.per[1]) dy -= B.L[1] * rint(dy * B.invL[1]);
-  if (B.per[2]) dz -= B.L[2] * rint(dz * B.invL[2]);
+// Single precision: add the FP32 force sums into the FP64 forces the
+// integrator and the caller read, and clear them for the next evaluation.
+__global__ void k_fold32(Dev D) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 3 * D.n; k += gridDim.x * blockDim.x) {
+    float f = D.F32[k];
+    D.F32[k] = 0.0f;
+    D.F[k] += (double)f;
+  }
+}
+
+__device__ __forceinline__ double xrint(double a) { return rint(a); }
+__device__ __forceinline__ float xrint(float a) { return rintf(a); }
+template <typename T>
+__device__ __forceinline__ void minimg(const SysBox& B, T& dx, T& dy, T& dz) {
+  if (B.per[0]) dx -= (T)B.L[0] * xrint(dx * (T)B.invL[0]);
+  if (B.per[1]) dy -= (T)B.L[1] * xrint(dy * (T)B.invL[1]);
+  if (B.per[2]) dz -= (T)B.L[2] * xrint(dz * (T)B.invL[2]);
 }
 
 // Exact short list, weights and coordination; species-bucketed bond list.
+// S (single precision): relative vectors from FP32 positions, lengths,
+// weights and coordination sums in FP32.
+template <bool S>
 __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restrict__ Pp) {
+  using T = typename std::conditional<S, float, double>::type;
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   // SG lanes per atom: lane `sub` of the group takes intermediate entries
@@ -955,7 +988,7 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   const SysBox& B = box_of(D, live ? i : 0);
   int mmax = wave_max(m);
   int cnt = 0;                // valid entries of atom i so far (uniform in the group)
-  double NC = 0, NH = 0;      // partial sums of this lane
+  T NC = 0, NH = 0;           // partial sums of this lane
   int bpos[ICAP / SG], bcls[ICAP / SG];   // this lane's bonds j > i: slot and class (-1: none)
 #pragma unroll
   for (int k = 0; k < ICAP / SG; ++k) {
@@ -969,16 +1002,17 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
     if (live && e < m) {
       j = D.in_e[i * ICAP + e];
       double4 xj = D.x[j];
-      dx = xj.x - xi.x; dy = xj.y - xi.y; dz = xj.z - xi.z;
-      minimg(B, dx, dy, dz);
-      double r2 = dx * dx + dy * dy + dz * dz;
+      T tx = (T)xj.x - (T)xi.x, ty = (T)xj.y - (T)xi.y, tz = (T)xj.z - (T)xi.z;
+      minimg(B, tx, ty, tz);
+      T r2 = tx * tx + ty * ty + tz * tz;
       int sj = __double2int_rn(xj.w);
       p = si + sj;
       if (r2 < P.R2[p] * P.R2[p]) {
         ok = true;
-        r = sqrt(r2);
-        w = cutw<double>(P, p, r, dw);
-        if (sj == 0) NC += w; else NH += w;
+        T rt = xsqrt(r2), dwt;
+        T wt = cutw<T>(P, p, rt, dwt);
+        dx = tx; dy = ty; dz = tz; r = rt; w = wt; dw = dwt;
+        if (sj == 0) NC += wt; else NH += wt;
       }
     }
     unsigned long long bal = __ballot(ok) & gmask;
@@ -1000,8 +1034,8 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   if (live && sub == 0) {
     if (cnt > SCAP) atomicOr(D.flags, F_OV_SHORT);
     D.sn[i] = min(cnt, SCAP);
-    D.NCt[i] = NC;
-    D.NHt[i] = NH;
+    D.NCt[i] = (double)NC;
+    D.NHt[i] = (double)NH;
   }
   // species-bucketed bond list: lane offsets by wave prefix sums, one LDS
   // add per wavefront and class, one global reservation per block and class
@@ -1063,8 +1097,9 @@ __device__ __forceinline__ PathInfo decode_path(const Dev& D, int i, int code) {
 // Gradient of E with respect to the path bonds, given dE/dprod.  `half`
 // halves the contribution to every atom except the path start (full-list LJ
 // visits each pair from both ends).
-template <typename R>
-__device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_all, double scale_start, Acc& acc) {
+template <typename R, typename AC>
+__device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_all, double scale_start, AC& acc) {
+  using A = typename AC::A;
   R w[3], dw[3], rl[3];
   V3<R> rv[3];
   for (int b = 0; b < pi.len; ++b) {
@@ -1074,33 +1109,34 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
     w[b] = (R)wd.x;
     dw[b] = (R)wd.y;
   }
+  const A sall = (A)scale_all;
   for (int b = 0; b < pi.len; ++b) {
     if (dw[b] == (R)0) continue;
     R others = 1;
     for (int c = 0; c < pi.len; ++c) if (c != b) others *= w[c];
     V3<R> g = (GP * others * dw[b] / rl[b]) * rv[b];
-    double gx = g.x, gy = g.y, gz = g.z;
+    A gx = g.x, gy = g.y, gz = g.z;
     int a = pi.at[b], c = pi.at[b + 1];
-    double sa = (b == 0) ? scale_start : scale_all;
+    A sa = (b == 0) ? (A)scale_start : sall;
     acc.force(a, sa * gx, sa * gy, sa * gz);
-    if (b + 1 < pi.len || scale_all == 1.0) acc.force(c, -scale_all * gx, -scale_all * gy, -scale_all * gz);
-    double rx = rv[b].x, ry = rv[b].y, rz = rv[b].z;
-    acc.W[0] -= scale_all * rx * gx; acc.W[1] -= scale_all * ry * gy; acc.W[2] -= scale_all * rz * gz;
-    acc.W[3] -= scale_all * rx * gy; acc.W[4] -= scale_all * rx * gz; acc.W[5] -= scale_all * ry * gz;
+    if (b + 1 < pi.len || scale_all == 1.0) acc.force(c, -sall * gx, -sall * gy, -sall * gz);
+    A rx = rv[b].x, ry = rv[b].y, rz = rv[b].z;
+    acc.W[0] -= sall * rx * gx; acc.W[1] -= sall * ry * gy; acc.W[2] -= sall * rz * gz;
+    acc.W[3] -= sall * rx * gy; acc.W[4] -= sall * rx * gz; acc.W[5] -= sall * ry * gz;
   }
 }
 
 // REBO pair + bond order + torsion, one lane per bond (Alg. 1 and 2 merged).
-template <typename R>
+template <typename R, typename A>
 __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   int n0 = D.bcount[0], n1 = D.bcount[1], n2 = D.bcount[2];
   n0 = min(n0, D.bcap); n1 = min(n1, D.bcap); n2 = min(n2, D.bcap);
   int total = n0 + n1 + n2;
-  double er = 0, et = 0;
-  Acc acc;
-  acc.init(D.F, -1, -1);
+  A er = 0, et = 0;
+  AccT<A> acc;
+  acc.init(fbuf<A>(D), -1, -1);
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
     int seg = g < n0 ? 0 : (g < n0 + n1 ? 1 : 2);
     int off = g - (seg == 0 ? 0 : (seg == 1 ? n0 : n0 + n1));
@@ -1114,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
     int p = seg;
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
-    double er0 = er, et0 = et, W0[6];
+    A er0 = er, et0 = et, W0[6];
     for (int c = 0; c < 6; ++c) W0[c] = acc.W[c];
     V3<R> gij = {0, 0, 0};
     R Gr = 0;
@@ -1137,27 +1173,28 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
       R b = bond_order_fwd(P, D, i, j, rij, r, false, bf, acc.st);
       bond_order_rev(P, D, i, j, rij, r, false, bf, Gb, gij, acc, tors);
       if (tors && bf.dh) GSdh = Gb * bf.Tv;
-      er += (double)(wij * (VR - b * VA));
+      er += (A)(wij * (VR - b * VA));
       Gr += dwij * (VR - b * VA) + wij * (dVR - b * dVA);
     }
     if (tors) {
       R Sdh = 0, Et = 0, Gwij = 0;
       dihedral(P, D, i, j, rij, r, wij, true, true, GSdh, Sdh, Et, gij, Gwij, acc);
-      et += (double)Et;
+      et += (A)Et;
       Gr += Gwij * dwij;
     }
     gij = gij + (Gr / r) * rij;
     acc.vec(i, j, rij, gij);
     acc.flush();
     if (D.nsys > 1) {
-      double dv[9] = {er - er0, et - et0, 0.0};
-      for (int c = 0; c < 6; ++c) dv[3 + c] = acc.W[c] - W0[c];
+      double dv[9] = {(double)(er - er0), (double)(et - et0), 0.0};
+      for (int c = 0; c < 6; ++c) dv[3 + c] = (double)(acc.W[c] - W0[c]);
       int sid = sys_of(D, i);
       for (int q = 0; q < 9; ++q)
         if (dv[q] != 0) atomic_add(&D.sys_acc[(size_t)sid * A_N + A_EREBO + q], dv[q]);
     }
   }
-  double v15[15] = {er, et, 0.0, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5], 0.0, 0.0, 0.0, 0.0,
+  double v15[15] = {(double)er, (double)et, 0.0, (double)acc.W[0], (double)acc.W[1], (double)acc.W[2],
+                    (double)acc.W[3], (double)acc.W[4], (double)acc.W[5], 0.0, 0.0, 0.0, 0.0,
                     (double)acc.st[0], (double)acc.st[1]};
   block_reduce_add<15>(v15, D.acc + A_EREBO);  // A_EREBO .. A_SPL64
 }
@@ -1242,7 +1279,7 @@ struct LjWaves {
   static constexpr int value = std::is_same<R, float>::value ? 6 : 5;
 };
 
-template <typename R>
+template <typename R, typename A>
 __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R>::value, 8))) void k_lj(
     Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
@@ -1264,8 +1301,8 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
   int wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   unsigned long long below = lanes_below();
-  double e = 0;
-  double fi[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
+  A e = 0;
+  A fi[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
   unsigned long long n_in = 0, n_c0 = 0;
   if (i < D.n) {
     double4 xi = D.x[i];
@@ -1363,10 +1400,11 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
         j = (int)(ent & 0x7FFFFFFu);
         code = (int)(ent >> 27);
         double4 xj = D.x[j];
-        double dx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
-        double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
-        double dz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
-        double r2 = dx * dx + dy * dy + dz * dz;
+        // relative vector in A: single precision forms it from FP32 positions
+        A dx = (A)xj.x - (A)xi.x + (A)((code / 9 - 1) * B.L[0]);
+        A dy = (A)xj.y - (A)xi.y + (A)(((code / 3) % 3 - 1) * B.L[1]);
+        A dz = (A)xj.z - (A)xi.z + (A)((code % 3 - 1) * B.L[2]);
+        A r2 = dx * dx + dy * dy + dz * dz;
         int p = si + __double2int_rn(xj.w);
         if (r2 < P.rc2[p]) {
           if (i < j) ++n_in;
@@ -1394,15 +1432,15 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
             }
           }
           if (plain) {
-            // pair arithmetic in R on the FP64 relative vector; FP64
-            // accumulation (energy and virial halved once, at the end)
+            // pair arithmetic in R on the relative vector; accumulation in A
+            // (energy and virial halved once, at the end)
             R V, g;
             lj_pair_r2<R>(P, p, (R)r2, V, g);   // dE/dr_ij vector = g * d
-            e += (double)V;
+            e += (A)V;
             R fx = g * (R)dx, fy = g * (R)dy, fz = g * (R)dz;
-            fi[0] += (double)fx; fi[1] += (double)fy; fi[2] += (double)fz;
-            W[0] += (double)(fx * (R)dx); W[1] += (double)(fy * (R)dy); W[2] += (double)(fz * (R)dz);
-            W[3] += (double)(fy * (R)dx); W[4] += (double)(fz * (R)dx); W[5] += (double)(fz * (R)dy);
+            fi[0] += (A)fx; fi[1] += (A)fy; fi[2] += (A)fz;
+            W[0] += (A)(fx * (R)dx); W[1] += (A)(fy * (R)dy); W[2] += (A)(fz * (R)dz);
+            W[3] += (A)(fy * (R)dx); W[4] += (A)(fz * (R)dx); W[5] += (A)(fz * (R)dy);
           }
         }
       }
@@ -1417,13 +1455,13 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
   if (ndq > 0) flush_deferred(D, dq[wv], ndq);
   // reduce the force on atom i across the wavefront
   for (int c = 0; c < 3; ++c) {
-    double s = fi[c];
+    A s = fi[c];
     for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0 && i < D.n && s != 0) atomic_add(&D.F[3 * i + c], s);
+    if (lane == 0 && i < D.n && s != 0) atomic_add(&fbuf<A>(D)[3 * i + c], s);
   }
   // each pair is seen from both ends: half the energy, minus half the virial
-  double v9[9] = {0.5 * e, -0.5 * W[0], -0.5 * W[1], -0.5 * W[2], -0.5 * W[3], -0.5 * W[4], -0.5 * W[5],
-                  (double)n_in, (double)n_c0};
+  double v9[9] = {0.5 * (double)e, -0.5 * (double)W[0], -0.5 * (double)W[1], -0.5 * (double)W[2],
+                  -0.5 * (double)W[3], -0.5 * (double)W[4], -0.5 * (double)W[5], (double)n_in, (double)n_c0};
   if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v9, A_ELJ, i < D.n);
   block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
 }
@@ -1431,7 +1469,7 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
 // Deferred LJ pairs (0 < C_ij < 1, or inside the S_r range where the modified
 // bond order b* enters through S_b): energy and the full gradient, including
 // the path atoms of C_ij and, where 0 < t_b < 1, the b* neighbourhood.
-template <typename R>
+template <typename R, typename A>
 __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
@@ -1443,72 +1481,74 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
   }
   __syncthreads();
   int nq = seg_start[NSEG];
-  double e = 0;
-  Acc acc;
-  acc.init(D.F, -1, -1);
+  A e = 0;
+  AccT<A> acc;
+  acc.init(fbuf<A>(D), -1, -1);
   unsigned long long ndsb = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += gridDim.x * blockDim.x) {
     int g = 0;
     while (seg_start[g + 1] <= t) ++g;
     int4 qe = D.q[(size_t)g * D.qcap + (t - seg_start[g])];
-    double W0[6];
+    A W0[6];
     for (int c = 0; c < 6; ++c) W0[c] = acc.W[c];
     int i = qe.x, j = qe.y, code = qe.z, pcode = qe.w;
     double4 xi = D.x[i], xj = D.x[j];
     const SysBox& B = box_of(D, i);
-    double dx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
-    double dy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
-    double dz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
+    // LJ part, C_ij and the switches in A (FP64, or FP32 in single precision)
+    A dx = (A)xj.x - (A)xi.x + (A)((code / 9 - 1) * B.L[0]);
+    A dy = (A)xj.y - (A)xi.y + (A)(((code / 3) % 3 - 1) * B.L[1]);
+    A dz = (A)xj.z - (A)xi.z + (A)((code % 3 - 1) * B.L[2]);
     int p = __double2int_rn(xi.w) + __double2int_rn(xj.w);
-    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    A r = xsqrt(dx * dx + dy * dy + dz * dz);
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
-    double V, dV;
-    lj_pair<double>(P, p, r, V, dV);
-    double prod = 0;
+    A V, dV;
+    lj_pair<A>(P, p, r, V, dV);
+    A prod = 0;
     PathInfo pi;
     pi.len = 0;
     if (pcode) {
       pi = decode_path(D, i, pcode);
       prod = 1;
-      for (int b = 0; b < pi.len; ++b) prod *= D.sw[pi.at[b] * SCAP + pi.slot[b]].x;
+      for (int b = 0; b < pi.len; ++b) prod *= (A)D.sw[pi.at[b] * SCAP + pi.slot[b]].x;
     }
-    double C = 1.0 - prod;
-    double dSr;
-    double Sr = Sw((r - P.sigma[p]) * P.inv_rlj[p], dSr);
-    dSr *= P.inv_rlj[p];
+    A C = (A)1 - prod;
+    A dSr;
+    A Sr = Sw((r - (A)P.sigma[p]) * (A)P.inv_rlj[p], dSr);
+    dSr *= (A)P.inv_rlj[p];
     V3<R> rij = {(R)dx, (R)dy, (R)dz};
     V3<R> gij = {0, 0, 0};
-    double Sb = 1.0, dSb = 0.0;
+    A Sb = 1, dSb = 0;
     BondFwd<R> bf;
-    if (Sr > 0.0) {
+    if (Sr > (A)0) {
       R bs = bond_order_fwd(P, D, i, j, rij, (R)r, true, bf, acc.st);
-      double inv_b = 1.0 / (P.bmax[p] - P.bmin[p]);
-      Sb = Sw(((double)bs - P.bmin[p]) * inv_b, dSb);
+      A inv_b = (A)(1.0 / (P.bmax[p] - P.bmin[p]));
+      Sb = Sw(((A)bs - (A)P.bmin[p]) * inv_b, dSb);
       dSb *= inv_b;
     }
-    double Qf = Sr * Sb + 1.0 - Sr;
+    A Qf = Sr * Sb + (A)1 - Sr;
     e += Qf * C * V;
-    double Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
-    if (dSb != 0.0) {   // the reverse pass reuses the forward state
+    A Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
+    if (dSb != (A)0) {   // the reverse pass reuses the forward state
       ++ndsb;
       R Gb = (R)(Sr * dSb * C * V);
       bond_order_rev(P, D, i, j, rij, (R)r, true, bf, Gb, gij, acc);
     }
-    if (prod > 0.0) path_grad<double>(D, pi, -Qf * V, 1.0, 1.0, acc);
+    if (prod > (A)0) path_grad<A>(D, pi, -Qf * V, 1.0, 1.0, acc);
     gij = gij + (R)(Gr / r) * rij;
     acc.vec(i, j, rij, gij);
     acc.flush();
     if (D.nsys > 1) {
-      double dv[7] = {Qf * C * V};
-      for (int c = 0; c < 6; ++c) dv[1 + c] = acc.W[c] - W0[c];
+      double dv[7] = {(double)(Qf * C * V)};
+      for (int c = 0; c < 6; ++c) dv[1 + c] = (double)(acc.W[c] - W0[c]);
       int sid = sys_of(D, i);
       for (int q = 0; q < 7; ++q)
         if (dv[q] != 0) atomic_add(&D.sys_acc[(size_t)sid * A_N + A_ELJ + q], dv[q]);
     }
   }
   __syncthreads();
-  double v13[13] = {e, acc.W[0], acc.W[1], acc.W[2], acc.W[3], acc.W[4], acc.W[5], 0.0, 0.0, (double)ndsb, 0.0,
+  double v13[13] = {(double)e, (double)acc.W[0], (double)acc.W[1], (double)acc.W[2], (double)acc.W[3],
+                    (double)acc.W[4], (double)acc.W[5], 0.0, 0.0, (double)ndsb, 0.0,
                     (double)acc.st[0], (double)acc.st[1]};
   block_reduce_add<13>(v13, D.acc + A_ELJ);  // A_ELJ .. A_SPL64
 }
@@ -1726,6 +1766,8 @@ struct airebo_ctx {
   size_t c_q = 0;
   double* F = nullptr;
   size_t c_F = 0;
+  float* F32 = nullptr;   // single precision only
+  size_t c_F32 = 0;
   double* acc = nullptr;
   size_t c_acc = 0;
   unsigned long long* stats = nullptr;
@@ -1796,7 +1838,8 @@ namespace {
 
 int check_options(const airebo_options& o) {
   if (!(o.skin > 0.0 && o.skin < 5.0)) return fail(AIREBO_E_ARG, "skin must be in (0, 5) A");
-  if (o.precision != AIREBO_FP64 && o.precision != AIREBO_MIXED) return fail(AIREBO_E_ARG, "unknown precision");
+  if (o.precision != AIREBO_FP64 && o.precision != AIREBO_MIXED && o.precision != AIREBO_SINGLE)
+    return fail(AIREBO_E_ARG, "unknown precision");
   if (o.term_mask < 0 || o.term_mask > 7) return fail(AIREBO_E_ARG, "bad term mask");
   if (o.lj_cap < 0) return fail(AIREBO_E_ARG, "bad lj_cap");
   auto okb = [](int b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; };
@@ -1812,6 +1855,7 @@ int ctx_create_impl(const DevParams& P, const std::vector<double>& tri, const ai
   airebo_ctx* c = new airebo_ctx();
   c->opt = o;
   c->P = P;
+  c->P.knot_delta = o.precision == AIREBO_SINGLE ? -1.0 : KNOT_DELTA;   // single: FP32 everywhere
   hipError_t e = hipSetDevice(o.device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->dtri, tri.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(c->dtri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -1886,7 +1930,7 @@ void airebo_ctx_free(airebo_ctx_t c) {
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->xsort, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
                   c->cell_atoms, c->lj_n, c->lj_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
-                  c->bcount, c->bonds, c->qcount, c->q, c->F, c->acc, c->dsys, c->atom_sys, c->sys_acc,
+                  c->bcount, c->bonds, c->qcount, c->q, c->F, c->F32, c->acc, c->dsys, c->atom_sys, c->sys_acc,
                   c->stats, c->flags, c->step, c->hx, c->hs};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -1967,6 +2011,13 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   size_t qcap = (8 * N + 1024 * NSEG) / NSEG;   // per segment
   rc |= grow(c->q, c->c_q, qcap * NSEG);
   rc |= grow(c->F, c->c_F, 3 * N);
+  if (c->opt.precision == AIREBO_SINGLE) {
+    size_t had = c->c_F32;
+    rc |= grow(c->F32, c->c_F32, 3 * N);
+    // the FP32 sums start at zero; every evaluation leaves them at zero
+    if (!rc && c->c_F32 != had && hipMemsetAsync(c->F32, 0, c->c_F32 * sizeof(float), s) != hipSuccess)
+      rc |= fail(AIREBO_E_DEVICE, "clearing the FP32 force sums failed");
+  }
   rc |= grow(c->acc, c->c_acc, NSLOT * A_N);
   rc |= grow(c->stats, c->c_st, S_N);
   rc |= grow(c->flags, c->c_fl, 4);
@@ -1992,7 +2043,7 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   D.lj_e = c->lj_e; D.in_n = c->in_n; D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
   D.NCt = c->NCt; D.NHt = c->NHt; D.bcap = (int)bcap; D.bcount = c->bcount; D.bonds = c->bonds;
   D.qcap = (int)qcap; D.qcount = c->qcount;
-  D.q = c->q; D.F = c->F; D.acc = c->acc; D.stats = c->stats; D.flags = c->flags; D.step = c->step;
+  D.q = c->q; D.F = c->F; D.F32 = c->F32; D.acc = c->acc; D.stats = c->stats; D.flags = c->flags; D.step = c->step;
   return 0;
 }
 
@@ -2021,16 +2072,21 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
                        4096)),
          dim3(256), s, D);
   int sblk = c->opt.short_block ? c->opt.short_block : 1024;
-  LAUNCH(c, K_SHORT, k_short, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), s, D, P);   // 16 lanes per atom
+  const int prec = c->opt.precision;
+  const bool single = prec == AIREBO_SINGLE;
+  if (single) LAUNCH(c, K_SHORT, k_short<true>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), s, D, P);
+  else LAUNCH(c, K_SHORT, k_short<false>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), s, D, P);  // 16 lanes per atom
   int bblk = c->opt.bond_block ? c->opt.bond_block : 64;
   int nb = c->opt.bond_grid ? c->opt.bond_grid : std::min(blocks((int64_t)D.n * 2, bblk), 8192);
   int qblk = c->opt.defer_block ? c->opt.defer_block : 64;
-  bool mixed = c->opt.precision == AIREBO_MIXED;
   bool bonded = mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION);
+  // arithmetic type R, accumulation type A: FP64 (double, double), mixed
+  // (float, double), single (float, float)
   if (mask & AIREBO_TERM_LJ) {
     dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
-    if (mixed) LAUNCH(c, K_LJ, k_lj<float>, glj, dim3(LJ_BLOCK), s, D, P);
-    else LAUNCH(c, K_LJ, k_lj<double>, glj, dim3(LJ_BLOCK), s, D, P);
+    if (prec == AIREBO_MIXED) LAUNCH(c, K_LJ, (k_lj<float, double>), glj, dim3(LJ_BLOCK), s, D, P);
+    else if (single) LAUNCH(c, K_LJ, (k_lj<float, float>), glj, dim3(LJ_BLOCK), s, D, P);
+    else LAUNCH(c, K_LJ, (k_lj<double, double>), glj, dim3(LJ_BLOCK), s, D, P);
   }
   // The LJ kernel fills the device on its own (a wavefront per atom); the
   // bonded kernel (a lane per bond) and the deferred b* pairs (a lane per
@@ -2045,20 +2101,23 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
     sb = c->side;
   }
   if (bonded) {
-    if (mixed) LAUNCH(c, K_BOND, k_bond<float>, dim3(nb), dim3(bblk), sb, D, P, mask);
-    else LAUNCH(c, K_BOND, k_bond<double>, dim3(nb), dim3(bblk), sb, D, P, mask);
+    if (prec == AIREBO_MIXED) LAUNCH(c, K_BOND, (k_bond<float, double>), dim3(nb), dim3(bblk), sb, D, P, mask);
+    else if (single) LAUNCH(c, K_BOND, (k_bond<float, float>), dim3(nb), dim3(bblk), sb, D, P, mask);
+    else LAUNCH(c, K_BOND, (k_bond<double, double>), dim3(nb), dim3(bblk), sb, D, P, mask);
   }
   if (mask & AIREBO_TERM_LJ) {
     // one lane per expected deferred pair (about 3 per atom in dense melts), so
     // that the latency-bound b* work is spread over many wavefronts
     dim3 gq(std::min(blocks(4 * (int64_t)D.n, qblk), 16384));
-    if (mixed) LAUNCH(c, K_BSTAR, k_bstar<float>, gq, dim3(qblk), s, D, P);
-    else LAUNCH(c, K_BSTAR, k_bstar<double>, gq, dim3(qblk), s, D, P);
+    if (prec == AIREBO_MIXED) LAUNCH(c, K_BSTAR, (k_bstar<float, double>), gq, dim3(qblk), s, D, P);
+    else if (single) LAUNCH(c, K_BSTAR, (k_bstar<float, float>), gq, dim3(qblk), s, D, P);
+    else LAUNCH(c, K_BSTAR, (k_bstar<double, double>), gq, dim3(qblk), s, D, P);
   }
   if (fork) {
     (void)hipEventRecord(c->ev_join, c->side);
     (void)hipStreamWaitEvent(s, c->ev_join, 0);
   }
+  if (single) LAUNCH(c, K_FOLD32, k_fold32, dim3(std::min(blocks(3 * (int64_t)D.n, 256), 4096)), dim3(256), s, D);
 }
 
 int check_flags(airebo_ctx* c, int flags) {

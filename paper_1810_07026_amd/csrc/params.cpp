@@ -191,6 +191,7 @@ bool build_params_text(const char* text, size_t len, DevParams& P, double* tri, 
     if (P.rc[p] - P.lj_sw < P.rljmax[p]) { err = "LJ switch region overlaps the bond-order switch"; return false; }
   }
   P.r_conn = 3.0 * P.R2max;
+  P.knot_delta = 1e-3;
   for (int p = 0; p < 3; ++p)
     if (P.rljmax[p] >= P.r_conn) { err = "LJ bond-order switch must lie inside three REBO bond lengths"; return false; }
 

@@ -2,16 +2,18 @@
 
 * The 32,012-atom polyethylene melt (106 x C100H202, the headline workload):
   GPU energy, every force and the virial against one full oracle evaluation,
-  FP64 at the FP64 bar and mixed precision at its own bar.
+  FP64 at the FP64 bar, mixed and single precision at their own bars.
 * The 512-system batch (301,512 atoms) with the launch shapes the autotuner
   cached for it: the smallest and the largest system of each family,
   taken whole from the batched result, against the oracle on that system
-  alone, FP64 and mixed.
+  alone, FP64, mixed and single.
 
 Bars: the FP64 bar of the parity tests (energy 1e-12 relative, max force
 error 1e-10 of the RMS force, virial 1e-10 relative; only summation order
 and last-bit differences of the math libraries separate the two sides) and
-the mixed bar derived there (force 1e-4 of the RMS force, energy 1e-6).
+the mixed bar derived there (force 1e-4 of the RMS force, energy 1e-6) and
+the single bar derived there (the mixed force bar plus absolute terms for
+FP32 position rounding and FP32 force sums; energy 1e-5).
 """
 import math
 
@@ -24,12 +26,27 @@ pytestmark = pytest.mark.gpu
 
 TOL_E, TOL_F, TOL_W = 1e-12, 1e-10, 1e-10
 TOL_MIXED_F, TOL_MIXED_E = 1e-4, 1e-6
+TOL_SINGLE_E = 1e-5
+U32 = 2.0 ** -24
 
 
-def check(e, f, w, eo, fo, wo, fp64, label):
+def tol_single_f(x, rms):
+    """Largest per-atom force error (eV/A) of single precision: FP32 term
+    arithmetic (the mixed bar), rounding of coordinates up to max |x| through
+    a per-atom force constant of 200 eV/A^2, and FP32 sums of ~200 terms of
+    up to 30 eV/A (derivation beside the single-precision parity tests)."""
+    X = float(np.abs(x).max())
+    return TOL_MIXED_F * rms + 200.0 * 2.0 * math.sqrt(3.0) * X * U32 + 200.0 * 30.0 * U32
+PRECS = {"fp64": 0, "mixed": 1, "single": 2}
+
+
+def check(e, f, w, eo, fo, wo, prec, label, x=None):
     rms = math.sqrt((fo ** 2).sum(1).mean())
     ferr = np.abs(f - fo).max() / rms
-    if fp64:
+    if prec == "single":
+        assert ferr * rms <= tol_single_f(x, rms), (label, ferr * rms, tol_single_f(x, rms))
+        assert abs(e[0] - eo[0]) <= TOL_SINGLE_E * max(abs(eo[0]), 1.0), (label, e[0], eo[0])
+    elif prec == "fp64":
         assert ferr <= TOL_F, (label, ferr)
         for t in range(4):
             assert abs(e[t] - eo[t]) <= TOL_E * max(abs(eo[t]), 1e-3 * abs(eo[0]), 1.0), (label, t, e, eo)
@@ -46,24 +63,24 @@ def melt(oracle):
     return d, oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "single"])
 def test_melt_32k_full(melt, prec):
     from paper_1810_07026_amd import airebo
     d, (eo, fo, wo) = melt
     assert len(d["species"]) == 32012
-    ctx = airebo.Context(precision=airebo.FP64 if prec == "fp64" else airebo.MIXED)
+    ctx = airebo.Context(precision=PRECS[prec])
     try:
         e, f, w = ctx.compute(d["x"], d["species"], d["box"], d["periodic"])
         e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
     finally:
         ctx.close()
-    ferr = check(e, f, w, eo, fo, wo, prec == "fp64", f"melt {prec}")
+    ferr = check(e, f, w, eo, fo, wo, prec, f"melt {prec}", d["x"])
     print(f"melt 32k {prec}: max force error / RMS force {ferr:.3g}")
-    # Newton's third law over the whole periodic system
-    assert np.abs(f.sum(0)).max() <= 1e-9 * np.abs(f).sum()
+    # Newton's third law over the whole periodic system (FP32 sums: to their rounding)
+    assert np.abs(f.sum(0)).max() <= (1e-6 if prec == "single" else 1e-9) * np.abs(f).sum()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "single"])
 def test_batch_512_full(oracle, prec):
     import torch
     from paper_1810_07026_amd import airebo, autotune
@@ -71,7 +88,7 @@ def test_batch_512_full(oracle, prec):
     n = int(d["sizes"].sum())
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     tune = autotune.lookup(autotune.workload_key(arch, n, 512, "mixed")) or {}
-    ctx = airebo.Context(precision=airebo.FP64 if prec == "fp64" else airebo.MIXED, tune=tune)
+    ctx = airebo.Context(precision=PRECS[prec], tune=tune)
     try:
         e, f, w = ctx.batch_compute(d["x"], d["species"], d["sizes"], d["boxes"], d["periodic"])
         e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
@@ -84,6 +101,6 @@ def test_batch_512_full(oracle, prec):
         for k in (min(ks, key=lambda q: d["sizes"][q]), max(ks, key=lambda q: d["sizes"][q])):
             a, b = off[k], off[k + 1]
             eo, fo, wo = oracle.compute(d["x"][a:b], d["species"][a:b], d["boxes"][k], d["periodic"][k])
-            ferr = check(e[k], f[a:b], w[k], eo, fo, wo, prec == "fp64", f"batch {prec} system {k}")
+            ferr = check(e[k], f[a:b], w[k], eo, fo, wo, prec, f"batch {prec} system {k}", d["x"][a:b])
             print(f"batch {prec} system {k} ({synth.FAMILIES[fam]}, {b - a} atoms): "
                   f"max force error / RMS {ferr:.3g}")

@@ -243,3 +243,125 @@ def test_nanotube(ctxs, mixed_ctx, oracle, nm):
     rms = math.sqrt((ref[1] ** 2).sum(1).mean())
     assert np.abs(f - ref[1]).max() / rms < TOL_MIXED_F
     assert abs(e[0] - ref[0][0]) <= TOL_MIXED_E * abs(ref[0][0])
+
+
+# ---------------------------------------------------------------------------
+# Single precision: FP32 throughout the force evaluation, from positions
+# rounded to FP32, with FP32 force sums.  Bound on max_a |dF_a| (eV/A):
+# * FP32 term arithmetic: the mixed bar, 1e-4 of the RMS force;
+# * position rounding: a coordinate of magnitude X carries up to X u
+#   (u = 2^-24), a relative vector 2 X u per component, |dr| <= 2 sqrt(3) X u;
+#   the stiffest per-atom force constant (four bonds of ~50 eV/A^2) turns it
+#   into 200 |dr| eV/A;
+# * FP32 force sums: ~200 terms per atom (LJ pairs, bond and path terms) of
+#   up to ~30 eV/A, rounding bound 200 * 30 u eV/A.
+# The last two are absolute: near-equilibrium systems (small RMS force) see
+# them at a larger fraction of their RMS force.  Energies: 1e-5 relative
+# (FP32 term arithmetic, FP32 per-lane sums of a few hundred terms).
+# ---------------------------------------------------------------------------
+TOL_SINGLE_E = 1e-5
+U32 = 2.0 ** -24
+
+
+def tol_single_f(x, rms):
+    """Bound on the largest per-atom force error (eV/A) of single precision
+    for coordinates up to max |x| and an RMS force rms."""
+    X = float(np.abs(x).max())
+    return TOL_MIXED_F * rms + 200.0 * 2.0 * math.sqrt(3.0) * X * U32 + 200.0 * 30.0 * U32
+
+
+@pytest.fixture(scope="module")
+def single_ctx():
+    from paper_1810_07026_amd import airebo
+    c = airebo.Context(precision=airebo.SINGLE)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("case", ["pe_small", "cluster", "flake", "tiled", "nanotube"])
+def test_single_error_bound(single_ctx, oracle, case):
+    if case == "pe_small":
+        d = synth.pe_small()
+    elif case == "cluster":
+        d = reactive_cluster(3, n=28)
+    elif case == "flake":
+        x, s = synth.graphene_flake(3, 3)
+        d = synth.isolated(x + np.random.default_rng(2).normal(scale=0.03, size=x.shape), s)
+    elif case == "tiled":
+        d = synth.tile(synth.pe_small(seed=synth.SEED0 + 17), (2, 2, 1))
+    else:
+        x, s, box, per = synth.nanotube(10, 10, 5)
+        d = dict(x=x + np.random.default_rng(25).normal(scale=0.04, size=x.shape), species=s, box=box, periodic=per)
+    e, f, w = run_gpu(single_ctx, d)
+    eo, fo, wo = oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
+    rms = math.sqrt((fo ** 2).sum(1).mean())
+    fabs = np.abs(f - fo).max()
+    print(f"single {case}: max force error {fabs:.3g} eV/A ({fabs / rms:.3g} of the RMS force), "
+          f"bound {tol_single_f(d['x'], rms):.3g}; energy {abs(e[0] - eo[0]) / abs(eo[0]):.3g}")
+    assert fabs < tol_single_f(d["x"], rms), fabs
+    assert abs(e[0] - eo[0]) <= TOL_SINGLE_E * max(abs(eo[0]), 1.0)
+    assert np.linalg.norm(w - wo) <= 10 * TOL_SINGLE_E * np.linalg.norm(wo) + 1e-6
+    st = single_ctx.stats()
+    assert st["spline_evals"] > 0 and st["spline_evals_fp64"] == 0   # no FP64 branch near knots
+
+
+def test_single_rounds_positions(single_ctx, mixed_ctx, oracle):
+    """Single precision forms relative vectors from FP32 positions: moving a
+    molecule far from the origin raises its force error with the coordinate
+    magnitude, while mixed precision (FP64-formed vectors) is unaffected."""
+    x, s = synth.graphene_flake(3, 3)
+    x = x + np.random.default_rng(4).normal(scale=0.03, size=x.shape)
+    x = x - x.min(0) + 2.0
+    near = dict(x=x, species=s, box=np.array([300.0, 300, 300]), periodic=np.zeros(3, np.int32))
+    far = dict(near, x=x + 250.0)
+    eo, fo, _ = oracle.compute(near["x"], s, near["box"], near["periodic"])
+    rms = math.sqrt((fo ** 2).sum(1).mean())
+    err = {}
+    for name, ctx in (("single", single_ctx), ("mixed", mixed_ctx)):
+        for where, d in (("near", near), ("far", far)):
+            err[name, where] = np.abs(run_gpu(ctx, d)[1] - fo).max() / rms
+    print({f"{a} {b}": f"{v:.3g}" for (a, b), v in err.items()})
+    assert err["single", "far"] * rms < tol_single_f(far["x"], rms)
+    assert err["single", "far"] > 3 * err["single", "near"]
+    assert err["mixed", "far"] < TOL_MIXED_F and err["mixed", "near"] < TOL_MIXED_F
+
+
+def test_single_sums_cleared(single_ctx):
+    """The FP32 force sums start from zero on every evaluation: repeated
+    evaluations agree up to the order of FP32 atomics (a stale sum would
+    double the forces), and the forces differ from FP64 at the FP32 level."""
+    from paper_1810_07026_amd import airebo
+    d = synth.pe_small()
+    f1 = run_gpu(single_ctx, d)[1]
+    f2 = run_gpu(single_ctx, d)[1]
+    rms = math.sqrt((f1 ** 2).sum(1).mean())
+    assert np.abs(f1 - f2).max() / rms < 1e-5
+    c64 = airebo.Context()
+    try:
+        f64 = run_gpu(c64, d)[1]
+    finally:
+        c64.close()
+    assert 1e-8 * rms < np.abs(f1 - f64).max() < tol_single_f(d["x"], rms)
+
+
+def test_single_nve_energy_conservation():
+    """400 steps of 0.25 fs in single precision (FP64 integrator) on the
+    248-atom PE system: the same drift bound as FP64, and each chunk of the
+    captured step starts from cleared FP32 sums."""
+    import torch
+    from paper_1810_07026_amd import airebo
+    d = synth.pe_small(seed=synth.SEED0 + 4)
+    ctx = airebo.Context(precision=airebo.SINGLE)
+    try:
+        x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+        v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+        th = ctx.nve(x, v, d["species"], d["box"], dt=0.25, nsteps=400, thermo_every=10).cpu().numpy()
+        e, f, _ = ctx.compute(x, d["species"], d["box"], d["periodic"])
+        f = f.cpu().numpy()
+    finally:
+        ctx.close()
+    drift = np.abs(th[:, 3] - th[0, 3]).max() / len(d["species"])
+    assert drift < 2e-4, drift
+    assert th[-1, 5] >= 1
+    # a fresh evaluation at the end state agrees with the last step's energy
+    assert abs(float(e[0].cpu()) - th[-1, 1]) < 1e-3 * abs(th[-1, 1]) + 1e-3

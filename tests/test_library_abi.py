@@ -23,6 +23,13 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_precision_codes_match_header():
+    src = open(os.path.join(ROOT, "include", "airebo.h")).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\bAIREBO_(FP64|MIXED|SINGLE)\s*=\s*(\d+)", src))
+    assert codes == {"FP64": airebo.FP64, "MIXED": airebo.MIXED, "SINGLE": airebo.SINGLE}
+    assert airebo.PRECISIONS == {"fp64": airebo.FP64, "mixed": airebo.MIXED, "single": airebo.SINGLE}
+
+
 def test_options_default_on_cpu():
     import ctypes
     L = airebo.load_library()
