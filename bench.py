@@ -208,7 +208,7 @@ def main():
             cpu["single_thread"] = {"value": n / (t5 - t4), "unit": "atom-steps/s", "cores": 1,
                                     "sample": f"one full FP64 force evaluation of the {n}-atom system, {t5 - t4:.1f} s"}
             rms = math.sqrt((fo ** 2).sum(1).mean())
-            ferr = {"force_rms_err_eVA": float(math.sqrt(((fg - fo) ** 2).sum(1).mean())),
+            ferr = {"force_rms_err_eVA": float(math.sqrt(((fg - fo) ** 2).sum(1).mean())), "force_rms_eVA": rms,
                     "force_rel_err_max": float(np.abs(fg - fo).max() / rms),
                     "energy_rel_err": float(abs(e0[0].item() - eo[0]) / abs(eo[0]))}
         else:
@@ -222,7 +222,7 @@ def main():
                              f"(every term touching them), {t3 - t2:.1f} s"}
             fo, fgs = fo[sel], fg[sel]
             rms = math.sqrt((fo ** 2).sum(1).mean())
-            ferr = {"force_rms_err_eVA": float(math.sqrt(((fgs - fo) ** 2).sum(1).mean())),
+            ferr = {"force_rms_err_eVA": float(math.sqrt(((fgs - fo) ** 2).sum(1).mean())), "force_rms_eVA": rms,
                     "force_rel_err_max": float(np.abs(fgs - fo).max() / rms), "sampled_atoms": len(sel)}
 
     forms = None

@@ -247,27 +247,31 @@ def test_nanotube(ctxs, mixed_ctx, oracle, nm):
 
 # ---------------------------------------------------------------------------
 # Single precision: FP32 throughout the force evaluation, from positions
-# rounded to FP32, with FP32 force sums.  Bound on max_a |dF_a| (eV/A):
+# rounded to FP32, with FP32 force sums.  Bound on max_a |dF_a| (eV/A), term
+# by term:
 # * FP32 term arithmetic: the mixed bar, 1e-4 of the RMS force;
-# * position rounding: a coordinate of magnitude X carries up to X u
-#   (u = 2^-24), a relative vector 2 X u per component, |dr| <= 2 sqrt(3) X u;
-#   the stiffest per-atom force constant (four bonds of ~50 eV/A^2) turns it
-#   into 200 |dr| eV/A;
 # * FP32 force sums: ~200 terms per atom (LJ pairs, bond and path terms) of
-#   up to ~30 eV/A, rounding bound 200 * 30 u eV/A.
-# The last two are absolute: near-equilibrium systems (small RMS force) see
-# them at a larger fraction of their RMS force.  Energies: 1e-5 relative
-# (FP32 term arithmetic, FP32 per-lane sums of a few hundred terms).
+#   up to ~30 eV/A, rounding bound 200 * 30 u eV/A (u = 2^-24);
+# * position rounding, the dominant term: the oracle evaluates it exactly,
+#   as F(x rounded to FP32) - F(x) in FP64.  A relative vector on the GPU
+#   carries at most twice the perturbation of the rounded positions (the
+#   FP32 difference of two coordinates, and the image shift added to it, are
+#   rounded once more), and the largest per-atom response to another
+#   perturbation of that size is taken as at most twice the realised one:
+#   4 max_a |F_a(x32) - F_a(x)|.
+# Energies: 1e-5 relative (FP32 term arithmetic, FP32 per-lane sums of a few
+# hundred terms).
 # ---------------------------------------------------------------------------
 TOL_SINGLE_E = 1e-5
 U32 = 2.0 ** -24
 
 
-def tol_single_f(x, rms):
+def tol_single_f(oracle, d, fo, rms):
     """Bound on the largest per-atom force error (eV/A) of single precision
-    for coordinates up to max |x| and an RMS force rms."""
-    X = float(np.abs(x).max())
-    return TOL_MIXED_F * rms + 200.0 * 2.0 * math.sqrt(3.0) * X * U32 + 200.0 * 30.0 * U32
+    on system d, whose FP64 oracle forces are fo (RMS rms)."""
+    x32 = np.asarray(d["x"], np.float64).astype(np.float32).astype(np.float64)
+    fpos = oracle.compute(x32, d["species"], d["box"], d["periodic"])[1]
+    return TOL_MIXED_F * rms + 4.0 * float(np.abs(fpos - fo).max()) + 200.0 * 30.0 * U32
 
 
 @pytest.fixture(scope="module")
@@ -296,9 +300,10 @@ def test_single_error_bound(single_ctx, oracle, case):
     eo, fo, wo = oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
     rms = math.sqrt((fo ** 2).sum(1).mean())
     fabs = np.abs(f - fo).max()
+    tol = tol_single_f(oracle, d, fo, rms)
     print(f"single {case}: max force error {fabs:.3g} eV/A ({fabs / rms:.3g} of the RMS force), "
-          f"bound {tol_single_f(d['x'], rms):.3g}; energy {abs(e[0] - eo[0]) / abs(eo[0]):.3g}")
-    assert fabs < tol_single_f(d["x"], rms), fabs
+          f"bound {tol:.3g}; energy {abs(e[0] - eo[0]) / abs(eo[0]):.3g}")
+    assert fabs < tol, (fabs, tol)
     assert abs(e[0] - eo[0]) <= TOL_SINGLE_E * max(abs(eo[0]), 1.0)
     assert np.linalg.norm(w - wo) <= 10 * TOL_SINGLE_E * np.linalg.norm(wo) + 1e-6
     st = single_ctx.stats()
@@ -314,19 +319,19 @@ def test_single_rounds_positions(single_ctx, mixed_ctx, oracle):
     x = x - x.min(0) + 2.0
     near = dict(x=x, species=s, box=np.array([300.0, 300, 300]), periodic=np.zeros(3, np.int32))
     far = dict(near, x=x + 250.0)
-    eo, fo, _ = oracle.compute(near["x"], s, near["box"], near["periodic"])
-    rms = math.sqrt((fo ** 2).sum(1).mean())
+    fo = {where: oracle.compute(d["x"], s, d["box"], d["periodic"])[1] for where, d in (("near", near), ("far", far))}
+    rms = math.sqrt((fo["near"] ** 2).sum(1).mean())
     err = {}
     for name, ctx in (("single", single_ctx), ("mixed", mixed_ctx)):
         for where, d in (("near", near), ("far", far)):
-            err[name, where] = np.abs(run_gpu(ctx, d)[1] - fo).max() / rms
+            err[name, where] = np.abs(run_gpu(ctx, d)[1] - fo[where]).max() / rms
     print({f"{a} {b}": f"{v:.3g}" for (a, b), v in err.items()})
-    assert err["single", "far"] * rms < tol_single_f(far["x"], rms)
+    assert err["single", "far"] * rms < tol_single_f(oracle, far, fo["far"], rms)
     assert err["single", "far"] > 3 * err["single", "near"]
     assert err["mixed", "far"] < TOL_MIXED_F and err["mixed", "near"] < TOL_MIXED_F
 
 
-def test_single_sums_cleared(single_ctx):
+def test_single_sums_cleared(single_ctx, oracle):
     """The FP32 force sums start from zero on every evaluation: repeated
     evaluations agree up to the order of FP32 atomics (a stale sum would
     double the forces), and the forces differ from FP64 at the FP32 level."""
@@ -341,7 +346,7 @@ def test_single_sums_cleared(single_ctx):
         f64 = run_gpu(c64, d)[1]
     finally:
         c64.close()
-    assert 1e-8 * rms < np.abs(f1 - f64).max() < tol_single_f(d["x"], rms)
+    assert 1e-8 * rms < np.abs(f1 - f64).max() < tol_single_f(oracle, d, f64, rms)
 
 
 def test_single_nve_energy_conservation():
