@@ -29,6 +29,7 @@ TOL_E, TOL_F, TOL_W = 1e-12, 1e-10, 1e-10
 TOL_MIXED_F, TOL_MIXED_E = 1e-4, 1e-6
 TOL_SINGLE_E = 1e-5
 U32 = 2.0 ** -24
+PRECS = {"fp64": 0, "mixed": 1, "single": 2}
 
 
 def tol_single_f(oracle, x, species, box, per, fo, rms):
