@@ -119,6 +119,9 @@ struct Params {
   double bmin[3], bmax[3];
   int bstar_use_R1;
   double rc_max;               // max over pairs of lj_cut_sigma * sigma
+  // AIREBO-M: Morse well depth, minimum and range per pair (optional records)
+  bool morse_ok = false;
+  double m_eps[3], m_re[3], m_alpha[3];
 };
 
 bool parse_params(const char* path, Params& P, std::string& err) {
@@ -211,6 +214,17 @@ bool parse_params(const char* path, Params& P, std::string& err) {
   double bs = 1;
   if (!get("bstar_use_R1", bs)) return false;
   P.bstar_use_R1 = (int)bs;
+  // Morse records: all nine or none
+  if (sc.count("morse_eps_CC")) {
+    for (int p = 0; p < 3; ++p) {
+      std::string t = pn[p];
+      if (!get("morse_eps_" + t, P.m_eps[p]) || !get("morse_re_" + t, P.m_re[p]) ||
+          !get("morse_alpha_" + t, P.m_alpha[p]))
+        return false;
+      if (!(P.m_eps[p] > 0 && P.m_re[p] > 0 && P.m_alpha[p] > 0)) { err = "Morse parameters must be positive"; return false; }
+    }
+    P.morse_ok = true;
+  }
   // Lorentz-Berthelot mixing
   P.sigma[0] = sCC; P.sigma[2] = sHH; P.sigma[1] = 0.5 * (sCC + sHH);
   P.eps[0] = eCC; P.eps[2] = eHH; P.eps[1] = std::sqrt(eCC * eHH);
@@ -697,8 +711,11 @@ void do_bond(const Params& P, const Sys& S, const std::vector<std::vector<Nb>>& 
   }
 }
 
+// The van der Waals pair term (Sec. 2.1.2): C_ij, the S_r / S_b blend and the
+// outer cutoff switch multiply V(r), which is Lennard-Jones, or with `morse`
+// the Morse form of the AIREBO-M variant (Sec. 2.1), eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}].
 void do_lj(const Params& P, const Sys& S, const std::vector<std::vector<Nb>>& N, int i, int j,
-           const double* dij, double r, Acc& acc) {
+           const double* dij, double r, bool morse, Acc& acc) {
   const int p = S.s[i] + S.s[j];
   const double sig = P.sigma[p], eps = P.eps[p], rc = P.lj_cut_sigma * sig;
   if (r >= rc) return;
@@ -740,10 +757,16 @@ void do_lj(const Params& P, const Sys& S, const std::vector<std::vector<Nb>>& N,
     if (tb.v > 0.0 && tb.v < 1.0) acc.st.dsb++;
     Qf = Sr * Sw(tb) + 1.0 - Sr;
   }
-  D sr6 = D(sig) / rr;
-  sr6 = sr6 * sr6 * sr6;
-  sr6 = sr6 * sr6;
-  D VLJ = 4.0 * eps * (sr6 * sr6 - sr6);
+  D VLJ;
+  if (morse) {
+    D ex = exp(-P.m_alpha[p] * (rr - P.m_re[p]));
+    VLJ = P.m_eps[p] * (ex * ex - 2.0 * ex);
+  } else {
+    D sr6 = D(sig) / rr;
+    sr6 = sr6 * sr6 * sr6;
+    sr6 = sr6 * sr6;
+    VLJ = 4.0 * eps * (sr6 * sr6 - sr6);
+  }
   D Scut = Sw((rr - (rc - P.lj_sw)) / P.lj_sw);
   scatter(st, Qf * C * VLJ * Scut, acc, 2);
 }
@@ -840,6 +863,8 @@ int oracle_compute(void* hp, int n, const double* x, const int* s, const double*
                    long long* stats, int nthreads) {
   const Handle* H = (const Handle*)hp;
   const Params& P = H->P;
+  const bool morse = mask & 8;   // Morse in place of LJ (AIREBO-M)
+  if (morse && !P.morse_ok) { g_err = "the parameter file has no Morse records"; return -2; }
   Sys S;
   int rc = prepare(H, n, x, s, box, per, S);
   if (rc) return rc;
@@ -889,9 +914,9 @@ int oracle_compute(void* hp, int n, const double* x, const int* s, const double*
         if (j < i && nearm[j]) return;  // seen from j's side
         if (j < i) {  // canonical orientation i' < j'
           double dm[3] = {-d[0], -d[1], -d[2]};
-          do_lj(P, S, N, j, i, dm, r, acc);
+          do_lj(P, S, N, j, i, dm, r, morse, acc);
         } else {
-          do_lj(P, S, N, i, j, d, r, acc);
+          do_lj(P, S, N, i, j, d, r, morse, acc);
         }
       });
     }

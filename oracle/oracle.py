@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 DEFAULT_PARAMS = os.path.join(os.path.dirname(HERE), "paper_1810_07026_amd", "params", "airebo_ch.param")
 
 MASK_REBO, MASK_LJ, MASK_TORS, MASK_ALL = 1, 2, 4, 7
+MASK_MORSE = 8   # with MASK_LJ: the Morse form of AIREBO-M in place of Lennard-Jones
 
 _lib = None
 

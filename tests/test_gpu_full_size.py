@@ -3,6 +3,7 @@
 * The 32,012-atom polyethylene melt (106 x C100H202, the headline workload):
   GPU energy, every force and the virial against one full oracle evaluation,
   FP64 at the FP64 bar, mixed and single precision at their own bars.
+* The 25,600-atom nanotube bundle, each precision at its bar.
 * The 512-system batch (301,512 atoms) with the launch shapes the autotuner
   cached for it: the smallest and the largest system of each family,
   taken whole from the batched result, against the oracle on that system
@@ -83,6 +84,49 @@ def test_melt_32k_full(melt, oracle, prec):
     ferr = check(e, f, w, eo, fo, wo, prec, f"melt {prec}", tol)
     print(f"melt 32k {prec}: max force error / RMS force {ferr:.3g}")
     # Newton's third law over the whole periodic system (FP32 sums: to their rounding)
+    assert np.abs(f.sum(0)).max() <= (1e-6 if prec == "single" else 1e-9) * np.abs(f).sum()
+
+
+@pytest.fixture(scope="module")
+def cnt(oracle):
+    """The nanotube bundle after 1,000 FP64 steps of 0.5 fs, the state the
+    bench's timed run ends in (the perfect lattice has RMS forces of only
+    0.19 eV/A, below the scale the relative force bars are derived for)."""
+    import torch
+    from paper_1810_07026_amd import airebo
+    d = dict(synth.nanotube_bundle())
+    c64 = airebo.Context()
+    try:
+        x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+        v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+        c64.nve(x, v, d["species"], d["box"], d["periodic"], dt=0.5, nsteps=1000, thermo_every=0)
+        d["x"] = x.cpu().numpy()
+    finally:
+        c64.close()
+    return d, oracle.compute(d["x"], d["species"], d["box"], d["periodic"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "single"])
+def test_cnt_bundle_full(cnt, oracle, prec):
+    """The 25,600-atom bundle of 16 (10,10) nanotubes (the nanotube workload
+    bench.py times) at the end state of 1,000 steps: every force, the energy
+    terms and the virial against one oracle evaluation, each precision at its
+    bar."""
+    from paper_1810_07026_amd import airebo
+    d, (eo, fo, wo) = cnt
+    assert len(d["species"]) == 25600
+    ctx = airebo.Context(precision=PRECS[prec])
+    try:
+        e, f, w = ctx.compute(d["x"], d["species"], d["box"], d["periodic"])
+        e, f, w = e.cpu().numpy(), f.cpu().numpy(), w.cpu().numpy()
+    finally:
+        ctx.close()
+    rms = math.sqrt((fo ** 2).sum(1).mean())
+    tol = None
+    if prec == "single":
+        tol = tol_single_f(oracle, d["x"], d["species"], d["box"], d["periodic"], fo, rms)
+    ferr = check(e, f, w, eo, fo, wo, prec, f"cnt {prec}", tol)
+    print(f"cnt bundle {prec}: max force error / RMS force {ferr:.3g}")
     assert np.abs(f.sum(0)).max() <= (1e-6 if prec == "single" else 1e-9) * np.abs(f).sum()
 
 

@@ -11,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle.oracle import MASK_LJ, MASK_REBO, MASK_TORS, DEFAULT_PARAMS
+from oracle.oracle import MASK_LJ, MASK_MORSE, MASK_REBO, MASK_TORS, DEFAULT_PARAMS
 from paper_1810_07026_amd import synth
 
 
@@ -166,6 +166,43 @@ def test_lj_closed_form(oracle, sp, p):
         assert e[2] == pytest.approx(ref, rel=1e-12, abs=1e-15)
 
 
+@pytest.mark.parametrize("sp,p", [((1, 1), "HH"), ((0, 0), "CC"), ((0, 1), "CH")])
+def test_morse_closed_form(oracle, sp, p):
+    """AIREBO-M: two unconnected atoms beyond r_LJmax: C = 1, S_r = 0, so
+    E = eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}] S_cut(r) with the file's Morse
+    records, and the force is minus its derivative along the axis."""
+    eps, re, al = SC["morse_eps_" + p], SC["morse_re_" + p], SC["morse_alpha_" + p]
+    sig = {"CC": SC["sigma_CC"], "HH": SC["sigma_HH"], "CH": 0.5 * (SC["sigma_CC"] + SC["sigma_HH"])}[p]
+    rc = SC["LJ_cut_sigma"] * sig
+    dw = SC["LJ_switch_width"]
+    for r in np.linspace(2 ** (1 / 6) * sig + 0.01, rc + 0.2, 40):
+        x = np.array([[20, 20, 20], [20 + r, 20, 20]], float)
+        e, f, _ = oracle.compute(x, sp, BIG, NOPER, mask=MASK_LJ | MASK_MORSE)
+        t = (r - (rc - dw)) / dw
+        s = 1.0 if t <= 0 else (0.0 if t >= 1 else 1 - t * t * (3 - 2 * t))
+        ds = 0.0 if (t <= 0 or t >= 1) else -6 * t * (1 - t) / dw
+        ex = math.exp(-al * (r - re))
+        v, dv = eps * (ex * ex - 2 * ex), eps * (-2 * al * ex * ex + 2 * al * ex)
+        ref = v * s if r < rc else 0.0
+        dref = (dv * s + v * ds) if r < rc else 0.0
+        assert e[2] == pytest.approx(ref, rel=1e-12, abs=1e-15)
+        assert f[1, 0] == pytest.approx(-dref, rel=1e-10, abs=1e-14)
+        assert f[0, 0] == pytest.approx(dref, rel=1e-10, abs=1e-14)
+
+
+def test_morse_well_matches_lj_well(oracle):
+    """The placeholder Morse records sit where the LJ well is: the Morse pair
+    energy at r_e equals -eps, which the LJ term also reaches at 2^(1/6) sigma
+    (two unconnected H atoms)."""
+    sig = SC["sigma_HH"]
+    r = 2 ** (1 / 6) * sig
+    x = np.array([[20, 20, 20], [20 + r, 20, 20]], float)
+    e_lj = oracle.compute(x, (1, 1), BIG, NOPER, mask=MASK_LJ)[0][2]
+    e_m = oracle.compute(x, (1, 1), BIG, NOPER, mask=MASK_LJ | MASK_MORSE)[0][2]
+    assert e_lj == pytest.approx(-SC["epsilon_HH"], rel=1e-9)
+    assert e_m == pytest.approx(-SC["morse_eps_HH"], rel=1e-9)
+
+
 @pytest.mark.parametrize("phi", np.linspace(0, 2 * math.pi, 13))
 def test_ethane_torsion_closed_form(oracle, phi):
     """Ethane: nine H-C-C-H dihedrals phi + t_a + t_b, weights 1, guards 1."""
@@ -252,6 +289,15 @@ def fd_check(oracle, x, s, box, per, mask, atoms, h=1e-5, tol=2e-6):
 def test_forces_fd_reactive(oracle, seed, mask):
     x, s = reactive_cluster(seed)
     fd_check(oracle, x, s, BIG, NOPER, mask, atoms=range(0, 24, 3))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_forces_fd_reactive_morse(oracle, seed):
+    """AIREBO-M on the reactive clusters: C_ij paths, the S_r / S_b blend
+    and b* all act on the Morse pair term."""
+    x, s = reactive_cluster(seed)
+    fd_check(oracle, x, s, BIG, NOPER, MASK_LJ | MASK_MORSE, atoms=range(0, 24, 3))
+    fd_check(oracle, x, s, BIG, NOPER, 7 | MASK_MORSE, atoms=range(1, 24, 5))
 
 
 @pytest.mark.parametrize("mask", [MASK_REBO, MASK_TORS, 7])
