@@ -28,6 +28,8 @@ FP32_VALU_PEAK = 157.3e12
 # per REBO bond (bond order forward + reverse, pair term, torsion).
 FLOP_PER_LJ_PAIR = 60
 FLOP_PER_BOND = 4000
+# potential variants: (term mask, van der Waals form, oracle mask)
+POTENTIALS = {"airebo": (7, 0, 7), "airebo_m": (7, 1, 7 | 8), "rebo": (1, 0, 1)}
 # arithmetic type of the force evaluation per precision mode (the integrator is FP64)
 DTYPES = {"fp64": "f64", "mixed": "f32+f64", "single": "f32"}
 
@@ -84,6 +86,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and surrogate timings beside the FP64 line")
     ap.add_argument("--form-steps", type=int, default=200)
+    ap.add_argument("--potential", choices=["airebo", "airebo_m", "rebo"], default="airebo",
+                    help="AIREBO, AIREBO-M (Morse in place of LJ, FP64) or REBO alone (no LJ, no torsion)")
     ap.add_argument("--thermo-out", default="",
                     help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds) to this text file")
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
@@ -120,7 +124,8 @@ def main():
     n = len(d["species"])
     box, per = d["box"], d["periodic"]
     prec = airebo.PRECISIONS[args.precision]
-    ctx = airebo.Context(precision=prec)
+    term_mask, vdw, omask = POTENTIALS[args.potential]
+    ctx = airebo.Context(precision=prec, term_mask=term_mask, vdw=vdw)
     dev = torch.device("cuda", 0)
     x = torch.tensor(d["x"], dtype=torch.float64, device=dev)
     v = torch.tensor(d["v"], dtype=torch.float64, device=dev)
@@ -181,7 +186,8 @@ def main():
         roof = {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": ach / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
                 # the committed counter profile is of the melt workload
-                "traffic": counter_traffic(cand, args.precision) if args.workload == "pe_melt_32k" else None,
+                "traffic": (counter_traffic(cand, args.precision)
+                            if args.workload == "pe_melt_32k" and args.potential == "airebo" else None),
                 "flop_per_launch": work[cand], "avg_launch_us": kern[cand]["avg_us"]}
         log(f"bench: kernels {json.dumps({k: round(v['avg_us'], 2) for k, v in kern.items()})}")
 
@@ -195,7 +201,7 @@ def main():
         if n <= 100000:
             log(f"bench: oracle on {threads} threads, one force evaluation of the {n}-atom system")
             t2 = time.perf_counter()
-            eo, fo, wo = orc.compute(xf_h, d["species"], box, per)
+            eo, fo, wo = orc.compute(xf_h, d["species"], box, per, mask=omask)
             t3 = time.perf_counter()
             cpu = {"value": n / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
                    "sample": f"one full FP64 force evaluation (= one MD step) of the {n}-atom system, "
@@ -215,7 +221,7 @@ def main():
             sel = np.sort(np.random.default_rng(0).choice(n, 4096, replace=False)).astype(np.int32)
             log(f"bench: oracle on {threads} threads, forces on {len(sel)} sampled atoms of {n}")
             t2 = time.perf_counter()
-            _, fo, _ = orc.compute(xf_h, d["species"], box, per, sel=sel)
+            _, fo, _ = orc.compute(xf_h, d["species"], box, per, mask=omask, sel=sel)
             t3 = time.perf_counter()
             cpu = {"value": len(sel) / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
                    "sample": f"exact FP64 forces on {len(sel)} random atoms of the {n}-atom system "
@@ -226,7 +232,7 @@ def main():
                     "force_rel_err_max": float(np.abs(fgs - fo).max() / rms), "sampled_atoms": len(sel)}
 
     forms = None
-    if not args.no_forms and args.workload == "pe_melt_32k":
+    if not args.no_forms and args.workload == "pe_melt_32k" and args.potential == "airebo":
         forms = measure_forms(d, xf, vf, args, value, fo if ferr is not None and n <= 100000 else None)
 
     out = {
@@ -235,7 +241,9 @@ def main():
         "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPES[args.precision],
         "data": "synthetic (seeded generators)",
-        "config": {"workload": (f"polyethylene melt 106 x C100H202, {n} atoms, 0.85 g/cm^3, "
+        "config": {"workload": ("" if args.potential == "airebo" else
+                                {"airebo_m": "AIREBO-M (Morse) on ", "rebo": "REBO only on "}[args.potential]) +
+                               (f"polyethylene melt 106 x C100H202, {n} atoms, 0.85 g/cm^3, "
                                 f"{box[0]:.2f} A periodic cube, 300 K, NVE dt 0.5 fs, {args.precision}"
                                 if args.workload == "pe_melt_32k" else
                                 f"bundle of 16 (10,10) carbon nanotubes, {n} atoms, 3.4 A between walls, "
@@ -245,7 +253,7 @@ def main():
                                 f"hybrid {n} atoms: AB graphite 30 layers + H-terminated diamond (111) 31 bilayers "
                                 f"+ polyethylene melt slab, box {box[0]:.1f} x {box[1]:.1f} x {box[2]:.1f} A, "
                                 f"300 K, NVE dt 0.5 fs, {args.precision}"),
-                   "n_atoms": n, "dt_fs": 0.5, "precision": args.precision},
+                   "n_atoms": n, "dt_fs": 0.5, "precision": args.precision, "potential": args.potential},
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": ferr,

@@ -62,7 +62,15 @@ enum {
  *                  combined across lanes in FP64.  Forces are handed out as
  *                  FP64 copies of the FP32 sums. */
 enum { AIREBO_FP64 = 0, AIREBO_MIXED = 1, AIREBO_SINGLE = 2 };
+/* Term mask.  AIREBO_TERM_REBO alone is the REBO-only potential (AIREBO
+ * without its intermolecular and torsion terms, Sec. 2.1). */
 enum { AIREBO_TERM_REBO = 1, AIREBO_TERM_LJ = 2, AIREBO_TERM_TORSION = 4, AIREBO_TERM_ALL = 7 };
+/* Van der Waals pair form inside the LJ term (Sec. 2.1): Lennard-Jones, or the
+ * Morse potential eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}] of the AIREBO-M variant,
+ * under the same C_ij, S_r / S_b blend and cutoff switch.  Morse needs the
+ * parameter set's morse_eps_ / morse_re_ / morse_alpha_ records (CC, CH, HH;
+ * AIREBO_E_PARAMS at context creation otherwise) and AIREBO_FP64. */
+enum { AIREBO_VDW_LJ = 0, AIREBO_VDW_MORSE = 1 };
 
 typedef struct airebo_ctx* airebo_ctx_t;
 typedef struct airebo_params_set* airebo_params_t;
@@ -80,7 +88,8 @@ typedef struct {
   int32_t bond_grid;   /* blocks of the bonded kernel's persistent grid (auto)        */
   int32_t defer_block; /* threads per block of the deferred-pair kernel: 64..256 (64) */
   int32_t short_block; /* threads per block of the short-list kernel: 256, 512, 1024 (1024) */
-  int32_t reserved[4];
+  int32_t vdw;         /* AIREBO_VDW_LJ (default) or AIREBO_VDW_MORSE (AIREBO-M)      */
+  int32_t reserved[3];
 } airebo_options;
 
 void airebo_options_default(airebo_options* opt);

@@ -16,6 +16,7 @@ DEFAULT_PARAMS = os.path.join(HERE, "params", "airebo_ch.param")
 
 FP64, MIXED, SINGLE = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "single": SINGLE}
+VDW_LJ, VDW_MORSE = 0, 1
 TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
               "reserved7", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks"]
@@ -42,7 +43,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("term_mask", ctypes.c_int32), ("skin", ctypes.c_double),
                 ("lj_cap", ctypes.c_int32), ("device", ctypes.c_int32), ("bond_block", ctypes.c_int32),
                 ("bond_grid", ctypes.c_int32), ("defer_block", ctypes.c_int32), ("short_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("vdw", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
     TUNABLES = ("bond_block", "bond_grid", "defer_block", "short_block")
 
@@ -179,7 +180,7 @@ class Context:
     """One AIREBO evaluation context on one GPU (params: a file path or a ParamSet)."""
 
     def __init__(self, params=DEFAULT_PARAMS, precision=FP64, term_mask=TERM_ALL, skin=1.0, lj_cap=0, device=0,
-                 tune=None):
+                 tune=None, vdw=VDW_LJ):
         import torch
         if not torch.cuda.is_available():
             raise AireboError(-7, "no GPU visible: the AIREBO library runs on the GPU only")
@@ -187,6 +188,7 @@ class Context:
         o = Options()
         self.L.airebo_options_default(ctypes.byref(o))
         o.precision, o.term_mask, o.skin, o.lj_cap, o.device = precision, term_mask, skin, lj_cap, device
+        o.vdw = vdw
         for k, v in (tune or {}).items():
             if k not in Options.TUNABLES:
                 raise AireboError(-1, f"unknown tunable {k}")

@@ -1259,6 +1259,40 @@ __device__ __forceinline__ void lj_pair_r2(const DevParams& P, int p, R r2, R& V
   }
 }
 
+// Morse pair term of the AIREBO-M variant, eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}],
+// under the same outer cutoff switch as the LJ term: V and dV/dr.
+template <typename R>
+__device__ __forceinline__ void morse_pair(const DevParams& P, int p, R r, R& V, R& dV) {
+  R a = (R)P.m_alpha[p];
+  R ex = xexp(-a * (r - (R)P.m_re[p]));
+  R e = (R)P.m_eps[p];
+  R v = e * (ex * ex - (R)2 * ex);
+  R dv = (R)2 * a * e * (ex - ex * ex);
+  R isw = (R)(1.0 / P.lj_sw);
+  R t = (r - (R)(P.rc[p] - P.lj_sw)) * isw, dS;
+  R S = Sw(t, dS);
+  V = v * S;
+  dV = dv * S + v * dS * isw;
+}
+
+// The van der Waals pair term: Lennard-Jones, or Morse with M (AIREBO-M).
+template <typename R, bool M>
+__device__ __forceinline__ void vdw_pair(const DevParams& P, int p, R r, R& V, R& dV) {
+  if constexpr (M) morse_pair<R>(P, p, r, V, dV);
+  else lj_pair<R>(P, p, r, V, dV);
+}
+// From r^2 for plain pairs: V and G = (dV/dr) / r.
+template <typename R, bool M>
+__device__ __forceinline__ void vdw_pair_r2(const DevParams& P, int p, R r2, R& V, R& G) {
+  if constexpr (M) {
+    R r = xsqrt(r2), dV;
+    morse_pair<R>(P, p, r, V, dV);
+    G = dV / r;
+  } else {
+    lj_pair_r2<R>(P, p, r2, V, G);
+  }
+}
+
 // LJ term (Alg. 3), one wavefront per atom over its full list.
 //
 // The wavefront first maps every atom reachable from i over at most three
@@ -1279,7 +1313,7 @@ struct LjWaves {
   static constexpr int value = std::is_same<R, float>::value ? 6 : 5;
 };
 
-template <typename R, typename A>
+template <typename R, typename A, bool M>
 __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R>::value, 8))) void k_lj(
     Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
@@ -1435,7 +1469,7 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
             // pair arithmetic in R on the relative vector; accumulation in A
             // (energy and virial halved once, at the end)
             R V, g;
-            lj_pair_r2<R>(P, p, (R)r2, V, g);   // dE/dr_ij vector = g * d
+            vdw_pair_r2<R, M>(P, p, (R)r2, V, g);   // dE/dr_ij vector = g * d
             e += (A)V;
             R fx = g * (R)dx, fy = g * (R)dy, fz = g * (R)dz;
             fi[0] += (A)fx; fi[1] += (A)fy; fi[2] += (A)fz;
@@ -1469,7 +1503,7 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
 // Deferred LJ pairs (0 < C_ij < 1, or inside the S_r range where the modified
 // bond order b* enters through S_b): energy and the full gradient, including
 // the path atoms of C_ij and, where 0 < t_b < 1, the b* neighbourhood.
-template <typename R, typename A>
+template <typename R, typename A, bool M>
 __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
@@ -1503,7 +1537,7 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
     A V, dV;
-    lj_pair<A>(P, p, r, V, dV);
+    vdw_pair<A, M>(P, p, r, V, dV);
     A prod = 0;
     PathInfo pi;
     pi.len = 0;
@@ -1825,6 +1859,7 @@ void airebo_options_default(airebo_options* opt) {
   opt->skin = 1.0;
   opt->lj_cap = 0;
   opt->device = 0;
+  opt->vdw = AIREBO_VDW_LJ;
 }
 
 }  // extern "C"
@@ -1841,6 +1876,9 @@ int check_options(const airebo_options& o) {
   if (o.precision != AIREBO_FP64 && o.precision != AIREBO_MIXED && o.precision != AIREBO_SINGLE)
     return fail(AIREBO_E_ARG, "unknown precision");
   if (o.term_mask < 0 || o.term_mask > 7) return fail(AIREBO_E_ARG, "bad term mask");
+  if (o.vdw != AIREBO_VDW_LJ && o.vdw != AIREBO_VDW_MORSE) return fail(AIREBO_E_ARG, "unknown van der Waals form");
+  if (o.vdw == AIREBO_VDW_MORSE && o.precision != AIREBO_FP64)
+    return fail(AIREBO_E_ARG, "the Morse (AIREBO-M) form is evaluated in FP64 only");
   if (o.lj_cap < 0) return fail(AIREBO_E_ARG, "bad lj_cap");
   auto okb = [](int b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; };
   auto oks = [](int b) { return b == 0 || b == 256 || b == 512 || b == 1024; };
@@ -1856,6 +1894,10 @@ int ctx_create_impl(const DevParams& P, const std::vector<double>& tri, const ai
   c->opt = o;
   c->P = P;
   c->P.knot_delta = o.precision == AIREBO_SINGLE ? -1.0 : KNOT_DELTA;   // single: FP32 everywhere
+  if (o.vdw == AIREBO_VDW_MORSE && !P.morse_ok) {
+    delete c;
+    return fail(AIREBO_E_PARAMS, "the parameter set has no Morse records (morse_eps_/morse_re_/morse_alpha_ CC, CH, HH)");
+  }
   hipError_t e = hipSetDevice(o.device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->dtri, tri.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(c->dtri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -2082,11 +2124,13 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
   bool bonded = mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION);
   // arithmetic type R, accumulation type A: FP64 (double, double), mixed
   // (float, double), single (float, float)
+  const bool morse = c->opt.vdw == AIREBO_VDW_MORSE;   // FP64 only (checked at context creation)
   if (mask & AIREBO_TERM_LJ) {
     dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
-    if (prec == AIREBO_MIXED) LAUNCH(c, K_LJ, (k_lj<float, double>), glj, dim3(LJ_BLOCK), s, D, P);
-    else if (single) LAUNCH(c, K_LJ, (k_lj<float, float>), glj, dim3(LJ_BLOCK), s, D, P);
-    else LAUNCH(c, K_LJ, (k_lj<double, double>), glj, dim3(LJ_BLOCK), s, D, P);
+    if (morse) LAUNCH(c, K_LJ, (k_lj<double, double, true>), glj, dim3(LJ_BLOCK), s, D, P);
+    else if (prec == AIREBO_MIXED) LAUNCH(c, K_LJ, (k_lj<float, double, false>), glj, dim3(LJ_BLOCK), s, D, P);
+    else if (single) LAUNCH(c, K_LJ, (k_lj<float, float, false>), glj, dim3(LJ_BLOCK), s, D, P);
+    else LAUNCH(c, K_LJ, (k_lj<double, double, false>), glj, dim3(LJ_BLOCK), s, D, P);
   }
   // The LJ kernel fills the device on its own (a wavefront per atom); the
   // bonded kernel (a lane per bond) and the deferred b* pairs (a lane per
@@ -2109,9 +2153,10 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
     // one lane per expected deferred pair (about 3 per atom in dense melts), so
     // that the latency-bound b* work is spread over many wavefronts
     dim3 gq(std::min(blocks(4 * (int64_t)D.n, qblk), 16384));
-    if (prec == AIREBO_MIXED) LAUNCH(c, K_BSTAR, (k_bstar<float, double>), gq, dim3(qblk), s, D, P);
-    else if (single) LAUNCH(c, K_BSTAR, (k_bstar<float, float>), gq, dim3(qblk), s, D, P);
-    else LAUNCH(c, K_BSTAR, (k_bstar<double, double>), gq, dim3(qblk), s, D, P);
+    if (morse) LAUNCH(c, K_BSTAR, (k_bstar<double, double, true>), gq, dim3(qblk), s, D, P);
+    else if (prec == AIREBO_MIXED) LAUNCH(c, K_BSTAR, (k_bstar<float, double, false>), gq, dim3(qblk), s, D, P);
+    else if (single) LAUNCH(c, K_BSTAR, (k_bstar<float, float, false>), gq, dim3(qblk), s, D, P);
+    else LAUNCH(c, K_BSTAR, (k_bstar<double, double, false>), gq, dim3(qblk), s, D, P);
   }
   if (fork) {
     (void)hipEventRecord(c->ev_join, c->side);

@@ -178,6 +178,18 @@ bool build_params_text(const char* text, size_t len, DevParams& P, double* tri, 
     err = "switch ranges must be increasing"; return false;
   }
   P.bstar_use_R1 = bs != 0;
+  // Morse pair term of AIREBO-M: all nine records or none
+  P.morse_ok = 0;
+  if (sc.count("morse_eps_CC")) {
+    for (int p = 0; p < 3; ++p) {
+      std::string t = pn[p];
+      if (!need("morse_eps_" + t, P.m_eps[p]) || !need("morse_re_" + t, P.m_re[p]) ||
+          !need("morse_alpha_" + t, P.m_alpha[p]))
+        return false;
+      if (!(P.m_eps[p] > 0 && P.m_re[p] > 0 && P.m_alpha[p] > 0)) { err = "Morse parameters must be positive"; return false; }
+    }
+    P.morse_ok = 1;
+  }
   P.sigma[0] = sCC; P.sigma[2] = sHH; P.sigma[1] = 0.5 * (sCC + sHH);   // Lorentz-Berthelot
   P.eps[0] = eCC; P.eps[2] = eHH; P.eps[1] = std::sqrt(eCC * eHH);
   P.rc_max = 0; P.R2max = 0;

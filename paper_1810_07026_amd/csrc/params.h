@@ -46,6 +46,8 @@ struct DevParams {
   double rc_max;                // largest LJ cutoff
   double r_conn;                // no path of three bonds reaches beyond this (3 max R2)
   double R2max;
+  int morse_ok;                 // Morse records present (AIREBO-M)
+  double m_eps[3], m_re[3], m_alpha[3];
   double knot_delta;            // FP32 spline arguments this close to a knot are evaluated in FP64
                                 // (set per context: 1e-3 for mixed precision, negative for single)
   unsigned char tri_nz[TRI_N][kTriCells];   // cell has a non-zero coefficient

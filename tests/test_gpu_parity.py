@@ -370,3 +370,51 @@ def test_single_nve_energy_conservation():
     assert th[-1, 5] >= 1
     # a fresh evaluation at the end state agrees with the last step's energy
     assert abs(float(e[0].cpu()) - th[-1, 1]) < 1e-3 * abs(th[-1, 1]) + 1e-3
+
+
+# ---------------------------------------------------------------------------
+# AIREBO-M: the Morse pair form in place of Lennard-Jones (FP64), at the FP64
+# bar against the oracle's Morse form.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def morse_ctx():
+    from paper_1810_07026_amd import airebo
+    c = airebo.Context(vdw=airebo.VDW_MORSE)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("case", ["pe_small", "cluster", "dense", "tiled"])
+def test_morse_parity(morse_ctx, ctxs, oracle, case):
+    from oracle.oracle import MASK_MORSE
+    if case == "pe_small":
+        d = synth.pe_small()
+    elif case == "cluster":
+        d = reactive_cluster(5, n=28)
+    elif case == "dense":
+        d = reactive_cluster(11, n=32, span=6.5)
+    else:
+        d = synth.tile(synth.pe_small(seed=synth.SEED0 + 17), (2, 2, 1))
+    ref = oracle.compute(d["x"], d["species"], d["box"], d["periodic"], mask=7 | MASK_MORSE)
+    got = run_gpu(morse_ctx, d)
+    compare(got, ref, f"morse {case}")
+    # the pair term really changed: LJ and Morse energies differ
+    e_lj = run_gpu(ctxs[7], d)[0]
+    assert abs(e_lj[2] - got[0][2]) > 1e-6 * max(abs(e_lj[2]), 1e-3)
+
+
+def test_morse_options_checked():
+    """Morse needs FP64 and a parameter set with the Morse records."""
+    from paper_1810_07026_amd import airebo
+    with pytest.raises(airebo.AireboError) as ex:
+        airebo.Context(vdw=airebo.VDW_MORSE, precision=airebo.MIXED)
+    assert ex.value.code == -1
+    text = "".join(line for line in open(airebo.DEFAULT_PARAMS) if not line.startswith("morse_"))
+    ps = airebo.ParamSet(text=text)
+    try:
+        airebo.Context(params=ps).close()   # LJ works without the Morse records
+        with pytest.raises(airebo.AireboError) as ex:
+            airebo.Context(params=ps, vdw=airebo.VDW_MORSE)
+        assert ex.value.code == -2
+    finally:
+        ps.close()
