@@ -65,7 +65,7 @@ enum { AIREBO_FP64 = 0, AIREBO_MIXED = 1, AIREBO_SINGLE = 2 };
 /* Term mask.  AIREBO_TERM_REBO alone is the REBO-only potential (AIREBO
  * without its intermolecular and torsion terms, Sec. 2.1). */
 enum { AIREBO_TERM_REBO = 1, AIREBO_TERM_LJ = 2, AIREBO_TERM_TORSION = 4, AIREBO_TERM_ALL = 7 };
-/* Van der Waals pair form inside the LJ term (Sec. 2.1): Lennard-Jones, or the
+/* Van der Waals pair form inside the LJ term (Sec. 2.1.2): Lennard-Jones, or the
  * Morse potential eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}] of the AIREBO-M variant,
  * under the same C_ij, S_r / S_b blend and cutoff switch.  Morse needs the
  * parameter set's morse_eps_ / morse_re_ / morse_alpha_ records (CC, CH, HH;

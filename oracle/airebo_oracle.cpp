@@ -713,7 +713,7 @@ void do_bond(const Params& P, const Sys& S, const std::vector<std::vector<Nb>>& 
 
 // The van der Waals pair term (Sec. 2.1.2): C_ij, the S_r / S_b blend and the
 // outer cutoff switch multiply V(r), which is Lennard-Jones, or with `morse`
-// the Morse form of the AIREBO-M variant (Sec. 2.1), eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}].
+// the Morse form of the AIREBO-M variant (Sec. 2.1.2), eps [e^{-2a(r-re)} - 2 e^{-a(r-re)}].
 void do_lj(const Params& P, const Sys& S, const std::vector<std::vector<Nb>>& N, int i, int j,
            const double* dij, double r, bool morse, Acc& acc) {
   const int p = S.s[i] + S.s[j];
