@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--form-steps", type=int, default=200)
     ap.add_argument("--potential", choices=["airebo", "airebo_m", "rebo"], default="airebo",
                     help="AIREBO, AIREBO-M (Morse in place of LJ, FP64) or REBO alone (no LJ, no torsion)")
+    ap.add_argument("--cnt-cells", type=int, default=40, help="nanotube bundle: translational cells per tube")
+    ap.add_argument("--cnt-grid", type=int, default=4, help="nanotube bundle: tubes per side of the square lattice")
     ap.add_argument("--thermo-out", default="",
                     help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds) to this text file")
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
@@ -415,7 +417,8 @@ def bench_conservation(args):
     is reported."""
     import torch
     from paper_1810_07026_amd import airebo, synth
-    d = synth.pe_melt() if args.system == "pe_melt" else synth.nanotube_bundle()
+    d = (synth.pe_melt() if args.system == "pe_melt" else
+         synth.nanotube_bundle(ncells=args.cnt_cells, nx=args.cnt_grid, ny=args.cnt_grid))
     s, box, per = d["species"], d["box"], d["periodic"]
     n = len(s)
     prec = airebo.PRECISIONS[args.precision]
@@ -452,7 +455,9 @@ def bench_conservation(args):
            "vs_baseline": None, "dtype": DTYPES[args.precision],
            "data": "synthetic (seeded generators)",
            "config": {"workload": ("polyethylene melt 106 x C100H202" if args.system == "pe_melt" else
-                                   "bundle of 16 (10,10) carbon nanotubes") +
+                                   f"bundle of {args.cnt_grid ** 2} (10,10) carbon nanotubes of "
+                                   f"{args.cnt_cells} cells, box {d['box'][0]:.1f} x {d['box'][1]:.1f} x "
+                                   f"{d['box'][2]:.1f} A") +
                                   f", {n} atoms, NVE {args.steps} steps of {args.dt} fs, {args.precision}",
                       "n_atoms": n, "dt_fs": args.dt},
            "atom_steps_per_s": n * args.steps / sec,
