@@ -6,6 +6,8 @@ periodic images.  A bare carbon (a radical) reacts within picoseconds of
 NVE, heats its box and ends in a blow-up that no force kernel can be
 blamed for; an earlier flake builder produced such chain ends.
 """
+import math
+
 import numpy as np
 import pytest
 from scipy.spatial import cKDTree
@@ -71,3 +73,41 @@ def test_batch_molecules_are_saturated():
         assert np.all(deg[s == 1] == 1), f"system {k}: H with {sorted(set(deg[s == 1]))} neighbours"
         assert np.all((deg[s == 0] >= 3) & (deg[s == 0] <= 4)), \
             f"system {k}: C with {sorted(set(deg[s == 0]))} neighbours"
+
+
+@pytest.mark.parametrize("n,m", [(5, 5), (10, 10), (10, 0), (8, 4)])
+def test_nanotube_geometry(n, m):
+    """A rolled (n, m) tube: every carbon has exactly three neighbours at the
+    graphene bond length (minimum image along the periodic axis; curvature
+    shortens the chord by well under 1%), and the radius is |C| / 2 pi with
+    |C| = a sqrt(n^2 + nm + m^2), a = sqrt(3) 1.42 A."""
+    x, s, box, per = synth.nanotube(n, m, 3)
+    assert (s == 0).all() and list(per) == [0, 0, 1]
+    d = x[:, None, :] - x[None, :, :]
+    d[..., 2] -= box[2] * np.round(d[..., 2] / box[2])
+    r = np.linalg.norm(d, axis=2)
+    np.fill_diagonal(r, np.inf)
+    near = (r < 1.6).sum(1)
+    assert (near == 3).all()
+    assert np.abs(r[r < 1.6] - 1.42).max() < 0.02
+    a = math.sqrt(3) * 1.42
+    radius = a * math.sqrt(n * n + n * m + m * m) / (2 * math.pi)
+    c = box[:2] / 2
+    assert np.allclose(np.linalg.norm(x[:, :2] - c, axis=1), radius, atol=1e-9)
+
+
+def test_nanotube_bundle_layout():
+    """16 (10,10) tubes of 40 cells: 25,600 atoms; walls of neighbouring tubes
+    (through the periodic boundary too) are 3.4 A apart."""
+    d = synth.nanotube_bundle()
+    x, box = d["x"], d["box"]
+    assert len(x) == 25600 and list(d["periodic"]) == [1, 1, 1]
+    per_tube = 1600
+    c0 = x[:per_tube, :2].mean(0)
+    rad = np.linalg.norm(x[0, :2] - c0)
+    centres = np.array([x[k * per_tube:(k + 1) * per_tube, :2].mean(0) for k in range(16)])
+    dc = centres[:, None, :] - centres[None, :, :]
+    dc -= box[:2] * np.round(dc / box[:2])
+    dist = np.linalg.norm(dc, axis=2)
+    np.fill_diagonal(dist, np.inf)
+    assert np.allclose(dist.min(1), 2 * rad + 3.4, atol=1e-6)
