@@ -1303,18 +1303,20 @@ __device__ __forceinline__ void vdw_pair_r2(const DevParams& P, int p, R r2, R& 
 // before one intermediate before two).  Then, over the full list, pairs
 // beyond 3 max R2 are plain LJ; nearer pairs look up C_ij: C = 0 is skipped,
 // C = 1 outside the S_r range is plain LJ, and every other pair (0 < C < 1 or
-// inside the S_r range) is deferred to a queue that k_defer evaluates in
+// inside the S_r range) is deferred to a queue that k_bstar evaluates in
 // full.  Each pair is seen from both ends: each end adds half the energy and
 // virial and the full force on its own atom.
 // Minimum waves per SIMD asked of the compiler for the LJ kernel: the FP32
-// instantiation fits six (80 VGPRs) without spilling; FP64 keeps five.
-template <typename R>
+// instantiations fit six (80 VGPRs) without spilling; FP64 keeps five; the
+// Morse form (a square root and an exponential more per pair) four, where
+// five would spill.
+template <typename R, bool M>
 struct LjWaves {
-  static constexpr int value = std::is_same<R, float>::value ? 6 : 5;
+  static constexpr int value = M ? 4 : (std::is_same<R, float>::value ? 6 : 5);
 };
 
 template <typename R, typename A, bool M>
-__global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R>::value, 8))) void k_lj(
+__global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R, M>::value, 8))) void k_lj(
     Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
