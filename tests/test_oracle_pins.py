@@ -480,3 +480,184 @@ def test_nve_drift_scales_dt2(oracle):
         drifts.append(np.abs(th[:, 3] - th[0, 3]).max())
     ratio = drifts[0] / drifts[1]
     assert 2.5 < ratio < 6.0, drifts
+
+
+# ---------------------------------------------------------------------------
+# closed forms of the parts that finite differences alone cannot fix: the
+# S_r / S_b blend of the LJ term and its switch arguments (Sec. 2.1.2), the
+# lambda exponent of an H centre, the g_C blend over N_ij and the conjugation
+# step F(x) inside N^conj (Sec. 2.1.3)
+# ---------------------------------------------------------------------------
+def cubic_switch(t):
+    """S(t) = 1 - t^2 (3 - 2t) on [0, 1], 1 below, 0 above (written out here)."""
+    if t <= 0.0:
+        return 1.0
+    if t >= 1.0:
+        return 0.0
+    return 1.0 - t * t * (3.0 - 2.0 * t)
+
+
+def lj_params(p):
+    sig = {"CC": SC["sigma_CC"], "HH": SC["sigma_HH"], "CH": 0.5 * (SC["sigma_CC"] + SC["sigma_HH"])}[p]
+    eps = {"CC": SC["epsilon_CC"], "HH": SC["epsilon_HH"],
+           "CH": math.sqrt(SC["epsilon_CC"] * SC["epsilon_HH"])}[p]
+    return sig, eps
+
+
+def v_lj(p, r):
+    sig, eps = lj_params(p)
+    rc = SC["LJ_cut_sigma"] * sig
+    dw = SC["LJ_switch_width"]
+    return 4 * eps * ((sig / r) ** 12 - (sig / r) ** 6) * cubic_switch((r - (rc - dw)) / dw)
+
+
+@pytest.mark.parametrize("sp,p", [((1, 1), "HH"), ((0, 0), "CC"), ((0, 1), "CH")])
+def test_lj_repulsive_blend_isolated(oracle, sp, p):
+    """Two unconnected atoms with sigma < r < 2^(1/6) sigma.  Neither has a
+    neighbour, so b* = (1 + 1)/2 + F(0, 0, 1) = 1 > b_max and S_b = 0: the
+    LJ energy is (1 - S_r(t_r)) V_LJ(r), t_r = (r - sigma) / (2^(1/6) sigma -
+    sigma), and the force along the axis is minus its derivative."""
+    sig, eps = lj_params(p)
+    rmin = 2 ** (1 / 6) * sig
+    assert SC["bmax_" + p] < 1.0
+    for f in np.linspace(0.03, 0.97, 15):
+        r = sig + f * (rmin - sig)
+        x = np.array([[20, 20, 20], [20 + r, 20, 20]], float)
+        e, F, _ = oracle.compute(x, sp, BIG, NOPER, mask=MASK_LJ)
+        bs = oracle.bond_order(x, sp, BIG, 0, 1, bstar=True, periodic=NOPER)["b"]
+        assert bs == pytest.approx(1.0, abs=1e-14)
+        tr = (r - sig) / (rmin - sig)
+        v = 4 * eps * ((sig / r) ** 12 - (sig / r) ** 6)
+        dv = 4 * eps * (-12 * sig ** 12 / r ** 13 + 6 * sig ** 6 / r ** 7)
+        blend = 1.0 - cubic_switch(tr)              # = t^2 (3 - 2t)
+        dblend = 6 * tr * (1 - tr) / (rmin - sig)
+        assert e[2] == pytest.approx(blend * v, rel=1e-12, abs=1e-16)
+        assert F[1, 0] == pytest.approx(-(blend * dv + dblend * v), rel=1e-9, abs=1e-14)
+    # at r = sigma the blend vanishes (S_r = 1, S_b = 0), at 2^(1/6) sigma it is 1
+    for r, ref in ((sig, 0.0), (rmin, -eps)):
+        x = np.array([[20, 20, 20], [20 + r, 20, 20]], float)
+        assert oracle.compute(x, sp, BIG, NOPER, mask=MASK_LJ)[0][2] == pytest.approx(ref, abs=1e-12)
+
+
+def two_h2(d, a1, a2):
+    """Two H2 molecules (0.74 A) in the xy plane, atom 2 at distance d from atom 0."""
+    return np.array([[20, 20, 20], [20 + 0.74 * math.cos(a1), 20 + 0.74 * math.sin(a1), 20],
+                     [20 + d, 20, 20], [20 + d + 0.74 * math.cos(a2), 20 + 0.74 * math.sin(a2), 20]], float)
+
+
+@pytest.mark.parametrize("geo", [(2.70, 0.5, 1.2), (2.66, 0.0, 0.8), (2.80, 1.9, 2.6), (2.75, 2.2, 0.3)])
+def test_lj_bond_order_blend_by_hand(oracle, geo):
+    """Two H2 molecules: the intramolecular pairs have C = 0 (w = 1), the four
+    cross pairs C = 1 (no atom within R2 of the other molecule).  Each cross
+    pair's LJ energy is [S_r(t_r) S_b(t_b) + 1 - S_r(t_r)] V_LJ(r), with
+    t_b = (b* - b_min) / (b_max - b_min) and b* taken from the bond-order
+    function with r_ij replaced by the constant.  At least one pair has S_r
+    and S_b both strictly between 0 and 1."""
+    x = two_h2(*geo)
+    s = [1, 1, 1, 1]
+    sig, _ = lj_params("HH")
+    rmin = 2 ** (1 / 6) * sig
+    ref, interior = 0.0, 0
+    for i, j in ((0, 2), (0, 3), (1, 2), (1, 3)):
+        r = float(np.linalg.norm(x[j] - x[i]))
+        assert r > SC["R2_HH"]
+        assert oracle.cij(x, s, BIG, i, j, periodic=NOPER) == 1.0
+        Sr = cubic_switch((r - sig) / (rmin - sig))
+        Sb = 1.0
+        if Sr > 0:
+            bs = oracle.bond_order(x, s, BIG, i, j, bstar=True, periodic=NOPER)["b"]
+            tb = (bs - SC["bmin_HH"]) / (SC["bmax_HH"] - SC["bmin_HH"])
+            Sb = cubic_switch(tb)
+            interior += (0 < Sr < 1) and (0 < Sb < 1)
+        ref += (Sr * Sb + 1 - Sr) * v_lj("HH", r)
+    assert interior >= 1
+    e = oracle.compute(x, s, BIG, NOPER, mask=MASK_LJ)[0]
+    assert e[2] == pytest.approx(ref, rel=1e-12, abs=1e-16)
+
+
+def test_lambda_exponent_by_hand(oracle):
+    """H centre i bonded to partner j and to one more neighbour k at an angle
+    whose cosine is a knot of g_H (-1/2).  p_ij = [1 + w_ik g_H(cos) e^lambda]^(-1/2)
+    with lambda = 4 [(rho_{s_k H} - r_ik) - (rho_{s_j H} - r_ij)] (P = 0 for an
+    H centre); for b*, r_ij is replaced by R1_ij.  k is H (rho_HH) or C (rho_CH)."""
+    gH = [v for n, v in REC if n == "gH" and abs(v[0] + 0.5) < 1e-12][0][1]
+    rho = {0: SC["rho_CH"], 1: SC["rho_HH"]}
+    pn = {0: "CH", 1: "HH"}
+    for sk, rij, rik in ((1, 0.9, 1.3), (1, 1.05, 1.15), (0, 1.0, 1.2), (0, 0.95, 1.6)):
+        th = 2 * math.pi / 3                          # cos = -1/2
+        x = np.array([[20, 20, 20], [20 + rij, 20, 20],
+                      [20 + rik * math.cos(th), 20 + rik * math.sin(th), 20]], float)
+        s = [1, 1, sk]
+        # j and k are not neighbours of each other
+        assert np.linalg.norm(x[1] - x[2]) > SC["R2_" + pn[sk]]
+        w = wcut(pn[sk], rik)
+        for bstar in (False, True):
+            r_lam = SC["R1_HH"] if bstar else rij
+            lam = 4.0 * ((rho[sk] - rik) - (rho[1] - r_lam))
+            ref = (1 + w * gH * math.exp(lam)) ** -0.5
+            bo = oracle.bond_order(x, s, BIG, 0, 1, bstar=bstar, periodic=NOPER)
+            assert bo["pij"] == pytest.approx(ref, rel=1e-13), (sk, rij, rik, bstar)
+            assert bo["pji"] == 1.0
+
+
+def test_gC_blend_by_hand(oracle):
+    """g_C(cos, N) = G_C(cos) + Q(N) (gamma_C(cos) - G_C(cos)), Q(N) =
+    [1 + cos(pi (N - 3.2) / 0.5)] / 2 on [3.2, 3.7] (1 below, 0 above).  G_C
+    and gamma_C alone are the function at N = 4 and N = 2; at cos = 1 they are
+    the last knots of their tables (8 and 1 here)."""
+    lo, hi = SC["gC_blend_lo"], SC["gC_blend_hi"]
+    Gk = [v for n, v in REC if n == "gC"][-1]
+    gk = [v for n, v in REC if n == "gammaC"][-1]
+    for c in (1.0, 0.5, 0.0, 0.9):
+        G = oracle.spline(0, c, 4.0)[0]
+        g = oracle.spline(0, c, 2.0)[0]
+        if c == 1.0:
+            assert G == Gk[1] and g == gk[1]
+        assert abs(G - g) > 0.05
+        for N in (3.2, 3.3, 3.45, 3.6, 3.7):
+            Q = 0.5 * (1 + math.cos(math.pi * (N - lo) / (hi - lo)))
+            dQ = -0.5 * math.pi / (hi - lo) * math.sin(math.pi * (N - lo) / (hi - lo))
+            val, grad = oracle.spline(0, c, N)
+            assert val == pytest.approx(G + Q * (g - G), rel=1e-13, abs=1e-14), (c, N)
+            if lo < N < hi:
+                assert grad[1] == pytest.approx(dQ * (g - G), rel=1e-10), (c, N)
+        assert oracle.spline(0, c, 3.45)[0] == pytest.approx(0.5 * (G + g), rel=1e-13)
+    # below the last common knot (cos <= -1/3) there is no N dependence
+    for c in (-0.9, -0.5, -1 / 3):
+        assert oracle.spline(0, c, 3.45)[0] == oracle.spline(0, c, 4.0)[0]
+
+
+def test_conjugation_step_by_hand(oracle):
+    """C_i - C_j bond (j bare); i has one more neighbour, carbon k, with two H
+    at 1.09 A and a third H at r3 inside (R1_CH, R2_CH).  Then x_ik = N_k -
+    w_ik = 2 + w(r3) lies in (2, 3), F(x) = [1 + cos(pi (x - 2))] / 2 and
+    N^conj_ij = 1 + (w_ik F(x_ik))^2 (the j side has no carbon neighbour)."""
+    ci = np.array([0.0, 0.0, 0.0])
+    cj = np.array([1.40, 0.0, 0.0])
+    u = np.array([-0.5, math.sqrt(3) / 2, 0.0])
+    for rik in (1.5, 1.8):
+        ck = ci + rik * u
+        # H's of k: tetrahedral directions pointing away from i
+        a = u
+        b = np.cross(a, [0, 0, 1.0]); b /= np.linalg.norm(b)
+        c = np.cross(a, b)
+        ct, st = math.cos(math.radians(70.5)), math.sin(math.radians(70.5))
+        dirs = [ct * a + st * (math.cos(ph) * b + math.sin(ph) * c) for ph in (0, 2 * math.pi / 3, 4 * math.pi / 3)]
+        for r3 in (1.40, 1.55, 1.70):
+            hs = [ck + 1.09 * dirs[0], ck + 1.09 * dirs[1], ck + r3 * dirs[2]]
+            x = np.array([ci, cj, ck] + hs) + 20
+            s = [0, 0, 0, 1, 1, 1]
+            d = np.linalg.norm(x[:, None] - x[None], axis=-1)
+            pairs = {"CC": SC["R2_CC"], "CH": SC["R2_CH"], "HH": SC["R2_HH"]}
+            names = ["CC", "CH", "HH"]
+            bonded = {(0, 1), (0, 2), (2, 3), (2, 4), (2, 5)}
+            for p_, q_ in itertools.combinations(range(6), 2):
+                inside = d[p_, q_] < pairs[names[s[p_] + s[q_]]]
+                assert inside == ((p_, q_) in bonded), (p_, q_, d[p_, q_])
+            w_ik = wcut("CC", rik)
+            xk = 2.0 + wcut("CH", r3)
+            assert 2.0 < xk < 3.0
+            Fx = 0.5 * (1 + math.cos(math.pi * (xk - 2.0)))
+            bo = oracle.bond_order(x, s, BIG, 0, 1, periodic=NOPER)
+            assert bo["Nconj"] == pytest.approx(1 + (w_ik * Fx) ** 2, rel=1e-13), (rik, r3)
+            assert bo["Nij"] == pytest.approx(w_ik, rel=1e-14) and bo["Nji"] == 0.0
