@@ -23,11 +23,16 @@ sys.path.insert(0, ROOT)
 
 FP64_VALU_PEAK = 78.6e12      # MI355X vector FP64, FLOP/s
 FP32_VALU_PEAK = 157.3e12
-# Algorithmic FP64 operations per unit of work of each kernel (see the design
-# notes for the breakdown): per LJ pair inside the cutoff (each pair once) and
-# per REBO bond (bond order forward + reverse, pair term, torsion).
-FLOP_PER_LJ_PAIR = 60
+# Algorithmic FP64 operations per unit of work of each kernel: per LJ pair
+# inside the cutoff (each pair once), per list pair beyond it, and per REBO
+# bond (bond order forward + reverse, pair term, torsion).
+FLOP_PER_LJ_PAIR = 45       # per pair inside its cutoff, each pair once
+FLOP_PER_SKIN_PAIR = 8      # per list pair beyond its cutoff (distance test)
 FLOP_PER_BOND = 4000
+# untimed preparation of the melt: capped steepest descent, then rescaled NVE
+PREP_SD_ITERS, PREP_SD_ALPHA, PREP_SD_CAP = 300, 0.01, 0.02     # iterations, A^2/eV, A
+PREP_EQ_CYCLES, PREP_EQ_STEPS = 20, 50
+SURROGATE_TILES = (3, 3, 4)   # 32,012-atom melt tiled to 1,152,432 atoms
 # potential variants: (term mask, van der Waals form, oracle mask)
 POTENTIALS = {"airebo": (7, 0, 7), "airebo_m": (7, 1, 7 | 8), "rebo": (1, 0, 1)}
 # arithmetic type of the force evaluation per precision mode (the integrator is FP64)
@@ -86,12 +91,16 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision and surrogate timings beside the FP64 line")
     ap.add_argument("--form-steps", type=int, default=200)
+    ap.add_argument("--no-prep", action="store_true", help="time the generated melt without its preparation run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 10^6-atom hybrid and surrogate sub-records of the default line")
+    ap.add_argument("--extra-steps", type=int, default=50, help="timed steps of each 10^6-atom sub-record form")
     ap.add_argument("--potential", choices=["airebo", "airebo_m", "rebo"], default="airebo",
                     help="AIREBO, AIREBO-M (Morse in place of LJ, FP64) or REBO alone (no LJ, no torsion)")
     ap.add_argument("--cnt-cells", type=int, default=40, help="nanotube bundle: translational cells per tube")
     ap.add_argument("--cnt-grid", type=int, default=4, help="nanotube bundle: tubes per side of the square lattice")
     ap.add_argument("--thermo-out", default="",
-                    help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds) to this text file")
+                    help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds P) to this text file")
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -132,69 +141,48 @@ def main():
     x = torch.tensor(d["x"], dtype=torch.float64, device=dev)
     v = torch.tensor(d["v"], dtype=torch.float64, device=dev)
 
-    if args.workload == "hybrid_1m":
-        # untimed preparation: velocity quench (NVE in short bursts, velocities
-        # zeroed after each) relaxes the strain of the assembled slabs, then
-        # fresh 300 K velocities
-        log("bench: hybrid preparation: 20 quench cycles of 10 steps (untimed)")
-        for _ in range(20):
-            ctx.nve(x, v, d["species"], box, per, nsteps=10, thermo_every=0)
-            v.zero_()
-        v.copy_(torch.tensor(synth.maxwell_velocities(d["species"], 300.0, np.random.default_rng(1810070267)),
-                             dtype=torch.float64, device=dev))
-    log(f"bench: n={n} warmup {args.warmup} steps")
-    ctx.nve(x, v, d["species"], box, per, nsteps=args.warmup, thermo_every=0)
-    torch.cuda.synchronize()
+    if args.workload == "pe_melt_32k" and not args.no_prep:
+        x, v = prepare_melt(d, x, v, log)
+    elif args.workload == "hybrid_1m":
+        x, v = prepare_hybrid(d, x, v, log)
+    # the timed region holds exactly `steps` velocity-Verlet steps of a session
+    # whose state is already on the device (begin and warm-up untimed)
+    log(f"bench: n={n} session start, warmup {args.warmup} steps")
     every = max(1, args.steps // 20)
-    log(f"bench: timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    th = ctx.nve(x, v, d["species"], box, per, nsteps=args.steps, thermo_every=every)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    value, ms, th = timed_session(lambda: ctx.md_begin(x, v, d["species"], box, per), ctx, n, args.steps,
+                                  args.warmup, every)
     th = th.cpu().numpy()
-    sec = t1 - t0
-    value = n * args.steps / sec
-    rebuilds = int(th[-1, 5])
-    log(f"bench: {value:.4g} atom-steps/s ({1e3 * sec / args.steps:.4f} ms/step), rebuilds {rebuilds}")
+    x, v = ctx.md_state()
+    ctx.md_end()
+    sec = 1e-3 * ms * args.steps
+    rebuilds = int(th[-1, 5] - th[0, 5])
+    log(f"bench: {value:.4g} atom-steps/s ({ms:.4f} ms/step), rebuilds {rebuilds}, T {th[0, 4]:.0f} -> "
+        f"{th[-1, 4]:.0f} K")
 
     # energy drift over the timed run: slope of (E - E0)/N and max |dE|/|E0|
-    t_ps = th[:, 0] * 0.5e-3
+    t_ps = (th[:, 0] - th[0, 0]) * 0.5e-3
     de = (th[:, 3] - th[0, 3]) / n
     slope = float(np.polyfit(t_ps, de, 1)[0]) if len(t_ps) > 2 else float("nan")
     maxrel = float(np.abs(th[:, 3] - th[0, 3]).max() / abs(th[0, 3]))
 
     # accuracy and the other forms are measured on the state the timed run
-    # ends in (equilibrated); the per-kernel profile continues from it
+    # ends in; the per-kernel profile continues from it
     xf, vf = x.clone(), v.clone()
     xf_h = xf.cpu().numpy()
-    # per-kernel device times (HIP events on the launch stream) and work counts
     e0, f0, _ = ctx.compute(xf, d["species"], box, per)
     st = ctx.stats()
     roof, kern = None, {}
     if not args.no_profile:
         xp, vp = x.clone(), v.clone()
         prof = ctx.profile_nve(xp, vp, d["species"], box, per, nsteps=args.profile_steps)
-        kern = {k: {"total_ms": ms, "launches": c, "avg_us": 1e3 * ms / c if c else 0.0}
-                for k, (ms, c) in prof.items() if c}
-        st_p = ctx.stats()
-        plain = st["lj_in_cut"] - st["cij_zero"] - st["bstar_queued"]
-        work = {"k_lj": FLOP_PER_LJ_PAIR * plain, "k_bond": FLOP_PER_BOND * st["bonds"]}
-        dom = max(kern, key=lambda k: kern[k]["total_ms"])
-        cand = dom if dom in work else max(work, key=lambda k: kern.get(k, {"total_ms": 0})["total_ms"])
-        avg_s = kern[cand]["avg_us"] * 1e-6
-        peak = FP64_VALU_PEAK if prec == airebo.FP64 else FP32_VALU_PEAK
-        ach = work[cand] / avg_s
-        roof = {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": ach / 1e12,
-                "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
-                # the committed counter profile is of the melt workload
-                "traffic": (counter_traffic(cand, args.precision)
-                            if args.workload == "pe_melt_32k" and args.potential == "airebo" else None),
-                "flop_per_launch": work[cand], "avg_launch_us": kern[cand]["avg_us"]}
-        log(f"bench: kernels {json.dumps({k: round(v['avg_us'], 2) for k, v in kern.items()})}")
+        kern = {k: {"total_ms": ms_, "launches": c, "avg_us": 1e3 * ms_ / c if c else 0.0}
+                for k, (ms_, c) in prof.items() if c}
+        roof = roofline(kern, st, prec, args)
+        log(f"bench: kernels {json.dumps({k: round(v_['avg_us'], 2) for k, v_ in kern.items()})}")
 
     cpu = None
     ferr = None
+    fo = None
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -211,7 +199,7 @@ def main():
             # the same evaluation on one thread
             log("bench: oracle on 1 thread, one force evaluation")
             t4 = time.perf_counter()
-            Oracle(nthreads=1).compute(xf_h, d["species"], box, per)
+            Oracle(nthreads=1).compute(xf_h, d["species"], box, per, mask=omask)
             t5 = time.perf_counter()
             cpu["single_thread"] = {"value": n / (t5 - t4), "unit": "atom-steps/s", "cores": 1,
                                     "sample": f"one full FP64 force evaluation of the {n}-atom system, {t5 - t4:.1f} s"}
@@ -223,30 +211,35 @@ def main():
             sel = np.sort(np.random.default_rng(0).choice(n, 4096, replace=False)).astype(np.int32)
             log(f"bench: oracle on {threads} threads, forces on {len(sel)} sampled atoms of {n}")
             t2 = time.perf_counter()
-            _, fo, _ = orc.compute(xf_h, d["species"], box, per, mask=omask, sel=sel)
+            _, fo_all, _ = orc.compute(xf_h, d["species"], box, per, mask=omask, sel=sel)
             t3 = time.perf_counter()
             cpu = {"value": len(sel) / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
                    "sample": f"exact FP64 forces on {len(sel)} random atoms of the {n}-atom system "
-                             f"(every term touching them), {t3 - t2:.1f} s"}
-            fo, fgs = fo[sel], fg[sel]
-            rms = math.sqrt((fo ** 2).sum(1).mean())
-            ferr = {"force_rms_err_eVA": float(math.sqrt(((fgs - fo) ** 2).sum(1).mean())), "force_rms_eVA": rms,
-                    "force_rel_err_max": float(np.abs(fgs - fo).max() / rms), "sampled_atoms": len(sel)}
+                             f"(every term touching them), {t3 - t2:.1f} s", "host_cpu": host_cpu()}
+            fos, fgs = fo_all[sel], fg[sel]
+            rms = math.sqrt((fos ** 2).sum(1).mean())
+            ferr = {"force_rms_err_eVA": float(math.sqrt(((fgs - fos) ** 2).sum(1).mean())), "force_rms_eVA": rms,
+                    "force_rel_err_max": float(np.abs(fgs - fos).max() / rms), "sampled_atoms": len(sel)}
 
     forms = None
     if not args.no_forms and args.workload == "pe_melt_32k" and args.potential == "airebo":
-        forms = measure_forms(d, xf, vf, args, value, fo if ferr is not None and n <= 100000 else None)
+        forms = measure_forms(d, xf, vf, args, fo)
+    extra = {}
+    if args.workload == "pe_melt_32k" and args.potential == "airebo" and not args.no_extra:
+        extra["hybrid_1m"] = record_or_error(lambda: hybrid_record(args))
+        extra["surrogate_1m"] = record_or_error(lambda: surrogate_record(args))
 
     out = {
         "metric": "AIREBO atom-steps/s on 1 GPU",
         "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * sec / args.steps, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPES[args.precision],
         "data": "synthetic (seeded generators)",
         "config": {"workload": ("" if args.potential == "airebo" else
                                 {"airebo_m": "AIREBO-M (Morse) on ", "rebo": "REBO only on "}[args.potential]) +
                                (f"polyethylene melt 106 x C100H202, {n} atoms, 0.85 g/cm^3, "
-                                f"{box[0]:.2f} A periodic cube, 300 K, NVE dt 0.5 fs, {args.precision}"
+                                f"{box[0]:.2f} A periodic cube, relaxed and equilibrated at 300 K (untimed), "
+                                f"NVE dt 0.5 fs, {args.precision}"
                                 if args.workload == "pe_melt_32k" else
                                 f"bundle of 16 (10,10) carbon nanotubes, {n} atoms, 3.4 A between walls, "
                                 f"box {box[0]:.1f} x {box[1]:.1f} x {box[2]:.1f} A periodic, 300 K, NVE dt 0.5 fs, "
@@ -259,12 +252,118 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": ferr,
-        "energy_drift": {"slope_eV_per_atom_per_ps": slope, "max_rel": maxrel, "rebuilds": rebuilds},
-        "work": {k: st[k] for k in ("lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds")},
-        "kernels_us": {k: round(v["avg_us"], 3) for k, v in kern.items()},
+        "energy_drift": {"slope_eV_per_atom_per_ps": slope, "max_rel": maxrel, "rebuilds": rebuilds,
+                         "T_start_K": float(th[0, 4]), "T_end_K": float(th[-1, 4])},
+        "work": {k: st[k] for k in ("lj_in_cut", "lj_entries", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds")},
+        "kernels_us": {k: round(v_["avg_us"], 3) for k, v_ in kern.items()},
         "forms": forms,
     }
+    out.update(extra)
     print(json.dumps(out))
+
+
+def record_or_error(make):
+    """A sub-record of the default line; a failure is reported in the record,
+    not raised, so that the headline line is still printed."""
+    try:
+        return make()
+    except Exception as e:   # noqa: BLE001 -- reported in the output
+        log(f"bench: sub-record failed: {e!r}")
+        return {"error": repr(e)}
+
+
+def timed_session(begin, ctx, n, steps, warmup, every=0):
+    """atom-steps/s of `steps` steps of an MD session: begin (untimed), warm-up
+    run (untimed), then one timed run bracketed by device synchronisations.
+    Returns (atom-steps/s, ms/step, thermo rows of the timed run or None)."""
+    import torch
+    begin()
+    ctx.md_run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = ctx.md_run(steps, thermo_every=every)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    return n * steps / sec, 1e3 * sec / steps, th
+
+
+def roofline(kern, st, prec, args):
+    """Roofline record of the kernel that dominates the step.  Algorithmic
+    work of the LJ kernel: 45 flop per LJ pair inside its cutoff (each pair
+    once) and 8 per list pair outside it (distance test only); of the
+    bonded kernel: 4,000 flop per bond (forward and reverse bond order, pair
+    term, torsion)."""
+    from paper_1810_07026_amd import airebo
+    skin_pairs = max(st["lj_entries"] // 2 - st["lj_in_cut"], 0)
+    work = {"k_lj": FLOP_PER_LJ_PAIR * st["lj_in_cut"] + FLOP_PER_SKIN_PAIR * skin_pairs,
+            "k_bond": FLOP_PER_BOND * st["bonds"]}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    cand = dom if dom in work else max(work, key=lambda k: kern.get(k, {"total_ms": 0})["total_ms"])
+    avg_s = kern[cand]["avg_us"] * 1e-6
+    peak = FP64_VALU_PEAK if prec == airebo.FP64 else FP32_VALU_PEAK
+    ach = work[cand] / avg_s
+    return {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": ach / 1e12,
+            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
+            # the committed counter profile is of the melt workload
+            "traffic": (counter_traffic(cand, args.precision)
+                        if args.workload == "pe_melt_32k" and args.potential == "airebo" else None),
+            "flop_per_launch": work[cand], "avg_launch_us": kern[cand]["avg_us"]}
+
+
+def prepare_melt(d, x, v, log):
+    """Untimed preparation of the melt: capped-step steepest descent on the
+    FP64 AIREBO forces (every atom moves at most 0.02 A per iteration), then
+    NVE with the velocities rescaled to 300 K every 50 steps, then fresh
+    300 K Maxwell velocities."""
+    import torch
+    from paper_1810_07026_amd import airebo, synth
+    s, box, per = d["species"], d["box"], d["periodic"]
+    ctx = airebo.Context()
+    x = x.clone()
+    e0 = None
+    for it in range(PREP_SD_ITERS):
+        e, f, _ = ctx.compute(x, s, box, per)
+        if e0 is None:
+            e0 = float(e[0])
+        step = PREP_SD_ALPHA * f
+        norm = step.norm(dim=1, keepdim=True)
+        x += step * torch.clamp(PREP_SD_CAP / torch.clamp(norm, min=1e-30), max=1.0)
+    e1 = float(ctx.compute(x, s, box, per)[0][0])
+    n = len(s)
+    log(f"bench: preparation: {PREP_SD_ITERS} capped steepest-descent steps, E {e0 / n:.5f} -> {e1 / n:.5f} eV/atom")
+    v = v.clone()
+    ctx.md_begin(x, v, s, box, per)
+    for _ in range(PREP_EQ_CYCLES):
+        th = ctx.md_run(PREP_EQ_STEPS, thermo_every=PREP_EQ_STEPS).cpu().numpy()
+        x, v = ctx.md_state()
+        v *= math.sqrt(300.0 / max(th[-1, 4], 1.0))
+        ctx.md_begin(x, v, s, box, per)
+    th = ctx.md_run(0, thermo_every=1).cpu().numpy()
+    ctx.md_end()
+    log(f"bench: preparation: {PREP_EQ_CYCLES} x {PREP_EQ_STEPS} NVE steps rescaled to 300 K (T {th[-1, 4]:.0f} K)")
+    v = torch.tensor(synth.maxwell_velocities(s, 300.0, np.random.default_rng(1810070268)), dtype=torch.float64,
+                     device=x.device)
+    ctx.close()
+    return x, v
+
+
+def prepare_hybrid(d, x, v, log):
+    """Untimed preparation of the hybrid slab: velocity quench (NVE in bursts
+    of 10 steps, velocities zeroed after each) relaxes the strain of the
+    assembled slabs, then fresh 300 K velocities."""
+    import torch
+    from paper_1810_07026_amd import airebo, synth
+    s, box, per = d["species"], d["box"], d["periodic"]
+    ctx = airebo.Context()
+    log("bench: hybrid preparation: 20 quench cycles of 10 steps (untimed)")
+    x, v = x.clone(), torch.zeros_like(v)
+    for _ in range(20):
+        ctx.nve(x, v, s, box, per, nsteps=10, thermo_every=0)
+        v.zero_()
+    ctx.close()
+    v = torch.tensor(synth.maxwell_velocities(s, 300.0, np.random.default_rng(1810070267)), dtype=torch.float64,
+                     device=x.device)
+    return x, v
 
 
 def force_err(f, fo):
@@ -274,24 +373,13 @@ def force_err(f, fo):
     return {"force_rms_err_eVA": e, "force_rel_rms_err": e / rms}
 
 
-def timed_nve(run, n, steps, warmup):
-    """atom-steps/s of run(nsteps) after a warm-up call (device-synchronised)."""
-    import torch
-    run(warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    extra = run(steps)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    return n * steps / sec, 1e3 * sec / steps, extra
-
-
-def measure_forms(d, x0, v0, args, fp64_value, fo):
-    """Mixed and single precision and the surrogate on the same system as the FP64 line,
-    from the state its timed run ended in: atom-steps/s of NVE and force RMS
-    error against the CPU oracle (when it was evaluated) or the FP64 GPU
-    forces at that state."""
-    import torch
+def measure_forms(d, x0, v0, args, fo):
+    """FP64, mixed and single precision and the surrogate (with and without
+    fallback) on the system of the headline line, all from the state its
+    timed run ended in and under one protocol: an MD session started from
+    that state, a warm-up run, then one timed run of --form-steps steps.
+    Force errors are against the CPU oracle at that state (when it was
+    evaluated) or the FP64 GPU forces."""
     from paper_1810_07026_amd import airebo, surrogate
     s, box, per = d["species"], d["box"], d["periodic"]
     n = len(s)
@@ -300,46 +388,106 @@ def measure_forms(d, x0, v0, args, fp64_value, fo):
     if fo is None:
         fo = ctx.compute(x0, s, box, per)[1].cpu().numpy()
         ref_kind = "fp64_gpu"
-    forms = {"reference": ref_kind, "steps": args.form_steps}
-    # mixed and single precision
-    for name, prec in (("mixed", airebo.MIXED), ("single", airebo.SINGLE)):
-        ctxm = airebo.Context(precision=prec)
-        xm, vm = x0.clone(), v0.clone()
-        val, ms, _ = timed_nve(lambda k: ctxm.nve(xm, vm, s, box, per, nsteps=k, thermo_every=0), n,
-                               args.form_steps, args.warmup)
-        fm = ctxm.compute(x0, s, box, per)[1].cpu().numpy()
-        forms[name] = dict(force_err(fm, fo), value=val, ms_per_step=ms, speedup_vs_fp64=val / fp64_value)
-        log(f"bench: {name} {val:.4g} atom-steps/s, force rel rms err {forms[name]['force_rel_rms_err']:.3g}")
-        del ctxm
-    # learned surrogate
+    forms = {"reference": ref_kind, "steps": args.form_steps, "warmup": args.warmup,
+             "protocol": "per form: session begun from the same state, warm-up run, one timed run"}
+    base = None
+    for name, prec in (("fp64", airebo.FP64), ("mixed", airebo.MIXED), ("single", airebo.SINGLE)):
+        c = ctx if prec == airebo.FP64 else airebo.Context(precision=prec)
+        val, ms, _ = timed_session(lambda: c.md_begin(x0, v0, s, box, per), c, n, args.form_steps, args.warmup)
+        c.md_end()
+        fm = c.compute(x0, s, box, per)[1].cpu().numpy()
+        base = val if base is None else base
+        forms[name] = dict(force_err(fm, fo), value=val, ms_per_step=ms, speedup_vs_fp64=val / base)
+        log(f"bench: {name} {val:.4g} atom-steps/s ({ms:.4f} ms/step), force rel rms err "
+            f"{forms[name]['force_rel_rms_err']:.3g}")
     if not os.path.exists(surrogate.WEIGHTS):
         forms["surrogate"] = {"error": "no trained weights (python -m paper_1810_07026_amd.surrogate train)"}
         return forms
     nn = airebo.Surrogate(path=surrogate.WEIGHTS)
-    e, f, _, sp, info = nn.compute(ctx, x0, s, box, per, threshold=1e30, want_spread=True)
-    sur = dict(force_err(f.cpu().numpy(), fo), threshold_eVA=surrogate.THRESHOLD,
-               max_spread_eVA=info["max_spread"], atoms_above_threshold=int((sp > surrogate.THRESHOLD).sum()))
-    for key, thr in (("with_fallback", surrogate.THRESHOLD), ("no_fallback", 1e30)):
-        xs, vs = x0.clone(), v0.clone()
-        val, ms, fb = timed_nve(lambda k: nn.nve(ctx, xs, vs, s, box, per, nsteps=k, thermo_every=0,
-                                                 threshold=thr)[1], n, args.form_steps, args.warmup)
-        # the call's initial force evaluation is counted with its steps
-        sur[key] = {"value": val, "ms_per_step": ms, "speedup_vs_fp64": val / fp64_value,
-                    "fallback_evaluations": fb, "fallback_rate": fb / (args.form_steps + 1)}
-        log(f"bench: surrogate ({key}) {val:.4g} atom-steps/s, fallbacks {fb}/{args.form_steps}")
-    forms["surrogate"] = sur
+    forms["surrogate"] = surrogate_forms(nn, ctx, x0, v0, s, box, per, fo, args.form_steps, args.warmup, base)
     return forms
 
 
-def bench_surrogate(args):
-    """Learned surrogate on a ~1e6-atom polyethylene melt (the 32,012-atom melt
-    tiled 3 x 3 x 3 = 864,324 atoms, fresh 300 K velocities, decorrelated by
-    untimed mixed-precision NVE), against AIREBO FP64 and mixed on the same
-    state; force errors against the FP64 GPU forces on every atom and
-    against the CPU oracle on sampled atoms."""
+def surrogate_forms(nn, ctx, x0, v0, s, box, per, f_ref, steps, warmup, fp64_value):
+    """Surrogate error at one state and its MD rate with and without the
+    AIREBO fallback (sessions as for the other forms); the fallback count is
+    that of the timed run."""
+    import torch
+    from paper_1810_07026_amd import surrogate
+    n = len(s)
+    e, f, _, sp, info = nn.compute(ctx, x0, s, box, per, threshold=1e30, want_spread=True)
+    f = f.cpu().numpy()
+    sp = sp.cpu().numpy()
+    rec = dict(force_err(f, f_ref), threshold_eVA=surrogate.THRESHOLD, max_spread_eVA=info["max_spread"],
+               atoms_above_threshold=int((sp > surrogate.THRESHOLD).sum()))
+    for key, thr in (("with_fallback", surrogate.THRESHOLD), ("no_fallback", 1e30)):
+        nn.md_begin(ctx, x0, v0, s, box, per, threshold=thr)
+        ctx.md_run(warmup)
+        torch.cuda.synchronize()
+        fb0 = ctx.stats()["nn_fallbacks"]
+        t0 = time.perf_counter()
+        ctx.md_run(steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        fb = ctx.stats()["nn_fallbacks"] - fb0
+        ctx.md_end()
+        val = n * steps / sec
+        rec[key] = {"value": val, "ms_per_step": 1e3 * sec / steps, "speedup_vs_fp64": val / fp64_value,
+                    "fallback_steps": int(fb), "fallback_rate": fb / steps}
+        log(f"bench: surrogate ({key}) {val:.4g} atom-steps/s, fallbacks {fb}/{steps}")
+    return rec
+
+
+def hybrid_record(args):
+    """The ~10^6-atom hybrid slab (graphite + H-terminated diamond + melt):
+    FP64 and mixed MD rates under the session protocol, and the mixed and
+    FP64 force errors against the CPU oracle on sampled atoms."""
+    import torch
+    from paper_1810_07026_amd import airebo, synth
+    from oracle.oracle import Oracle
+    d = synth.hybrid_1m()
+    s, box, per = d["species"], d["box"], d["periodic"]
+    n = len(s)
+    x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+    x, v = prepare_hybrid(d, x, v, log)
+    rec = {"workload": f"hybrid {n} atoms: AB graphite + H-terminated diamond (111) + polyethylene melt slab, "
+                       f"box {box[0]:.1f} x {box[1]:.1f} x {box[2]:.1f} A, 300 K, NVE dt 0.5 fs",
+           "n_atoms": n, "steps": args.extra_steps, "warmup": 5}
+    base = None
+    forces = {}
+    for name, prec in (("fp64", airebo.FP64), ("mixed", airebo.MIXED)):
+        c = airebo.Context(precision=prec)
+        val, ms, _ = timed_session(lambda: c.md_begin(x, v, s, box, per), c, n, args.extra_steps, 5)
+        c.md_end()
+        forces[name] = c.compute(x, s, box, per)[1].cpu().numpy()
+        base = val if base is None else base
+        rec[name] = {"value": val, "ms_per_step": ms, "speedup_vs_fp64": val / base}
+        log(f"bench: hybrid {name} {val:.4g} atom-steps/s ({ms:.3f} ms/step)")
+        c.close()
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        sel = np.sort(np.random.default_rng(0).choice(n, 4096, replace=False)).astype(np.int32)
+        t2 = time.perf_counter()
+        _, fo, _ = Oracle(nthreads=threads).compute(x.cpu().numpy(), s, box, per, sel=sel)
+        t3 = time.perf_counter()
+        fo = fo[sel]
+        for name in forces:
+            rec[name].update(force_err(forces[name][sel], fo))
+        rec["oracle_sample"] = {"atoms": len(sel), "seconds": t3 - t2, "cores": threads}
+    return rec
+
+
+def surrogate_record(args):
+    """The learned surrogate on a >= 10^6-atom melt (the 32,012-atom melt
+    tiled 3 x 3 x 4 = 1,152,432 atoms, fresh 300 K velocities decorrelated
+    by untimed mixed-precision NVE) beside AIREBO FP64 and mixed on the same
+    state; errors against the FP64 GPU forces on every atom and against the
+    CPU oracle on sampled atoms."""
     import torch
     from paper_1810_07026_amd import airebo, surrogate, synth
-    d = synth.tile(synth.pe_melt(), (3, 3, 3))
+    from oracle.oracle import Oracle
+    d = synth.tile(synth.pe_melt(), SURROGATE_TILES)
     s, box, per = d["species"], d["box"], d["periodic"]
     n = len(s)
     rng = np.random.default_rng(1810070266)
@@ -347,66 +495,48 @@ def bench_surrogate(args):
     v = torch.tensor(synth.maxwell_velocities(s, 300.0, rng), dtype=torch.float64, device="cuda")
     ctx = airebo.Context()
     ctxm = airebo.Context(precision=airebo.MIXED)
-    log(f"bench: surrogate workload n={n}; decorrelating replicas ({args.warmup} mixed NVE steps, untimed)")
-    ctxm.nve(x, v, s, box, per, nsteps=max(args.warmup, 100), thermo_every=0)
+    log(f"bench: surrogate workload n={n}; decorrelating replicas (100 mixed NVE steps, untimed)")
+    ctxm.nve(x, v, s, box, per, nsteps=100, thermo_every=0)
     torch.cuda.synchronize()
-    x0, v0 = x.clone(), v.clone()
-    e64, f64, _ = ctx.compute(x0, s, box, per)
-    f64 = f64.cpu().numpy()
+    steps = args.extra_steps
+    rec = {"workload": f"polyethylene melt of {n} atoms (106 x C100H202 tiled "
+                       f"{' x '.join(map(str, SURROGATE_TILES))}, {box[0]:.1f} x {box[1]:.1f} x {box[2]:.1f} A "
+                       f"periodic, 300 K), NVE dt 0.5 fs", "n_atoms": n, "steps": steps, "warmup": 5}
+    f64 = ctx.compute(x, s, box, per)[1].cpu().numpy()
+    fm = ctxm.compute(x, s, box, per)[1].cpu().numpy()
+    for name, c in (("fp64", ctx), ("mixed", ctxm)):
+        val, ms, _ = timed_session(lambda: c.md_begin(x, v, s, box, per), c, n, steps, 5)
+        c.md_end()
+        rec[name] = {"value": val, "ms_per_step": ms}
+        log(f"bench: surrogate workload {name} {val:.4g} atom-steps/s ({ms:.3f} ms/step)")
+    rec["mixed"]["speedup_vs_fp64"] = rec["mixed"]["value"] / rec["fp64"]["value"]
+    rec["mixed"].update(force_err(fm, f64))
     nn = airebo.Surrogate(path=surrogate.WEIGHTS)
-    err = surrogate.force_error(nn, ctx, x0, s, box, per, f64)
-    fm = ctxm.compute(x0, s, box, per)[1].cpu().numpy()
-    steps = args.steps
-    res = {}
-    for key, run in (
-            ("fp64", lambda k: ctx.nve(x, v, s, box, per, nsteps=k, thermo_every=0)),
-            ("mixed", lambda k: ctxm.nve(x, v, s, box, per, nsteps=k, thermo_every=0)),
-            ("surrogate_with_fallback", lambda k: nn.nve(ctx, x, v, s, box, per, nsteps=k, thermo_every=0,
-                                                         threshold=surrogate.THRESHOLD)[1]),
-            ("surrogate_no_fallback", lambda k: nn.nve(ctx, x, v, s, box, per, nsteps=k, thermo_every=0,
-                                                       threshold=1e30)[1])):
-        x.copy_(x0)
-        v.copy_(v0)
-        val, ms, extra = timed_nve(run, n, steps, 5)
-        res[key] = {"value": val, "ms_per_step": ms}
-        if key.startswith("surrogate"):
-            res[key]["fallback_steps"] = extra
-        log(f"bench: {key} {val:.4g} atom-steps/s ({ms:.3f} ms/step)")
-    for k in res:
-        res[k]["speedup_vs_fp64"] = res[k]["value"] / res["fp64"]["value"]
-    # per-kernel device time of the surrogate step
-    x.copy_(x0)
-    v.copy_(v0)
-    prof = nn.profile_nve(ctx, x, v, s, box, per, nsteps=5, threshold=1e30)
-    kern = {k: round(1e3 * ms / c, 2) for k, (ms, c) in prof.items() if c and k.startswith("nn")}
-    # CPU oracle on sampled atoms
-    cpu = None
-    acc_or = None
+    rec["surrogate"] = surrogate_forms(nn, ctx, x, v, s, box, per, f64, steps, 5, rec["fp64"]["value"])
+    rec["surrogate"]["error_reference"] = "fp64_gpu"
     if not args.no_cpu_baseline:
-        from oracle.oracle import Oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         sel = np.sort(rng.choice(n, 2048, replace=False)).astype(np.int32)
-        xh = x0.cpu().numpy()
-        t2 = time.perf_counter()
-        _, fo, _ = Oracle(nthreads=threads).compute(xh, s, box, per, sel=sel)
-        t3 = time.perf_counter()
+        _, fo, _ = Oracle(nthreads=threads).compute(x.cpu().numpy(), s, box, per, sel=sel)
         fo = fo[sel]
-        fn = nn.compute(ctx, x0, s, box, per, threshold=1e30)[1].cpu().numpy()[sel]
-        acc_or = {"surrogate": force_err(fn, fo), "fp64_gpu": force_err(f64[sel], fo),
-                  "mixed_gpu": force_err(fm[sel], fo), "sampled_atoms": len(sel)}
-        cpu = {"value": len(sel) / (t3 - t2), "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"exact FP64 AIREBO forces on {len(sel)} random atoms of the {n}-atom melt, "
-                         f"{t3 - t2:.1f} s"}
-    out = {"metric": "AIREBO atom-steps/s on 1 GPU", "value": res["surrogate_with_fallback"]["value"],
-           "unit": "atom-steps/s", "n_gpus": 1, "steps": steps, "warmup": 5,
-           "ms_per_step": res["surrogate_with_fallback"]["ms_per_step"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic (seeded generators)",
-           "config": {"workload": f"learned surrogate (4-member ensemble, fallback at {surrogate.THRESHOLD} eV/A) on "
-                                  f"a polyethylene melt of {n} atoms (106 x C100H202 tiled 3x3x3, "
-                                  f"{box[0]:.1f} A periodic cube, 300 K), NVE dt 0.5 fs", "n_atoms": n},
-           "forms": res, "surrogate_error_vs_fp64_gpu": err,
-           "mixed_error_vs_fp64_gpu": force_err(fm, f64), "accuracy_vs_oracle": acc_or,
-           "cpu_baseline": cpu, "kernels_us": kern}
+        fn = nn.compute(ctx, x, s, box, per, threshold=1e30)[1].cpu().numpy()[sel]
+        rec["accuracy_vs_oracle"] = {"surrogate": force_err(fn, fo), "fp64_gpu": force_err(f64[sel], fo),
+                                     "mixed_gpu": force_err(fm[sel], fo), "sampled_atoms": len(sel)}
+    return rec
+
+
+def bench_surrogate(args):
+    """The surrogate sub-record as its own line (value: surrogate with
+    fallback on the >= 10^6-atom melt)."""
+    rec = surrogate_record(args)
+    sur = rec["surrogate"]["with_fallback"]
+    out = {"metric": "AIREBO atom-steps/s on 1 GPU", "value": sur["value"], "unit": "atom-steps/s", "n_gpus": 1,
+           "steps": rec["steps"], "warmup": rec["warmup"], "ms_per_step": sur["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64",
+           "data": "synthetic (seeded generators)",
+           "config": {"workload": "learned surrogate (4-member ensemble, fallback at 0.1 eV/A) on a " +
+                                  rec["workload"], "n_atoms": rec["n_atoms"]},
+           "record": rec}
     print(json.dumps(out))
 
 
@@ -444,7 +574,7 @@ def bench_conservation(args):
     sec = time.perf_counter() - t0
     th = np.concatenate(rows)
     if args.thermo_out:
-        np.savetxt(args.thermo_out, th, fmt="%.10g", header="step PE_eV KE_eV Etot_eV T_K rebuilds")
+        np.savetxt(args.thermo_out, th, fmt="%.10g", header="step PE_eV KE_eV Etot_eV T_K rebuilds P_bar")
     e, temp = th[:, 3], th[:, 4]
     rel = (e - e[0]) / abs(e[0])
     t_ps = np.arange(len(e)) * every * args.dt * 1e-3
@@ -502,15 +632,12 @@ def bench_batch(args):
     ctx = airebo.Context(precision=prec, tune=tune)
     x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
     v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
-    ctx.batch_nve(x, v, d["species"], d["sizes"], d["boxes"], d["periodic"], nsteps=args.warmup, thermo_every=0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    th = ctx.batch_nve(x, v, d["species"], d["sizes"], d["boxes"], d["periodic"], nsteps=args.steps,
-                       thermo_every=max(1, args.steps // 10))
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
+    value, ms, th = timed_session(
+        lambda: ctx.batch_md_begin(x, v, d["species"], d["sizes"], d["boxes"], d["periodic"]), ctx, n, args.steps,
+        args.warmup, max(1, args.steps // 10))
+    ctx.md_end()
     th = th.cpu().numpy()
-    value = n * args.steps / sec
+    sec = 1e-3 * ms * args.steps
     de = np.abs(th[:, :, 3] - th[0, :, 3]).max(0) / d["sizes"]
     drift = float((np.abs(th[-1, :, 3] - th[0, :, 3])).max())
     log(f"bench: per-system max |dE|/N (eV/atom): median {np.median(de):.3g}, max {de.max():.3g} "

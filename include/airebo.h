@@ -26,6 +26,10 @@
  *   - The caller owns every array it passes; the library never frees or
  *     keeps a caller pointer beyond the call.  A context owns its parameter
  *     copy and all scratch memory.  A context is not thread safe.
+ *   - Capacities (LJ list entries per atom, deferred-pair queue) grow on
+ *     demand: an evaluation or MD chunk that overflows one is repeated with
+ *     the capacity grown.  AIREBO_E_CAPACITY is returned only when a growth
+ *     limit is reached or a fixed per-atom limit is exceeded.
  */
 #ifndef AIREBO_H
 #define AIREBO_H
@@ -89,7 +93,11 @@ typedef struct {
   int32_t defer_block; /* threads per block of the deferred-pair kernel: 64..256 (64) */
   int32_t short_block; /* threads per block of the short-list kernel: 256, 512, 1024 (1024) */
   int32_t vdw;         /* AIREBO_VDW_LJ (default) or AIREBO_VDW_MORSE (AIREBO-M)      */
-  int32_t reserved[3];
+  int32_t lj_slack;    /* LJ list entries per atom kept free beyond the largest row when an
+                          MD session sizes the list; 0 = automatic (a quarter of the
+                          largest row + 32)                                             */
+  int32_t queue_per_atom; /* initial deferred-pair queue entries per atom; 0 = automatic (8) */
+  int32_t reserved;
 } airebo_options;
 
 void airebo_options_default(airebo_options* opt);
@@ -148,11 +156,19 @@ int airebo_compute_host(airebo_ctx_t ctx, int64_t n, const double* pos, const in
  * and vel (device [n][3], A and A/fs) in place; positions are wrapped into the
  * box whenever the neighbour lists are rebuilt (when an atom has moved more
  * than half the skin since the last build).  mass: host [2] amu of C and H.
- * thermo: device [(nsteps / thermo_every) + 1][6] rows of
- * {step, PE, KE, Etot, T, rebuilds}, written for step 0 and every
- * thermo_every steps (thermo may be NULL when thermo_every <= 0).  The step
- * sequence is captured once into a HIP graph and replayed.  Errors as for
- * airebo_compute. */
+ * thermo: device [(nsteps / thermo_every) + 1][7] rows of
+ * {step, PE, KE, Etot, T, rebuilds, P}, written for step 0 and every
+ * thermo_every steps (thermo may be NULL when thermo_every <= 0).  PE and
+ * KE in eV, T in K, `rebuilds` the neighbour-list builds since the start of
+ * the call, P the pressure in bar, (2 KE + W_xx + W_yy + W_zz) / (3 V), for
+ * boxes periodic in all three directions (0 otherwise).
+ * One call is one MD session (airebo_md_begin, airebo_md_run,
+ * airebo_md_state, airebo_md_end): one step is captured into a HIP graph and
+ * replayed in chunks of 256 steps; after each chunk every error flag is
+ * read.  A list or queue overflow repeats the chunk with the capacity grown;
+ * a non-finite step (AIREBO_E_NONFINITE) or another error ends the call
+ * with pos and vel holding the state at the start of the failing chunk.
+ * Errors as for airebo_compute. */
 int airebo_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int32_t* species, const double* box,
                const int32_t* periodic, const double* mass, double dt_fs, int64_t nsteps, int64_t thermo_every,
                double* thermo, void* stream);
@@ -173,21 +189,54 @@ int airebo_batch_compute(airebo_ctx_t ctx, int32_t nsys, const int64_t* sys_off,
 
 /* Batched velocity Verlet: as airebo_nve over every system of the batch, the
  * whole step of all systems captured into one HIP graph.  thermo: device
- * [(nsteps / thermo_every) + 1][nsys][6] rows {step, PE, KE, Etot, T, rebuilds}
+ * [(nsteps / thermo_every) + 1][nsys][7] rows {step, PE, KE, Etot, T, rebuilds, P}
  * per system.  Neighbour lists of all systems are rebuilt together when any
  * atom has moved more than half the skin. */
 int airebo_batch_nve(airebo_ctx_t ctx, int32_t nsys, const int64_t* sys_off, const double* boxes,
                      const int32_t* periodic, double* pos, double* vel, const int32_t* species, const double* mass,
                      double dt_fs, int64_t nsteps, int64_t thermo_every, double* thermo, void* stream);
 
+/* Molecular-dynamics session held by the context (velocity Verlet, Sec. 2).
+ * The state stays on the device between calls, so a run of k steps costs k
+ * replays of the captured step and nothing else.
+ *   airebo_md_begin        copies pos and vel (device [n][3], read during the
+ *                          call only), sizes the lists with one evaluation,
+ *                          computes the initial forces and captures one step;
+ *                          arguments as for airebo_nve.  Ends any earlier
+ *                          session of the context.
+ *   airebo_batch_md_begin  the same for a batch (arguments as for
+ *                          airebo_batch_nve).
+ *   airebo_md_run          advances the session by nsteps steps; thermo as
+ *                          for airebo_nve (row 0: the state before the run).
+ *                          Synchronises the stream.  Overflow and error
+ *                          handling as for airebo_nve; after an error the
+ *                          session holds the state at the start of the
+ *                          failing chunk.
+ *   airebo_md_state        writes the current positions (wrapped) and
+ *                          velocities into pos and vel (device [n][3]; either
+ *                          may be NULL); ordered on `stream`.
+ *   airebo_md_end          ends the session (keeps the context's buffers).
+ * Any other call on the context (airebo_compute, ...) ends its session.
+ * Errors: AIREBO_E_ARG (no session, bad arguments) and those of airebo_nve. */
+int airebo_md_begin(airebo_ctx_t ctx, int64_t n, const double* pos, const double* vel, const int32_t* species,
+                    const double* box, const int32_t* periodic, const double* mass, double dt_fs, void* stream);
+int airebo_batch_md_begin(airebo_ctx_t ctx, int32_t nsys, const int64_t* sys_off, const double* boxes,
+                          const int32_t* periodic, const double* pos, const double* vel, const int32_t* species,
+                          const double* mass, double dt_fs, void* stream);
+int airebo_md_run(airebo_ctx_t ctx, int64_t nsteps, int64_t thermo_every, double* thermo, void* stream);
+int airebo_md_state(airebo_ctx_t ctx, double* pos, double* vel, void* stream);
+void airebo_md_end(airebo_ctx_t ctx);
+
 /* Counters of the last airebo_compute / airebo_nve call (host [16] int64):
  *   0 LJ pairs inside the cutoff (each pair once)   1 pairs with C_ij = 0
  *   2 pairs queued for the modified bond order b*   3 b* pairs with dS_b != 0
  *   4 bonds                                          5 neighbour-list rebuilds
- *   6 max short neighbours of one atom               7 reserved
+ *   6 max short neighbours of one atom               7 LJ list entries (airebo_compute)
  *   8 max LJ entries of one atom                     9 spline evaluations
  *  10 of those evaluated in FP64 near a knot (AIREBO_MIXED)
- *  11 surrogate steps that fell back to AIREBO (airebo_nn_*)    12-15 reserved
+ *  11 surrogate steps that fell back to AIREBO (airebo_nn_*)
+ *  12 capacity growths (LJ list or queue) of the last call or MD session
+ *  13-15 reserved
  * Slots 0-4 and 9-10 refer to the last force evaluation (every step in NVE). */
 int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
 
@@ -318,6 +367,13 @@ int airebo_nn_train_step(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const doub
 int airebo_nn_nve(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int32_t* species,
                   const double* box, const int32_t* periodic, const double* mass, double dt_fs, int64_t nsteps,
                   int64_t thermo_every, double* thermo, double threshold, int64_t* fallbacks, void* stream);
+/* An MD session (see airebo_md_begin) driven by surrogate forces with the
+ * fallback threshold of airebo_nn_nve; advance it with airebo_md_run, read
+ * it with airebo_md_state, end it with airebo_md_end.  The surrogate object
+ * must outlive the session. */
+int airebo_nn_md_begin(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, const double* pos, const double* vel,
+                       const int32_t* species, const double* box, const int32_t* periodic, const double* mass,
+                       double dt_fs, double threshold, void* stream);
 /* Per-kernel timing of airebo_nn_nve; output as for airebo_profile_nve. */
 int airebo_nn_profile_nve(airebo_nn_t nn, airebo_ctx_t ctx, int64_t n, double* pos, double* vel,
                           const int32_t* species, const double* box, const int32_t* periodic, const double* mass,

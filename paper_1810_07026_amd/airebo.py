@@ -18,8 +18,10 @@ FP64, MIXED, SINGLE = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "single": SINGLE}
 VDW_LJ, VDW_MORSE = 0, 1
 TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
+THERMO_COLUMNS = ("step", "PE", "KE", "Etot", "T", "rebuilds", "P_bar")
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
-              "reserved7", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks"]
+              "lj_entries", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks",
+              "regrowths"]
 
 EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "airebo_compute", "airebo_nve",
            "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name",
@@ -30,7 +32,9 @@ EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "ai
            "airebo_nn_compute", "airebo_nn_gradient", "airebo_nn_adam", "airebo_nn_nve", "airebo_nn_profile_nve",
            "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check",
            "airebo_params_load", "airebo_params_parse", "airebo_params_free", "airebo_ctx_create_from_params",
-           "airebo_compute_host", "airebo_nn_train_step"]
+           "airebo_compute_host", "airebo_nn_train_step",
+           "airebo_md_begin", "airebo_batch_md_begin", "airebo_md_run", "airebo_md_state", "airebo_md_end",
+           "airebo_nn_md_begin"]
 
 
 class AireboError(RuntimeError):
@@ -43,9 +47,11 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("term_mask", ctypes.c_int32), ("skin", ctypes.c_double),
                 ("lj_cap", ctypes.c_int32), ("device", ctypes.c_int32), ("bond_block", ctypes.c_int32),
                 ("bond_grid", ctypes.c_int32), ("defer_block", ctypes.c_int32), ("short_block", ctypes.c_int32),
-                ("vdw", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("vdw", ctypes.c_int32), ("lj_slack", ctypes.c_int32), ("queue_per_atom", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     TUNABLES = ("bond_block", "bond_grid", "defer_block", "short_block")
+    CAPACITIES = ("lj_slack", "queue_per_atom")
 
 
 _lib = None
@@ -102,6 +108,19 @@ def load_library(path=LIB_PATH):
                                    ctypes.POINTER(ctypes.c_int32), dp, dp, ip, ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_double, ctypes.c_int64, ctypes.c_int64, dp, vp]
     L.airebo_batch_nve.restype = ctypes.c_int
+    hdp2 = ctypes.POINTER(ctypes.c_double)
+    L.airebo_md_begin.argtypes = [vp, ctypes.c_int64, dp, dp, ip, hdp2, ctypes.POINTER(ctypes.c_int32), hdp2,
+                                  ctypes.c_double, vp]
+    L.airebo_md_begin.restype = ctypes.c_int
+    L.airebo_batch_md_begin.argtypes = [vp, ctypes.c_int32, i64p, hdp2, ctypes.POINTER(ctypes.c_int32), dp, dp, ip,
+                                        hdp2, ctypes.c_double, vp]
+    L.airebo_batch_md_begin.restype = ctypes.c_int
+    L.airebo_md_run.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, dp, vp]
+    L.airebo_md_run.restype = ctypes.c_int
+    L.airebo_md_state.argtypes = [vp, dp, dp, vp]
+    L.airebo_md_state.restype = ctypes.c_int
+    L.airebo_md_end.argtypes = [vp]
+    L.airebo_md_end.restype = None
     L.airebo_last_error.argtypes = []
     L.airebo_last_error.restype = ctypes.c_char_p
     # learned surrogate
@@ -127,6 +146,7 @@ def load_library(path=LIB_PATH):
         "airebo_nn_train_step": geo + [dp, c_d, c_d, c_d, c_d, hd, vp],
         "airebo_nn_nve": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_i64, c_i64, dp, c_d,
                           ctypes.POINTER(ctypes.c_int64), vp],
+        "airebo_nn_md_begin": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_d, vp],
         "airebo_nn_profile_nve": [vp, vp, c_i64, dp, dp, ip, hd, hi32, hd, c_d, c_i64, c_d,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), vp],
         "airebo_nn_save": [vp, ctypes.c_char_p],
@@ -151,6 +171,18 @@ def _check(L, rc):
 def _host3(a, ctype):
     arr = (ctype * 3)(*a)
     return arr
+
+
+def _state(t, n, name, device):
+    """A positions or velocities tensor the library may read and write as
+    double [n][3]: float64, contiguous, shape (n, 3), on the context's device."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device == device):
+        raise AireboError(-1, f"{name} must be a CUDA tensor on {device}")
+    if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (n, 3):
+        raise AireboError(-1, f"{name} must be a contiguous float64 tensor of shape ({n}, 3), "
+                              f"got {t.dtype} {tuple(t.shape)}{'' if t.is_contiguous() else ' (non-contiguous)'}")
+    return t
 
 
 class ParamSet:
@@ -190,7 +222,7 @@ class Context:
         o.precision, o.term_mask, o.skin, o.lj_cap, o.device = precision, term_mask, skin, lj_cap, device
         o.vdw = vdw
         for k, v in (tune or {}).items():
-            if k not in Options.TUNABLES:
+            if k not in Options.TUNABLES + Options.CAPACITIES:
                 raise AireboError(-1, f"unknown tunable {k}")
             setattr(o, k, int(v))
         self.tune = dict(tune or {})
@@ -249,13 +281,15 @@ class Context:
 
     def nve(self, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5, nsteps=10,
             thermo_every=1):
-        """Velocity Verlet in place on device tensors x, v; returns the thermo rows (device tensor)."""
+        """Velocity Verlet in place on device tensors x, v; returns the thermo rows (device tensor,
+        columns THERMO_COLUMNS)."""
         import torch
-        assert x.is_cuda and v.is_cuda and x.dtype == torch.float64 and v.dtype == torch.float64
         s = self._dev(species, torch.int32)
-        n = x.shape[0]
+        n = s.shape[0]
+        _state(x, n, "x", self.device)
+        _state(v, n, "v", self.device)
         rows = nsteps // thermo_every + 1 if thermo_every > 0 else 1
-        th = torch.zeros((rows, 6), dtype=torch.float64, device=self.device)
+        th = torch.zeros((rows, len(THERMO_COLUMNS)), dtype=torch.float64, device=self.device)
         m = (ctypes.c_double * 2)(*masses)
         rc = self.L.airebo_nve(self.h, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
                                ctypes.c_void_p(s.data_ptr()), _host3(box, ctypes.c_double),
@@ -267,8 +301,9 @@ class Context:
     def profile_nve(self, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5, nsteps=10):
         """Per-kernel device time over nsteps eager NVE steps: {name: (total ms, launches)}."""
         import torch
-        assert x.is_cuda and v.is_cuda
         s = self._dev(species, torch.int32)
+        _state(x, s.shape[0], "x", self.device)
+        _state(v, s.shape[0], "v", self.device)
         nk = self.L.airebo_kernel_count()
         ms = (ctypes.c_double * nk)()
         cnt = (ctypes.c_int64 * nk)()
@@ -309,13 +344,16 @@ class Context:
 
     def batch_nve(self, x, v, species, sizes, boxes, periodic=None, masses=(12.011, 1.008), dt=0.5, nsteps=10,
                   thermo_every=1):
-        """Batched velocity Verlet in place; returns thermo [rows, nsys, 6] (device tensor)."""
+        """Batched velocity Verlet in place; returns thermo [rows, nsys, 7] (device tensor)."""
         import torch
-        assert x.is_cuda and v.is_cuda
         s = self._dev(species, torch.int32)
         nsys, off, b, p = self._batch_host(sizes, boxes, periodic)
+        if int(off[-1]) != s.shape[0]:
+            raise AireboError(-1, f"system sizes add up to {int(off[-1])} atoms, species has {s.shape[0]}")
+        _state(x, s.shape[0], "x", self.device)
+        _state(v, s.shape[0], "v", self.device)
         rows = nsteps // thermo_every + 1 if thermo_every > 0 else 1
-        th = torch.zeros((rows, nsys, 6), dtype=torch.float64, device=self.device)
+        th = torch.zeros((rows, nsys, len(THERMO_COLUMNS)), dtype=torch.float64, device=self.device)
         m = (ctypes.c_double * 2)(*masses)
         rc = self.L.airebo_batch_nve(
             self.h, nsys, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -324,6 +362,67 @@ class Context:
             nsteps, thermo_every, ctypes.c_void_p(th.data_ptr()), self._stream())
         _check(self.L, rc)
         return th
+
+    # ---- MD session: state held on the device between calls
+    def md_begin(self, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5):
+        """Start an MD session from device tensors x, v (copied; they are not modified)."""
+        import torch
+        s = self._dev(species, torch.int32)
+        n = s.shape[0]
+        _state(x, n, "x", self.device)
+        _state(v, n, "v", self.device)
+        self._md = (n, 1, s)   # the species tensor must outlive the call only; kept for md_state shapes
+        m = (ctypes.c_double * 2)(*masses)
+        _check(self.L, self.L.airebo_md_begin(self.h, n, _p(x), _p(v), _p(s), _host3(box, ctypes.c_double),
+                                              _host3(periodic, ctypes.c_int32), m, dt, self._stream()))
+
+    def batch_md_begin(self, x, v, species, sizes, boxes, periodic=None, masses=(12.011, 1.008), dt=0.5):
+        import torch
+        s = self._dev(species, torch.int32)
+        nsys, off, b, p = self._batch_host(sizes, boxes, periodic)
+        if int(off[-1]) != s.shape[0]:
+            raise AireboError(-1, f"system sizes add up to {int(off[-1])} atoms, species has {s.shape[0]}")
+        _state(x, s.shape[0], "x", self.device)
+        _state(v, s.shape[0], "v", self.device)
+        self._md = (s.shape[0], nsys, s)
+        m = (ctypes.c_double * 2)(*masses)
+        _check(self.L, self.L.airebo_batch_md_begin(
+            self.h, nsys, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            _p(x), _p(v), _p(s), m, dt, self._stream()))
+
+    def md_run(self, nsteps, thermo_every=0):
+        """Advance the session; returns thermo rows [rows, 7] ([rows, nsys, 7] for a batch) or None."""
+        import torch
+        if getattr(self, "_md", None) is None:
+            raise AireboError(-1, "no MD session")
+        n, nsys, _ = self._md
+        th = None
+        if thermo_every > 0:
+            rows = nsteps // thermo_every + 1
+            shape = (rows, len(THERMO_COLUMNS)) if nsys == 1 else (rows, nsys, len(THERMO_COLUMNS))
+            th = torch.zeros(shape, dtype=torch.float64, device=self.device)
+        _check(self.L, self.L.airebo_md_run(self.h, nsteps, thermo_every, _p(th) if th is not None else None,
+                                            self._stream()))
+        return th
+
+    def md_state(self, x=None, v=None):
+        """Current positions and velocities of the session (new tensors unless given)."""
+        import torch
+        if getattr(self, "_md", None) is None:
+            raise AireboError(-1, "no MD session")
+        n = self._md[0]
+        x = torch.empty((n, 3), dtype=torch.float64, device=self.device) if x is None else _state(x, n, "x",
+                                                                                                  self.device)
+        v = torch.empty((n, 3), dtype=torch.float64, device=self.device) if v is None else _state(v, n, "v",
+                                                                                                  self.device)
+        _check(self.L, self.L.airebo_md_state(self.h, _p(x), _p(v), self._stream()))
+        return x, v
+
+    def md_end(self):
+        self.L.airebo_md_end(self.h)
+        self._md = None
+        self._md_nn = None
 
     def stats(self):
         out = (ctypes.c_int64 * 16)()
@@ -494,10 +593,11 @@ class Surrogate:
 
         Returns (thermo rows, steps evaluated by AIREBO)."""
         import torch
-        assert x.is_cuda and v.is_cuda and x.dtype == torch.float64 and v.dtype == torch.float64
         s = torch.as_tensor(species, dtype=torch.int32, device=self.device).contiguous()
+        _state(x, s.shape[0], "x", self.device)
+        _state(v, s.shape[0], "v", self.device)
         rows = nsteps // thermo_every + 1 if thermo_every > 0 else 1
-        th = torch.zeros((rows, 6), dtype=torch.float64, device=self.device)
+        th = torch.zeros((rows, len(THERMO_COLUMNS)), dtype=torch.float64, device=self.device)
         m = (ctypes.c_double * 2)(*masses)
         nfb = ctypes.c_int64()
         _check(self.L, self.L.airebo_nn_nve(self.h, ctx.h, x.shape[0], _p(x), _p(v), _p(s),
@@ -511,6 +611,8 @@ class Surrogate:
         """Per-kernel device time over nsteps eager surrogate NVE steps: {name: (total ms, launches)}."""
         import torch
         s = torch.as_tensor(species, dtype=torch.int32, device=self.device).contiguous()
+        _state(x, s.shape[0], "x", self.device)
+        _state(v, s.shape[0], "v", self.device)
         nk = self.L.airebo_kernel_count()
         ms = (ctypes.c_double * nk)()
         cnt = (ctypes.c_int64 * nk)()
@@ -519,6 +621,21 @@ class Surrogate:
                                                      _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32),
                                                      m, dt, nsteps, float(threshold), ms, cnt, self._stream()))
         return {self.L.airebo_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(nk)}
+
+    def md_begin(self, ctx, x, v, species, box, periodic=(1, 1, 1), masses=(12.011, 1.008), dt=0.5,
+                 threshold=0.1):
+        """Start an MD session of `ctx` driven by this surrogate (advance it with ctx.md_run)."""
+        import torch
+        s = torch.as_tensor(species, dtype=torch.int32, device=self.device).contiguous()
+        n = s.shape[0]
+        _state(x, n, "x", self.device)
+        _state(v, n, "v", self.device)
+        m = (ctypes.c_double * 2)(*masses)
+        ctx._md = (n, 1, s)
+        ctx._md_nn = self   # the surrogate must outlive the session
+        _check(self.L, self.L.airebo_nn_md_begin(self.h, ctx.h, n, _p(x), _p(v), _p(s),
+                                                 _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32), m,
+                                                 dt, float(threshold), self._stream()))
 
 
 def mfma_check(A, B):

@@ -42,6 +42,7 @@
 #include <type_traits>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -81,8 +82,8 @@ const char* const kKernelNames[K_COUNT] = {
     "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo", "nn_zero", "nn_order", "nn_desc",
     "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32"};
 // statistics slots (unsigned long long)
-enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_MAXPATH = 7,
-       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_N = 16 };
+enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_LJENT = 7,
+       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_N = 16 };
 
 // One system of a batch: its own periodic box and cell grid.  A single
 // configuration is a batch of one.
@@ -261,8 +262,9 @@ __device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx,
     }
   }
   bool kx = x < (R)0 || x > (R)4, ky = y < (R)0 || y > (R)4;
-  x = x < (R)0 ? (R)0 : (x > (R)4 ? (R)4 : x);
-  y = y < (R)0 ? (R)0 : (y > (R)4 ? (R)4 : y);
+  // clamped to the table (a NaN argument maps to the first cell)
+  x = fmin(fmax(x, (R)0), (R)4);
+  y = fmin(fmax(y, (R)0), (R)4);
   int cx = min((int)x, 3), cy = min((int)y, 3);
   R tx = x - (R)cx, ty = y - (R)cy;
   const double* c = Pc[cx][cy];
@@ -296,9 +298,10 @@ __device__ __forceinline__ R tricubic(const DevParams& P, int t, R x, R y, R z, 
     }
   }
   bool kx = x < (R)0 || x > (R)4, ky = y < (R)0 || y > (R)4, kz = z < (R)1 || z > (R)9;
-  x = x < (R)0 ? (R)0 : (x > (R)4 ? (R)4 : x);
-  y = y < (R)0 ? (R)0 : (y > (R)4 ? (R)4 : y);
-  z = z < (R)1 ? (R)1 : (z > (R)9 ? (R)9 : z);
+  // clamped to the table (a NaN argument maps to the first cell)
+  x = fmin(fmax(x, (R)0), (R)4);
+  y = fmin(fmax(y, (R)0), (R)4);
+  z = fmin(fmax(z, (R)1), (R)9);
   int cx = min((int)x, 3), cy = min((int)y, 3), cz = min((int)z - 1, 7);
   int cell = (cx * 4 + cy) * 8 + cz;
   dx = dy = dz = 0;
@@ -371,6 +374,18 @@ struct AccT {
 template <typename A> __device__ __forceinline__ A* fbuf(const Dev& D);
 template <> __device__ __forceinline__ double* fbuf<double>(const Dev& D) { return D.F; }
 template <> __device__ __forceinline__ float* fbuf<float>(const Dev& D) { return D.F32; }
+
+// Copy the parameter block into LDS (all threads of the block take part).
+// The bond-order code reads spline knots and coefficients at lane-dependent
+// addresses in long dependent chains; from LDS each of those reads costs a
+// fraction of an L2 round trip.
+__device__ __forceinline__ void stage_params(DevParams& dst, const DevParams* __restrict__ src) {
+  static_assert(sizeof(DevParams) % 8 == 0, "parameter block is copied in 8-byte words");
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(&dst);
+  for (int k = threadIdx.x; k < (int)(sizeof(DevParams) / 8); k += blockDim.x) d[k] = s[k];
+  __syncthreads();
+}
 
 // Block reduction of `nv` doubles per thread into global accumulators.
 template <int NV>
@@ -1130,7 +1145,9 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
 template <typename R, typename A>
 __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
   if (D.skip && *D.skip) return;
-  const DevParams& P = *Pp;
+  __shared__ DevParams sP;
+  stage_params(sP, Pp);
+  const DevParams& P = sP;
   int n0 = D.bcount[0], n1 = D.bcount[1], n2 = D.bcount[2];
   n0 = min(n0, D.bcap); n1 = min(n1, D.bcap); n2 = min(n2, D.bcap);
   int total = n0 + n1 + n2;
@@ -1275,6 +1292,47 @@ __device__ __forceinline__ void morse_pair(const DevParams& P, int p, R r, R& V,
   dV = dv * S + v * dS * isw;
 }
 
+// Per-species-pair constants of the plain pair term, read once per kernel
+// (uniform loads) and selected per lane by the pair class p, so that the
+// pair loop issues no parameter load that depends on a gathered position.
+struct PairConst {
+  double rc2[3], sg2[3], e4[3], r0[3], rlj2[3];
+  double rconn2, isw;
+  __device__ void load(const DevParams& P) {
+    for (int p = 0; p < 3; ++p) {
+      rc2[p] = P.rc2[p];
+      sg2[p] = P.sigma[p] * P.sigma[p];
+      e4[p] = 4.0 * P.eps[p];
+      r0[p] = P.rc[p] - P.lj_sw;
+      rlj2[p] = P.rljmax[p] * P.rljmax[p];
+    }
+    rconn2 = P.r_conn * P.r_conn;
+    isw = 1.0 / P.lj_sw;
+  }
+};
+__device__ __forceinline__ double sel3(const double (&a)[3], int p) { return p == 0 ? a[0] : (p == 1 ? a[1] : a[2]); }
+
+// Plain LJ pair from r^2 with the pair-class constants already selected:
+// sg2 = sigma^2, e4 = 4 eps, r0 = start of the outer switch.
+template <typename R>
+__device__ __forceinline__ void lj_pair_r2c(R r2, R sg2, R e4, R r0, R isw, R& V, R& G) {
+  R ir2 = (R)1 / r2;
+  R s2 = sg2 * ir2;
+  R s6 = s2 * s2 * s2;
+  R v = e4 * (s6 * s6 - s6);
+  R gv = e4 * ((R)-12 * s6 * s6 + (R)6 * s6) * ir2;
+  if (r2 > r0 * r0) {
+    R r = sqrt(r2);
+    R dS;
+    R S = Sw((r - r0) * isw, dS);
+    V = v * S;
+    G = gv * S + v * dS * isw / r;
+  } else {
+    V = v;
+    G = gv;
+  }
+}
+
 // The van der Waals pair term: Lennard-Jones, or Morse with M (AIREBO-M).
 template <typename R, bool M>
 __device__ __forceinline__ void vdw_pair(const DevParams& P, int p, R r, R& V, R& dV) {
@@ -1332,6 +1390,11 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
   // deferred pairs of the wavefront, appended to the queue in one reservation
   // when WAVE more might not fit and at the end
   __shared__ int4 dq[LJ_BLOCK / WAVE][2 * WAVE];
+  // per-pair-class constants of the plain pair term, read by lane-dependent
+  // class index from LDS
+  __shared__ PairConst K;
+  if (threadIdx.x == 0) K.load(P);
+  __syncthreads();
   int ndq = 0;
   int lane = threadIdx.x & (WAVE - 1);
   int wv = threadIdx.x / WAVE;
@@ -1344,6 +1407,7 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
     double4 xi = D.x[i];
     int si = __double2int_rn(xi.w);
     const SysBox& B = box_of(D, i);
+    const double Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
     // ---- path map: levels 1 and 2, one lane per (q1, q2)
     int ncand = 0;
     {
@@ -1437,15 +1501,15 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
         code = (int)(ent >> 27);
         double4 xj = D.x[j];
         // relative vector in A: single precision forms it from FP32 positions
-        A dx = (A)xj.x - (A)xi.x + (A)((code / 9 - 1) * B.L[0]);
-        A dy = (A)xj.y - (A)xi.y + (A)(((code / 3) % 3 - 1) * B.L[1]);
-        A dz = (A)xj.z - (A)xi.z + (A)((code % 3 - 1) * B.L[2]);
+        A dx = (A)xj.x - (A)xi.x + (A)((code / 9 - 1) * Lx);
+        A dy = (A)xj.y - (A)xi.y + (A)(((code / 3) % 3 - 1) * Ly);
+        A dz = (A)xj.z - (A)xi.z + (A)((code % 3 - 1) * Lz);
         A r2 = dx * dx + dy * dy + dz * dz;
         int p = si + __double2int_rn(xj.w);
-        if (r2 < P.rc2[p]) {
+        if ((double)r2 < sel3(K.rc2, p)) {
           if (i < j) ++n_in;
           bool plain = true;
-          if (r2 < P.r_conn * P.r_conn) {
+          if (r2 < K.rconn2) {
             double prod = 0.0;
             int h = hslot(j);
             for (int probe = 0; probe < HCAP; ++probe) {
@@ -1462,7 +1526,7 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
             if (prod >= 1.0) {
               if (i < j) ++n_c0;
               plain = false;
-            } else if (prod > 0.0 || r2 < P.rljmax[p] * P.rljmax[p]) {
+            } else if (prod > 0.0 || r2 < sel3(K.rlj2, p)) {
               push = i < j;
               plain = false;
             }
@@ -1470,8 +1534,9 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
           if (plain) {
             // pair arithmetic in R on the relative vector; accumulation in A
             // (energy and virial halved once, at the end)
-            R V, g;
-            vdw_pair_r2<R, M>(P, p, (R)r2, V, g);   // dE/dr_ij vector = g * d
+            R V, g;   // dE/dr_ij vector = g * d
+            if constexpr (M) vdw_pair_r2<R, M>(P, p, (R)r2, V, g);
+            else lj_pair_r2c<R>((R)r2, (R)sel3(K.sg2, p), (R)sel3(K.e4, p), (R)sel3(K.r0, p), (R)K.isw, V, g);
             e += (A)V;
             R fx = g * (R)dx, fy = g * (R)dy, fz = g * (R)dz;
             fi[0] += (A)fx; fi[1] += (A)fy; fi[2] += (A)fz;
@@ -1508,7 +1573,9 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
 template <typename R, typename A, bool M>
 __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
-  const DevParams& P = *Pp;
+  __shared__ DevParams sP;
+  stage_params(sP, Pp);
+  const DevParams& P = sP;
   __shared__ int seg_start[NSEG + 1];
   if (threadIdx.x == 0) {
     int run = 0;
@@ -1589,12 +1656,20 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
   block_reduce_add<13>(v13, D.acc + A_ELJ);  // A_ELJ .. A_SPL64
 }
 
-// Maximum of per-atom counts into a statistics slot (one atomic per wavefront).
-__global__ void k_max(const int* __restrict__ a, int n, unsigned long long* out) {
+// Maximum of per-atom counts into a statistics slot, and the sum of the
+// counts clamped to `cap` into another (one atomic each per wavefront).
+__global__ void k_max(const int* __restrict__ a, int n, int cap, unsigned long long* out_max,
+                      unsigned long long* out_sum) {
   int m = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) m = max(m, a[t]);
+  unsigned long long sum = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    m = max(m, a[t]);
+    sum += (unsigned long long)min(a[t], cap);
+  }
   m = wave_max(m);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && m > 0) atomicMax(out, (unsigned long long)m);
+  sum = wave_sum(sum);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && m > 0) atomicMax(out_max, (unsigned long long)m);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && sum > 0) atomicAdd(out_sum, sum);
 }
 
 __global__ void k_finish(Dev D, double* energy, double* virial) {
@@ -1678,39 +1753,60 @@ __global__ void k_kick(Dev D, double* vel, double m0, double m1, double dt) {
       vel[3 * i + c] = v;
       ke += 0.5 * m * v * v / FTM;
     }
+    // a step that diverges stops the run at the end of its chunk
+    if (!isfinite(ke)) atomicOr(D.flags, F_NONFINITE);
   }
   double v1[1] = {ke};
   if (D.nsys > 1) sys_add<1>(D, i < D.n ? sys_of(D, i) : 0, v1, A_KE, i < D.n);
   block_reduce_add<1>(v1, D.acc + A_KE);
 }
 
-// Thermo rows {step, PE, KE, Etot, T, rebuilds}: one row per system and
-// output step ([row][nsys][6]); one block.
-__global__ void k_thermo(Dev D, double* thermo, int every, int nrows) {
+// Control block of an MD run: where k_thermo writes its rows.  It lives in
+// device memory and is written by the host before a run's replays, so the
+// captured step does not depend on the run's output buffer.
+struct MdCtl {
+  double* thermo;   // [nrows][nsys][THERMO_W] or null
+  int every;        // a row every `every` steps (0: none)
+  int nrows;
+};
+constexpr int THERMO_W = 7;
+constexpr double EV_A3_TO_BAR = 1.602176634e6;
+
+// Thermo rows {step, PE, KE, Etot, T, rebuilds, P}: one row per system and
+// output step ([row][nsys][THERMO_W]); one block.  P (bar) = (2 KE + tr W) /
+// (3 V), defined for systems periodic in all three directions (0 otherwise).
+__global__ void k_thermo(Dev D, const MdCtl* __restrict__ ctl) {
   int s = *D.step;
+  double* thermo = ctl->thermo;
+  int every = ctl->every, nrows = ctl->nrows;
   __syncthreads();
   if (blockIdx.x == 0 && thermo && every > 0 && s % every == 0 && s / every < nrows) {
     for (int sid = threadIdx.x; sid < D.nsys; sid += blockDim.x) {
-      double pe = 0, ke = 0;
+      double pe = 0, ke = 0, w = 0;
       int na = D.sys[sid].natoms;
       if (D.nsys == 1) {
         for (int g = 0; g < NSLOT; ++g) {
           const double* a = D.acc + g * A_N;
           pe += a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
           ke += a[A_KE];
+          w += a[A_VIR] + a[A_VIR + 1] + a[A_VIR + 2];
         }
       } else {
         const double* a = D.sys_acc + (size_t)sid * A_N;
         pe = a[A_EREBO] + a[A_ELJ] + a[A_ETORS];
         ke = a[A_KE];
+        w = a[A_VIR] + a[A_VIR + 1] + a[A_VIR + 2];
       }
-      double* row = thermo + 6 * ((size_t)(s / every) * D.nsys + sid);
+      const SysBox& B = D.sys[sid];
+      bool per = B.per[0] && B.per[1] && B.per[2];
+      double* row = thermo + THERMO_W * ((size_t)(s / every) * D.nsys + sid);
       row[0] = s;
       row[1] = pe;
       row[2] = ke;
       row[3] = pe + ke;
       row[4] = na > 1 ? 2.0 * ke / ((3.0 * na - 3.0) * KB) : 0.0;
       row[5] = (double)D.stats[S_REBUILD];
+      row[6] = per ? (2.0 * ke + w) / (3.0 * B.L[0] * B.L[1] * B.L[2]) * EV_A3_TO_BAR : 0.0;
     }
   }
   __syncthreads();
@@ -1827,6 +1923,34 @@ struct airebo_ctx {
   size_t c_asys = 0;
   double* sys_acc = nullptr;
   size_t c_sacc = 0;
+  // deferred-pair queue entries reserved per atom (grows on overflow)
+  int q_per_atom = 8;
+  // capacity growths of the current call or MD session (statistics slot S_REGROW)
+  unsigned long long regrow = 0;
+  // molecular-dynamics session (airebo_md_*): the run's parameters, its
+  // device state and save area, and the captured step
+  struct Md {
+    bool on = false;
+    int nsys = 0;
+    std::vector<int64_t> off;
+    std::vector<double> boxes;
+    std::vector<int32_t> pers;
+    double m0 = 0, m1 = 0, dt = 0;
+    std::function<void(hipStream_t, bool)> forces;   // one force evaluation (bool: zero the sums first)
+    const int* skip = nullptr;                       // surrogate: flag that skips the AIREBO kernels
+    double* vel = nullptr;                           // velocities [n][3]
+    double4* xsave = nullptr;                        // state at the start of the current chunk
+    double* vsave = nullptr;
+    unsigned long long* ssave = nullptr;             // [S_N] statistics, then the step counter
+    size_t c_vel = 0, c_xs = 0, c_vs = 0, c_ss = 0;
+    void* ctl = nullptr;                             // device MdCtl
+    double hctl[2] = {0, 0};                         // host image of the control block (pointer + two ints)
+    double* scratch = nullptr;                       // energies / virials of the sizing evaluation
+    size_t c_scr = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cs = nullptr;
+  } md;
   // per-kernel timing (profile mode)
   bool prof = false;
   struct Ev { int k; hipEvent_t a, b; };
@@ -1881,7 +2005,8 @@ int check_options(const airebo_options& o) {
   if (o.vdw != AIREBO_VDW_LJ && o.vdw != AIREBO_VDW_MORSE) return fail(AIREBO_E_ARG, "unknown van der Waals form");
   if (o.vdw == AIREBO_VDW_MORSE && o.precision != AIREBO_FP64)
     return fail(AIREBO_E_ARG, "the Morse (AIREBO-M) form is evaluated in FP64 only");
-  if (o.lj_cap < 0) return fail(AIREBO_E_ARG, "bad lj_cap");
+  if (o.lj_cap < 0 || o.lj_slack < 0 || o.queue_per_atom < 0 || o.queue_per_atom > 1024)
+    return fail(AIREBO_E_ARG, "bad lj_cap, lj_slack or queue_per_atom");
   auto okb = [](int b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; };
   auto oks = [](int b) { return b == 0 || b == 256 || b == 512 || b == 1024; };
   if (!okb(o.bond_block) || !okb(o.defer_block) || !oks(o.short_block) || o.bond_grid < 0)
@@ -1894,6 +2019,7 @@ int check_options(const airebo_options& o) {
 int ctx_create_impl(const DevParams& P, const std::vector<double>& tri, const airebo_options& o, airebo_ctx_t* out) {
   airebo_ctx* c = new airebo_ctx();
   c->opt = o;
+  if (o.queue_per_atom > 0) c->q_per_atom = o.queue_per_atom;
   c->P = P;
   c->P.knot_delta = o.precision == AIREBO_SINGLE ? -1.0 : KNOT_DELTA;   // single: FP32 everywhere
   if (o.vdw == AIREBO_VDW_MORSE && !P.morse_ok) {
@@ -1969,6 +2095,12 @@ int airebo_ctx_create(const char* path, const airebo_options* opt, airebo_ctx_t*
 
 void airebo_ctx_free(airebo_ctx_t c) {
   if (!c) return;
+  if (c->md.exec) (void)hipGraphExecDestroy(c->md.exec);
+  if (c->md.graph) (void)hipGraphDestroy(c->md.graph);
+  if (c->md.cs) (void)hipStreamDestroy(c->md.cs);
+  void* mdp[] = {c->md.vel, c->md.xsave, c->md.vsave, c->md.ssave, c->md.ctl, c->md.scratch};
+  for (void* p : mdp)
+    if (p) hipFree(p);
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
@@ -1988,7 +2120,12 @@ namespace {
 // Size buffers for a batch of nsys systems (atoms of system k are
 // [off[k], off[k+1]); box and periodic flags [nsys][3]); fill the Dev
 // descriptor and upload the per-system boxes.
-int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, hipStream_t s) {
+void md_end_impl(airebo_ctx* c);
+
+int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, hipStream_t s,
+          bool keep_md = false) {
+  // any other use of the context ends an MD session: its captured step holds the buffers set up here
+  if (c->md.on && !keep_md) md_end_impl(c);
   if (nsys < 1 || !off || !boxes || !pers) return fail(AIREBO_E_ARG, "null box, periodic or offsets");
   int64_t n = off[nsys] - off[0];
   if (off[0] != 0 || n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
@@ -2052,7 +2189,7 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   size_t bcap = N * SCAP / 2 + 64;
   rc |= grow(c->bonds, c->c_b, 3 * bcap);
   rc |= grow(c->qcount, c->c_qc, NSEG * QSTRIDE);
-  size_t qcap = (8 * N + 1024 * NSEG) / NSEG;   // per segment
+  size_t qcap = ((size_t)c->q_per_atom * N + 1024 * NSEG) / NSEG;   // per segment
   rc |= grow(c->q, c->c_q, qcap * NSEG);
   rc |= grow(c->F, c->c_F, 3 * N);
   if (c->opt.precision == AIREBO_SINGLE) {
@@ -2175,6 +2312,26 @@ int check_flags(airebo_ctx* c, int flags) {
   if (flags & F_OV_PATH) return fail(AIREBO_E_CAPACITY, "path map capacity exceeded");
   if (flags & F_OV_BOND) return fail(AIREBO_E_CAPACITY, "bond list capacity exceeded");
   if (flags & F_OV_QUEUE) return fail(AIREBO_E_CAPACITY, "b* queue capacity exceeded");
+  if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded");
+  if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 192 neighbours within 6 A or 48 within 3.5 A");
+  return 0;
+}
+
+// Capacity growth after an overflow reported in `flags`: the LJ list to the
+// largest row seen (plus headroom), the deferred-pair queue to twice its
+// entries per atom.  Returns nonzero when a limit is reached.
+int grow_caps(airebo_ctx* c, int flags) {
+  ++c->regrow;
+  if (flags & F_OV_LJ) {
+    if (c->lj_cap >= (1 << 16)) return 1;
+    unsigned long long need = c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32;
+    c->lj_cap = (int)std::min<unsigned long long>(std::max<unsigned long long>(need, c->lj_cap + c->lj_cap / 2 + 32),
+                                                  1u << 16);
+  }
+  if (flags & F_OV_QUEUE) {
+    if (c->q_per_atom >= 1024) return 1;
+    c->q_per_atom *= 2;
+  }
   return 0;
 }
 
@@ -2185,7 +2342,8 @@ int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* box
                  void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(hipSetDevice(c->opt.device));
-  for (int attempt = 0; attempt < 4; ++attempt) {
+  c->regrow = 0;
+  for (int attempt = 0; attempt < 6; ++attempt) {
     int rc = setup(c, nsys, off, boxes, pers, s);
     if (rc) return rc;
     Dev& D = c->D;
@@ -2205,155 +2363,282 @@ int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* box
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, energy, virial);
     if (n > 0) {
       int g = std::min(blocks(n, 256), 1024);
-      hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.stats + S_MAXLJ);
+      hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.lj_cap, D.stats + S_MAXLJ,
+                         D.stats + S_LJENT);
     }
     HIPCHK(hipGetLastError());
     int flags = 0;
     HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (flags & F_OV_LJ) {   // grow the LJ list and evaluate again
-      c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + 64, 1u << 16);
+    c->host_stats[S_REGROW] = c->regrow;
+    if (flags & (F_OV_LJ | F_OV_QUEUE)) {   // grow the LJ list or the queue and evaluate again
+      if (grow_caps(c, flags)) return fail(AIREBO_E_CAPACITY, "list or queue capacity limit reached");
       continue;
     }
     return check_flags(c, flags);
   }
-  return fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established");
+  return fail(AIREBO_E_CAPACITY, "list or queue capacity could not be established");
 }
 
-// Velocity Verlet over a batch; thermo [rows][nsys][6] (device).
-int nve_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, double* pos,
-             double* vel, const int32_t* species, const double* mass, double dt, int64_t nsteps, int64_t every,
-             double* thermo, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->opt.device));
-  int64_t n = off[nsys] - off[0];
-  if (n == 0) return 0;
-  // establish list capacity with a plain evaluation first
-  double* scratch = nullptr;
-  HIPCHK(hipMalloc((void**)&scratch, sizeof(double) * 10 * (size_t)nsys));
-  int rc = compute_impl(c, nsys, off, boxes, pers, pos, species, scratch, nullptr, scratch + 4 * (size_t)nsys, stream);
-  if (rc) { (void)hipFree(scratch); return rc; }
-  // headroom for list growth between rebuilds
-  c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32, 1u << 16);
-  rc = setup(c, nsys, off, boxes, pers, s);
-  if (rc) { (void)hipFree(scratch); return rc; }
+// ---------------------------------------------------------------------------
+// Molecular dynamics: velocity Verlet (Sec. 2) in a session held by the
+// context.  md_begin loads positions and velocities, sizes the lists with one
+// evaluation, computes the initial forces and captures one step into a HIP
+// graph; md_run replays it in chunks; md_state copies the state out.
+// Before each chunk the state (positions, velocities, statistics, step
+// counter) is copied aside on the device.  After the chunk every error flag
+// is read: a list or queue overflow restores the state, grows the capacity,
+// recomputes the forces of the restored state and captures the step again;
+// a non-finite step restores the state and returns the error.
+// ---------------------------------------------------------------------------
+constexpr int64_t MD_CHUNK = 256;
+constexpr int F_ERRORS = F_OV_SHORT | F_OV_INT | F_OV_LJ | F_OV_PATH | F_OV_BOND | F_OV_QUEUE | F_NONFINITE |
+                         F_BADSPEC | F_OV_NN;
+
+void md_release_graph(airebo_ctx* c) {
+  if (c->md.exec) (void)hipGraphExecDestroy(c->md.exec);
+  if (c->md.graph) (void)hipGraphDestroy(c->md.graph);
+  c->md.exec = nullptr;
+  c->md.graph = nullptr;
+}
+
+void md_end_impl(airebo_ctx* c) {
+  md_release_graph(c);
+  c->md.on = false;
+  c->md.forces = nullptr;
+  c->md.skip = nullptr;
+  c->D.skip = nullptr;
+}
+
+inline int thermo_block(int nsys) { return std::min(1024, std::max(64, ((nsys + 63) / 64) * 64)); }
+
+// One step: kick and drift, rebuild when flagged, forces, kick, thermo row.
+void md_step(airebo_ctx* c, hipStream_t s) {
+  Dev& D = c->D;
+  int64_t n = D.n;
+  auto& md = c->md;
+  double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
+  int kd_blocks = std::max(blocks(n, 256), blocks(NSLOT * A_N, 256));   // k_kick_drift also zeroes the sums
+  LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(kd_blocks), dim3(256), s, D, md.vel, md.m0, md.m1, md.dt, half_skin2);
+  launch_rebuild(c, s);
+  md.forces(s, false);
+  LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, md.vel, md.m0, md.m1, md.dt);
+  LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(thermo_block(D.nsys)), s, D, (const MdCtl*)md.ctl);
+}
+
+// Forces and kinetic energy of the positions in the context (after a load or
+// a restore), with the lists rebuilt; clears the flags.
+void md_prime(airebo_ctx* c, hipStream_t s) {
+  Dev& D = c->D;
+  hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
+  (void)hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, s);
+  launch_rebuild(c, s);
+  c->md.forces(s, true);
+  hipLaunchKernelGGL(k_kick, dim3(blocks(D.n, 256)), dim3(256), 0, s, D, c->md.vel, c->md.m0, c->md.m1, 0.0);
+}
+
+// Buffers of the session for the current capacities; the Dev descriptor
+// pointed at the context's force array.
+int md_setup(airebo_ctx* c, hipStream_t s) {
+  auto& md = c->md;
+  int rc = setup(c, md.nsys, md.off.data(), md.boxes.data(), md.pers.data(), s, true);
+  if (rc) return rc;
   Dev& D = c->D;
   D.F = c->F;
-  int nrows = every > 0 ? (int)(nsteps / every) + 1 : 0;
-  double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
-  int tb = std::min(1024, std::max(64, ((nsys + 63) / 64) * 64));
-  // k_kick_drift also zeroes the accumulators: cover NSLOT * A_N threads
-  int kd_blocks = std::max(blocks(n, 256), blocks(NSLOT * A_N, 256));
-  hipError_t err = hipSuccess;
-  auto body = [&](bool first) {
-    if (first) {
-      hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
-      (void)hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s);
-      (void)hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, s);
-      (void)hipMemsetAsync(c->step, 0, sizeof(int), s);
-      hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
-      launch_rebuild(c, s);
-      launch_forces(c, s);
-      // kinetic energy of the initial state (zero-length kick)
-      hipLaunchKernelGGL(k_kick, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], 0.0);
-      hipLaunchKernelGGL(k_thermo, dim3(1), dim3(tb), 0, s, D, thermo, (int)every, nrows);
-      return;
-    }
-    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(kd_blocks), dim3(256), s, D, vel, mass[0], mass[1], dt, half_skin2);
-    launch_rebuild(c, s);
-    launch_forces(c, s, false);
-    LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt);
-    LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(tb), s, D, thermo, (int)every, nrows);
-  };
-  body(true);
+  D.skip = md.skip;
+  size_t n = (size_t)std::max(D.n, 1);
+  rc |= grow(md.vel, md.c_vel, 3 * n);
+  rc |= grow(md.xsave, md.c_xs, n);
+  rc |= grow(md.vsave, md.c_vs, 3 * n);
+  rc |= grow(md.ssave, md.c_ss, S_N + 1);
+  if (!md.ctl) HIPCHK(hipMalloc(&md.ctl, sizeof(MdCtl)));
+  return rc ? AIREBO_E_DEVICE : 0;
+}
+
+hipError_t md_capture(airebo_ctx* c) {
+  auto& md = c->md;
+  md_release_graph(c);
+  if (!md.cs) {
+    hipError_t e = hipStreamCreateWithFlags(&md.cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipStreamBeginCapture(md.cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  md_step(c, md.cs);
+  e = hipStreamEndCapture(md.cs, &md.graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&md.exec, md.graph, nullptr, nullptr, 0);
+  return e;
+}
+
+int md_sync_flags(airebo_ctx* c, hipStream_t s, int& flags) {
+  flags = 0;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->host_stats[S_REGROW] = c->regrow;
+  return 0;
+}
+
+// Start a session.  `size` runs one evaluation that establishes the list
+// capacities; `forces` launches one force evaluation of the session.
+int md_begin_impl(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers,
+                  const double* pos, const double* vel, const int32_t* species, const double* mass, double dt,
+                  hipStream_t s, const std::function<int()>& size, std::function<void(hipStream_t, bool)> forces,
+                  const int* skip) {
+  HIPCHK(hipSetDevice(c->opt.device));
+  if (c->md.on) md_end_impl(c);
+  int64_t n = off[nsys] - off[0];
+  if (n < 1) return fail(AIREBO_E_ARG, "an MD session needs at least one atom");
+  int rc = size();
+  if (rc) return rc;
+  // room for list growth between rebuilds
+  unsigned long long mx = c->host_stats[S_MAXLJ];
+  unsigned long long slack = c->opt.lj_slack > 0 ? (unsigned long long)c->opt.lj_slack : mx / 4 + 32;
+  c->lj_cap = (int)std::min<unsigned long long>(std::max<unsigned long long>(mx + slack, 1), 1u << 16);
+  auto& md = c->md;
+  md.nsys = nsys;
+  md.off.assign(off, off + nsys + 1);
+  md.boxes.assign(boxes, boxes + 3 * (size_t)nsys);
+  md.pers.assign(pers, pers + 3 * (size_t)nsys);
+  md.m0 = mass[0];
+  md.m1 = mass[1];
+  md.dt = dt;
+  md.forces = std::move(forces);
+  md.skip = skip;
+  rc = md_setup(c, s);
+  if (rc) { md_end_impl(c); return rc; }
+  Dev& D = c->D;
+  HIPCHK(hipMemcpyAsync(md.vel, vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
+  md_prime(c, s);
+  int flags = 0;
+  rc = md_sync_flags(c, s, flags);
+  if (!rc && (flags & F_ERRORS)) rc = check_flags(c, flags);
+  if (!rc && !c->prof) {
+    hipError_t e = md_capture(c);
+    if (e != hipSuccess) rc = fail(AIREBO_E_DEVICE, std::string("md capture: ") + hipGetErrorString(e));
+  }
+  if (rc) { md_end_impl(c); return rc; }
+  md.on = true;
+  return 0;
+}
+
+// Advance the session by nsteps; thermo rows [nsteps / every + 1][nsys][7]
+// (device; row 0 is the state at the start of the run).
+int md_run_impl(airebo_ctx* c, int64_t nsteps, int64_t every, double* thermo, hipStream_t s) {
+  auto& md = c->md;
+  if (!md.on) return fail(AIREBO_E_ARG, "no MD session (airebo_md_begin)");
+  HIPCHK(hipSetDevice(c->opt.device));
+  Dev& D = c->D;
+  int64_t n = D.n;
+  MdCtl h{every > 0 ? thermo : nullptr, (int)std::max<int64_t>(every, 0),
+          every > 0 ? (int)(nsteps / every) + 1 : 0};
+  static_assert(sizeof(MdCtl) <= sizeof md.hctl, "control block image");
+  std::memcpy(md.hctl, &h, sizeof h);
+  HIPCHK(hipMemcpyAsync(md.ctl, md.hctl, sizeof(MdCtl), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(c->step, 0, sizeof(int), s));
+  // row 0: the current state (its sums are those of the last evaluation)
+  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(thermo_block(D.nsys)), 0, s, D, (const MdCtl*)md.ctl);
   if (c->prof) {   // per-kernel timing: eager launches, one event pair per kernel
     HIPCHK(hipStreamSynchronize(s));
     for (auto& e : c->ev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     c->ev.clear();
-    for (int64_t k = 0; k < nsteps; ++k) body(false);
-    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t k = 0; k < nsteps; ++k) md_step(c, s);
+    int flags = 0;
+    int rc = md_sync_flags(c, s, flags);
+    if (rc) return rc;
+    return (flags & F_ERRORS) ? check_flags(c, flags) : 0;
   }
-  // One step is captured into a graph and replayed in chunks.  Before each
-  // chunk the state (positions, velocities, step counter, statistics) is
-  // copied aside on the device; when a rebuild overflows the LJ list during
-  // the chunk, the state is restored, the list capacity grows by half, the
-  // step is captured again and the chunk is repeated.
-  constexpr int64_t CHUNK = 256;
-  if (c->prof) nsteps = 0;
-  double4* xsave = nullptr;
-  double* vsave = nullptr;
-  unsigned long long* ssave = nullptr;   // [S_N] statistics, then the step counter
-  if (nsteps > 0) {
-    err = hipMalloc((void**)&xsave, sizeof(double4) * n);
-    if (err == hipSuccess) err = hipMalloc((void**)&vsave, sizeof(double) * 3 * n);
-    if (err == hipSuccess) err = hipMalloc((void**)&ssave, sizeof(unsigned long long) * (S_N + 1));
-  }
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cs = nullptr;
-  auto capture = [&]() -> hipError_t {
-    if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
-    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    hipStream_t keep = s;
-    s = cs;
-    body(false);
-    s = keep;
-    e = hipStreamEndCapture(cs, &graph);
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    return e;
-  };
+  hipEvent_t ready = nullptr;   // the replays on the capture stream follow the caller's stream
+  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  (void)hipEventRecord(ready, s);
+  (void)hipStreamWaitEvent(md.cs, ready, 0);
+  (void)hipEventDestroy(ready);
+  hipStream_t cs = md.cs;
   int regrow = 0;
-  if (nsteps > 0 && err == hipSuccess) err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (nsteps > 0 && err == hipSuccess) err = hipStreamSynchronize(s);
-  if (nsteps > 0 && err == hipSuccess) err = capture();
-  for (int64_t done = 0; done < nsteps && err == hipSuccess;) {
-    int64_t k = std::min(CHUNK, nsteps - done);
-    err = hipMemcpyAsync(xsave, c->x, sizeof(double4) * n, hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess) err = hipMemcpyAsync(vsave, vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess)
-      err = hipMemcpyAsync(ssave, c->stats, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess) err = hipMemcpyAsync(ssave + S_N, c->step, sizeof(int), hipMemcpyDeviceToDevice, cs);
-    for (int64_t q = 0; q < k && err == hipSuccess; ++q) err = hipGraphLaunch(exec, cs);
-    int fl = 0;
-    if (err == hipSuccess) err = hipMemcpyAsync(&fl, c->flags, sizeof(int), hipMemcpyDeviceToHost, cs);
-    if (err == hipSuccess) err = hipStreamSynchronize(cs);
-    if (err != hipSuccess) break;
-    if (!(fl & F_OV_LJ)) { done += k; continue; }
-    if (++regrow > 6 || c->lj_cap >= (1 << 16)) break;   // reported below
-    c->lj_cap = std::min(c->lj_cap + c->lj_cap / 2 + 32, 1 << 16);
-    int rc2 = setup(c, nsys, off, boxes, pers, cs);
-    if (rc2) { err = hipErrorOutOfMemory; break; }
-    D.F = c->F;
-    err = hipMemcpyAsync(c->x, xsave, sizeof(double4) * n, hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess) err = hipMemcpyAsync(vel, vsave, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess)
-      err = hipMemcpyAsync(c->stats, ssave, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess) err = hipMemcpyAsync(c->step, ssave + S_N, sizeof(int), hipMemcpyDeviceToDevice, cs);
-    if (err == hipSuccess) hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, cs, D, F_REBUILD);
-    if (err == hipSuccess) err = hipStreamSynchronize(cs);
-    if (err == hipSuccess) err = capture();
+  for (int64_t done = 0; done < nsteps;) {
+    int64_t k = std::min(MD_CHUNK, nsteps - done);
+    HIPCHK(hipMemcpyAsync(md.xsave, c->x, sizeof(double4) * n, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(hipMemcpyAsync(md.vsave, md.vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(hipMemcpyAsync(md.ssave, c->stats, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(hipMemcpyAsync(md.ssave + S_N, c->step, sizeof(int), hipMemcpyDeviceToDevice, cs));
+    for (int64_t q = 0; q < k; ++q) HIPCHK(hipGraphLaunch(md.exec, cs));
+    int flags = 0;
+    int rc = md_sync_flags(c, cs, flags);
+    if (rc) return rc;
+    if (!(flags & F_ERRORS)) { done += k; continue; }
+    // restore the state at the start of the chunk and recompute its forces
+    HIPCHK(hipMemcpyAsync(c->x, md.xsave, sizeof(double4) * n, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(hipMemcpyAsync(md.vel, md.vsave, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(hipMemcpyAsync(c->stats, md.ssave, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs));
+    HIPCHK(hipMemcpyAsync(c->step, md.ssave + S_N, sizeof(int), hipMemcpyDeviceToDevice, cs));
+    bool capacity = (flags & (F_OV_LJ | F_OV_QUEUE)) && !(flags & (F_ERRORS & ~(F_OV_LJ | F_OV_QUEUE)));
+    if (capacity) {
+      if (++regrow > 8 || grow_caps(c, flags)) {
+        rc = fail(AIREBO_E_CAPACITY, "list or queue capacity limit reached during MD");
+      } else {
+        rc = md_setup(c, cs);
+      }
+    }
+    md_prime(c, cs);
+    int f2 = 0;
+    int rc2 = md_sync_flags(c, cs, f2);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (!capacity) return check_flags(c, flags);
+    if (f2 & F_ERRORS) return check_flags(c, f2);
+    hipError_t e = md_capture(c);
+    if (e != hipSuccess) return fail(AIREBO_E_DEVICE, std::string("md capture: ") + hipGetErrorString(e));
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  if (cs) (void)hipStreamDestroy(cs);
-  if (xsave) (void)hipFree(xsave);
-  if (vsave) (void)hipFree(vsave);
-  if (ssave) (void)hipFree(ssave);
-  if (err != hipSuccess) {
-    (void)hipFree(scratch);
-    return fail(AIREBO_E_DEVICE, std::string("nve: ") + hipGetErrorString(err));
+  return 0;
+}
+
+// Current positions (wrapped into periodic boxes) and velocities.
+int md_state_impl(airebo_ctx* c, double* pos, double* vel, hipStream_t s) {
+  auto& md = c->md;
+  if (!md.on) return fail(AIREBO_E_ARG, "no MD session (airebo_md_begin)");
+  HIPCHK(hipSetDevice(c->opt.device));
+  Dev& D = c->D;
+  if (pos) hipLaunchKernelGGL(k_store, dim3(blocks(D.n, 256)), dim3(256), 0, s, D, pos);
+  if (vel) HIPCHK(hipMemcpyAsync(vel, md.vel, sizeof(double) * 3 * D.n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Session of the AIREBO force field on a batch.
+int md_begin_airebo(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers,
+                    const double* pos, const double* vel, const int32_t* species, const double* mass, double dt,
+                    hipStream_t s) {
+  auto size = [&]() -> int {
+    size_t need = 10 * (size_t)nsys;
+    if (grow(c->md.scratch, c->md.c_scr, need)) return AIREBO_E_DEVICE;
+    return compute_impl(c, nsys, off, boxes, pers, pos, species, c->md.scratch, nullptr,
+                        c->md.scratch + 4 * (size_t)nsys, s);
+  };
+  return md_begin_impl(c, nsys, off, boxes, pers, pos, vel, species, mass, dt, s, size,
+                       [c](hipStream_t st, bool zero) { launch_forces(c, st, zero); }, nullptr);
+}
+
+// airebo_nve as one session: begin, run, state out, end.
+int nve_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, double* pos,
+             double* vel, const int32_t* species, const double* mass, double dt, int64_t nsteps, int64_t every,
+             double* thermo, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int64_t n = off[nsys] - off[0];
+  if (n == 0) return 0;
+  int rc = md_begin_airebo(c, nsys, off, boxes, pers, pos, vel, species, mass, dt, s);
+  if (!rc) rc = md_run_impl(c, nsteps, every, thermo, s);
+  // on an error the state is that of the last completed chunk
+  int rc2 = c->md.on ? md_state_impl(c, pos, vel, s) : 0;
+  if (c->md.on) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (!rc2 && e != hipSuccess) rc2 = fail(AIREBO_E_DEVICE, std::string("nve: ") + hipGetErrorString(e));
   }
-  hipLaunchKernelGGL(k_store, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos);
-  int flags = 0;
-  HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  (void)hipFree(scratch);
-  if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded during NVE");
-  return check_flags(c, flags);
+  md_end_impl(c);
+  return rc ? rc : rc2;
 }
 
 }  // namespace
@@ -2421,6 +2706,41 @@ int airebo_batch_nve(airebo_ctx_t c, int32_t nsys, const int64_t* sys_off, const
   if (nsteps < 0 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0)) return fail(AIREBO_E_ARG, "bad step count, dt or mass");
   if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
   return nve_impl(c, nsys, sys_off, boxes, periodic, pos, vel, species, mass, dt, nsteps, every, thermo, stream);
+}
+
+int airebo_md_begin(airebo_ctx_t c, int64_t n, const double* pos, const double* vel, const int32_t* species,
+                    const double* box, const int32_t* periodic, const double* mass, double dt, void* stream) {
+  if (!c || !pos || !vel || !species || !mass || !box || !periodic) return fail(AIREBO_E_ARG, "null argument");
+  if (n < 1 || n >= (1ll << 27) || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0))
+    return fail(AIREBO_E_ARG, "bad n, dt or mass");
+  int64_t off[2] = {0, n};
+  return md_begin_airebo(c, 1, off, box, periodic, pos, vel, species, mass, dt, (hipStream_t)stream);
+}
+
+int airebo_batch_md_begin(airebo_ctx_t c, int32_t nsys, const int64_t* sys_off, const double* boxes,
+                          const int32_t* periodic, const double* pos, const double* vel, const int32_t* species,
+                          const double* mass, double dt, void* stream) {
+  if (!c || nsys < 1 || !sys_off || !boxes || !periodic || !mass || !pos || !vel || !species)
+    return fail(AIREBO_E_ARG, "null argument");
+  if (sys_off[nsys] < 1 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0))
+    return fail(AIREBO_E_ARG, "bad atom count, dt or mass");
+  return md_begin_airebo(c, nsys, sys_off, boxes, periodic, pos, vel, species, mass, dt, (hipStream_t)stream);
+}
+
+int airebo_md_run(airebo_ctx_t c, int64_t nsteps, int64_t thermo_every, double* thermo, void* stream) {
+  if (!c) return fail(AIREBO_E_ARG, "null argument");
+  if (nsteps < 0 || thermo_every < 0) return fail(AIREBO_E_ARG, "bad step count");
+  if (thermo_every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+  return md_run_impl(c, nsteps, thermo_every, thermo, (hipStream_t)stream);
+}
+
+int airebo_md_state(airebo_ctx_t c, double* pos, double* vel, void* stream) {
+  if (!c) return fail(AIREBO_E_ARG, "null argument");
+  return md_state_impl(c, pos, vel, (hipStream_t)stream);
+}
+
+void airebo_md_end(airebo_ctx_t c) {
+  if (c) md_end_impl(c);
 }
 
 int airebo_profile_nve(airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species,

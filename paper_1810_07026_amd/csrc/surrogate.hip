@@ -1263,6 +1263,7 @@ template <typename Body>
 int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species, const double* box,
             const int32_t* periodic, hipStream_t s, Body body) {
   HIPCHK(hipSetDevice(c->opt.device));
+  c->regrow = 0;
   int64_t off[2] = {0, n};
   for (int attempt = 0; attempt < 4; ++attempt) {
     int rc = setup(c, 1, off, box, periodic, s);
@@ -1275,7 +1276,8 @@ int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species,
     hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
     launch_rebuild(c, s);
     int g = std::min(blocks(n, 256), 1024);
-    hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.stats + S_MAXLJ);
+    hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.lj_cap, D.stats + S_MAXLJ,
+                       D.stats + S_LJENT);
     rc = body(D);
     if (rc) return rc;
     HIPCHK(hipGetLastError());
@@ -1283,14 +1285,13 @@ int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species,
     HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (flags & F_OV_LJ) {
-      c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + 64, 1u << 16);
+    if (flags & (F_OV_LJ | F_OV_QUEUE)) {
+      if (grow_caps(c, flags)) return fail(AIREBO_E_CAPACITY, "list or queue capacity limit reached");
       continue;
     }
-    if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 192 neighbours within 6 A or 48 within 3.5 A");
     return check_flags(c, flags);
   }
-  return fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established");
+  return fail(AIREBO_E_CAPACITY, "list or queue capacity could not be established");
 }
 
 const char kMagic[8] = {'A', 'I', 'R', 'N', 'N', '0', '0', '1'};
@@ -1564,101 +1565,50 @@ int airebo_nn_train_step(airebo_nn_t m, airebo_ctx_t c, int64_t n, const double*
   return airebo_nn_adam(m, lr, 0.9, 0.999, 1e-8, stream);
 }
 
-int airebo_nn_nve(airebo_nn_t m, airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species,
-                  const double* box, const int32_t* periodic, const double* mass, double dt, int64_t nsteps,
-                  int64_t every, double* thermo, double threshold, int64_t* fallbacks, void* stream) {
+int airebo_nn_md_begin(airebo_nn_t m, airebo_ctx_t c, int64_t n, const double* pos, const double* vel,
+                       const int32_t* species, const double* box, const int32_t* periodic, const double* mass,
+                       double dt, double threshold, void* stream) {
   if (nn_check(m)) return AIREBO_E_ARG;
   if (!vel || !mass) return fail(AIREBO_E_ARG, "null argument");
   int rc = nn_args_ok(c, n, pos, species, box, periodic);
   if (rc) return rc;
-  if (nsteps < 0 || !(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0) || !(threshold > 0))
-    return fail(AIREBO_E_ARG, "bad step count, dt, mass or threshold");
-  if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+  if (!(dt > 0) || !(mass[0] > 0) || !(mass[1] > 0) || !(threshold > 0))
+    return fail(AIREBO_E_ARG, "bad dt, mass or threshold");
   if (c->opt.device != m->device) return fail(AIREBO_E_ARG, "context and surrogate on different devices");
   rc = nn_buffers(m, n, false);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(hipSetDevice(c->opt.device));
   float thr = (float)std::min(threshold, 1e30);
-  // list capacity from a plain surrogate evaluation
-  rc = nn_eval(c, n, pos, species, box, periodic, s, [&](Dev& D) -> int {
-    D.skip = m->skip;
-    nn_step(c, m, thr, s);
-    return 0;
-  });
-  c->D.skip = nullptr;
-  if (rc) return rc;
-  c->lj_cap = (int)std::min<unsigned long long>(c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32, 1u << 16);
-  int64_t off[2] = {0, n};
-  rc = setup(c, 1, off, box, periodic, s);
-  if (rc) return rc;
-  Dev& D = c->D;
-  D.F = c->F;
-  D.skip = m->skip;
-  int nrows = every > 0 ? (int)(nsteps / every) + 1 : 0;
-  double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
-  auto body = [&](bool first) {
-    if (first) {
-      hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
-      (void)hipMemsetAsync(c->stats, 0, S_N * sizeof(unsigned long long), s);
-      (void)hipMemsetAsync(c->cell_count, 0, sizeof(int) * c->ncell, s);
-      (void)hipMemsetAsync(c->step, 0, sizeof(int), s);
-      hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
-      launch_rebuild(c, s);
+  auto size = [&]() -> int {   // list capacity from a plain surrogate evaluation
+    int r = nn_eval(c, n, pos, species, box, periodic, s, [&](Dev& D) -> int {
+      D.skip = m->skip;
       nn_step(c, m, thr, s);
-      hipLaunchKernelGGL(k_kick, dim3(blocks(n, 256)), dim3(256), 0, s, D, vel, mass[0], mass[1], 0.0);
-      hipLaunchKernelGGL(k_thermo, dim3(1), dim3(64), 0, s, D, thermo, (int)every, nrows);
-      return;
-    }
-    LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(std::max(blocks(n, 256), blocks(NSLOT * A_N, 256))), dim3(256), s, D,
-           vel, mass[0], mass[1], dt, half_skin2);
-    launch_rebuild(c, s);
-    nn_step(c, m, thr, s);
-    LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, vel, mass[0], mass[1], dt);
-    LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(64), s, D, thermo, (int)every, nrows);
+      return 0;
+    });
+    c->D.skip = nullptr;
+    return r;
   };
-  hipError_t err = hipSuccess;
-  body(true);
-  if (c->prof) {
-    HIPCHK(hipStreamSynchronize(s));
-    for (auto& e : c->ev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
-    c->ev.clear();
-    for (int64_t k = 0; k < nsteps; ++k) body(false);
-    HIPCHK(hipStreamSynchronize(s));
-    nsteps = 0;
+  int64_t off[2] = {0, n};
+  return md_begin_impl(c, 1, off, box, periodic, pos, vel, species, mass, dt, s, size,
+                       [c, m, thr](hipStream_t st, bool) { nn_step(c, m, thr, st); }, m->skip);
+}
+
+int airebo_nn_nve(airebo_nn_t m, airebo_ctx_t c, int64_t n, double* pos, double* vel, const int32_t* species,
+                  const double* box, const int32_t* periodic, const double* mass, double dt, int64_t nsteps,
+                  int64_t every, double* thermo, double threshold, int64_t* fallbacks, void* stream) {
+  if (nsteps < 0) return fail(AIREBO_E_ARG, "bad step count");
+  if (every > 0 && !thermo) return fail(AIREBO_E_ARG, "thermo output needed when thermo_every > 0");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = airebo_nn_md_begin(m, c, n, pos, vel, species, box, periodic, mass, dt, threshold, stream);
+  if (!rc) rc = md_run_impl(c, nsteps, every, thermo, s);
+  int rc2 = c && c->md.on ? md_state_impl(c, pos, vel, s) : 0;
+  if (c && c->md.on) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (!rc2 && e != hipSuccess) rc2 = fail(AIREBO_E_DEVICE, std::string("surrogate nve: ") + hipGetErrorString(e));
   }
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t cs = nullptr;
-  if (nsteps > 0) {
-    err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
-    if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (err == hipSuccess) {
-      hipStream_t keep = s;
-      s = cs;
-      body(false);
-      s = keep;
-      err = hipStreamEndCapture(cs, &graph);
-    }
-    if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) err = hipGraphLaunch(exec, cs);
-    if (err == hipSuccess) err = hipStreamSynchronize(cs);
-  }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  if (cs) (void)hipStreamDestroy(cs);
-  c->D.skip = nullptr;
-  if (err != hipSuccess) return fail(AIREBO_E_DEVICE, std::string("surrogate nve: ") + hipGetErrorString(err));
-  hipLaunchKernelGGL(k_store, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos);
-  int flags = 0;
-  HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (fallbacks) *fallbacks = (int64_t)c->host_stats[S_FALLBACK];
-  if (flags & F_OV_LJ) return fail(AIREBO_E_CAPACITY, "LJ list capacity exceeded during NVE");
-  if (flags & F_OV_NN) return fail(AIREBO_E_CAPACITY, "more than 192 neighbours within 6 A or 48 within 3.5 A");
-  return check_flags(c, flags);
+  if (c) md_end_impl(c);
+  if (!rc && fallbacks) *fallbacks = (int64_t)c->host_stats[S_FALLBACK];
+  return rc ? rc : rc2;
 }
 
 int airebo_nn_profile_nve(airebo_nn_t m, airebo_ctx_t c, int64_t n, double* pos, double* vel,

@@ -54,7 +54,7 @@ def test_batch_nve_equals_single(ctx, small_batch):
     v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
     th = ctx.batch_nve(x, v, d["species"], d["sizes"], d["boxes"], d["periodic"], nsteps=10,
                        thermo_every=5).cpu().numpy()
-    assert th.shape == (3, len(d["sizes"]), 6)
+    assert th.shape == (3, len(d["sizes"]), 7)   # step, PE, KE, Etot, T, rebuilds, P
     for k, (a, b) in enumerate(split(d)):
         xs = torch.tensor(d["x"][a:b], dtype=torch.float64, device="cuda")
         vs = torch.tensor(d["v"][a:b], dtype=torch.float64, device="cuda")
