@@ -34,7 +34,7 @@ EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "ai
            "airebo_params_load", "airebo_params_parse", "airebo_params_free", "airebo_ctx_create_from_params",
            "airebo_compute_host", "airebo_nn_train_step",
            "airebo_md_begin", "airebo_batch_md_begin", "airebo_md_run", "airebo_md_state", "airebo_md_end",
-           "airebo_nn_md_begin"]
+           "airebo_nn_md_begin", "airebo_compute_static"]
 
 
 class AireboError(RuntimeError):
@@ -82,6 +82,9 @@ def load_library(path=LIB_PATH):
     L.airebo_compute_host.argtypes = [vp, ctypes.c_int64, hdp, ctypes.POINTER(ctypes.c_int32), hdp,
                                       ctypes.POINTER(ctypes.c_int32), hdp, hdp, hdp]
     L.airebo_compute_host.restype = ctypes.c_int
+    L.airebo_compute_static.argtypes = [vp, ctypes.c_int64, dp, ip, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32), dp, dp, dp, vp]
+    L.airebo_compute_static.restype = ctypes.c_int
     L.airebo_ctx_free.argtypes = [vp]
     L.airebo_ctx_free.restype = None
     L.airebo_compute.argtypes = [vp, ctypes.c_int64, dp, ip, ctypes.POINTER(ctypes.c_double),
@@ -276,6 +279,24 @@ class Context:
                                    _host3(box, ctypes.c_double), _host3(periodic, ctypes.c_int32),
                                    ctypes.c_void_p(e.data_ptr()), ctypes.c_void_p(f.data_ptr()),
                                    ctypes.c_void_p(w.data_ptr()), self._stream())
+        _check(self.L, rc)
+        return e, f, w
+
+    def compute_static(self, x, species, box, periodic=(1, 1, 1), energy=None, forces=None, virial=None):
+        """airebo_compute_static (no device allocation inside the library): energy [4], forces [n,3],
+        virial [6] as device tensors; pass preallocated outputs to allocate nothing here either."""
+        import torch
+        x = self._dev(x, torch.float64).reshape(-1, 3)
+        s = self._dev(species, torch.int32)
+        n = x.shape[0]
+        e = energy if energy is not None else torch.empty(4, dtype=torch.float64, device=self.device)
+        w = virial if virial is not None else torch.empty(6, dtype=torch.float64, device=self.device)
+        f = forces if forces is not None else torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        for t, shape in ((e, (4,)), (w, (6,)), (f, (n, 3))):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
+                raise AireboError(-1, f"output must be a contiguous float64 tensor of shape {shape} on {self.device}")
+        rc = self.L.airebo_compute_static(self.h, n, _p(x), _p(s), _host3(box, ctypes.c_double),
+                                          _host3(periodic, ctypes.c_int32), _p(e), _p(f), _p(w), self._stream())
         _check(self.L, rc)
         return e, f, w
 

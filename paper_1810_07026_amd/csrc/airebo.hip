@@ -43,6 +43,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1824,6 +1825,53 @@ __global__ void k_set_flags(Dev D, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *D.flags = v;
 }
 
+// ---------------------------------------------------------------------------
+// Work area of the allocation-free evaluation (airebo_compute_static): every
+// buffer of one evaluation of up to STATIC_MAX_ATOMS atoms, carved out of one
+// file-scope device array at fixed offsets.
+// ---------------------------------------------------------------------------
+constexpr int64_t STATIC_MAX_ATOMS = 8192;
+constexpr int64_t STATIC_LJ_ENTRIES = STATIC_MAX_ATOMS * 512;   // LJ list entries (512 per atom at the maximum)
+constexpr int64_t STATIC_MAX_CELLS = 32768;
+constexpr int64_t STATIC_QUEUE = 16 * STATIC_MAX_ATOMS + 1024 * NSEG;   // deferred-pair queue entries
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct StaticLayout {
+  size_t x, xref, xsort, cell_of, cell_count, cell_start, cell_cursor, cell_atoms, lj_n, lj_e, in_n, in_e, sn, sj,
+      sd, sw, NCt, NHt, bcount, bonds, qcount, q, F32, acc, stats, flags, step, sys, total;
+};
+constexpr StaticLayout static_layout() {
+  StaticLayout L{};
+  size_t o = 0;
+  const size_t N = STATIC_MAX_ATOMS, C = STATIC_MAX_CELLS;
+  const size_t bcap = N * SCAP / 2 + 64;
+  size_t* fields[] = {&L.x, &L.xref, &L.xsort, &L.cell_of, &L.cell_count, &L.cell_start, &L.cell_cursor,
+                      &L.cell_atoms, &L.lj_n, &L.lj_e, &L.in_n, &L.in_e, &L.sn, &L.sj, &L.sd, &L.sw, &L.NCt,
+                      &L.NHt, &L.bcount, &L.bonds, &L.qcount, &L.q, &L.F32, &L.acc, &L.stats, &L.flags, &L.step,
+                      &L.sys};
+  const size_t bytes[] = {32 * N, 32 * N, 16 * N, 4 * N, 4 * C, 4 * (C + 1), 4 * C, 4 * N, 4 * N,
+                          4 * (size_t)STATIC_LJ_ENTRIES, 4 * N, 4 * N * ICAP, 4 * N, 4 * N * SCAP, 32 * N * SCAP,
+                          16 * N * SCAP, 8 * N, 8 * N, 16, 8 * 3 * bcap, 4 * NSEG * QSTRIDE,
+                          16 * (size_t)STATIC_QUEUE, 12 * N, 8 * NSLOT * A_N, 8 * S_N, 16, 16, sizeof(SysBox)};
+  for (size_t k = 0; k < sizeof(bytes) / sizeof(bytes[0]); ++k) {
+    *fields[k] = o;
+    o += al256(bytes[k]);
+  }
+  L.total = o;
+  return L;
+}
+constexpr StaticLayout kStatic = static_layout();
+static_assert(kStatic.total < (size_t)32 << 20, "static work area stays under 32 MiB");
+
+// The work area itself.  Host code never uses this name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kStatic.total];
+
+// Store one system box in device memory (passed by value: no host copy).
+__global__ void k_put_box(SysBox* dst, SysBox b) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = b;
+}
+
 }  // namespace airebo
 
 // ---------------------------------------------------------------------------
@@ -1833,6 +1881,10 @@ using namespace airebo;
 
 namespace {
 thread_local std::string g_err;
+// device address of the static work area, per device ordinal (set at context creation)
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -2026,7 +2078,20 @@ int ctx_create_impl(const DevParams& P, const std::vector<double>& tri, const ai
     delete c;
     return fail(AIREBO_E_PARAMS, "the parameter set has no Morse records (morse_eps_/morse_re_/morse_alpha_ CC, CH, HH)");
   }
+  if (o.device < 0 || o.device >= kMaxDevices) {
+    delete c;
+    return fail(AIREBO_E_ARG, "device ordinal out of range");
+  }
   hipError_t e = hipSetDevice(o.device);
+  if (e == hipSuccess) {   // once per device, with that device current
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[o.device]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e == hipSuccess && !ptr) e = hipErrorInvalidSymbol;
+      if (e == hipSuccess) g_static_ptr[o.device] = ptr;
+    }
+  }
   if (e == hipSuccess) e = hipMalloc((void**)&c->dtri, tri.size() * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(c->dtri, tri.data(), tri.size() * sizeof(double), hipMemcpyHostToDevice);
   c->P.tri = c->dtri;
@@ -2122,26 +2187,21 @@ namespace {
 // descriptor and upload the per-system boxes.
 void md_end_impl(airebo_ctx* c);
 
-int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, hipStream_t s,
-          bool keep_md = false) {
-  // any other use of the context ends an MD session: its captured step holds the buffers set up here
-  if (c->md.on && !keep_md) md_end_impl(c);
+// Boxes and cell grids of a batch (atoms of system k are [off[k], off[k+1]));
+// box lengths and periodic flags [nsys][3].
+int plan_boxes(const airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers,
+               std::vector<SysBox>& hsys, size_t& ncell) {
   if (nsys < 1 || !off || !boxes || !pers) return fail(AIREBO_E_ARG, "null box, periodic or offsets");
   int64_t n = off[nsys] - off[0];
   if (off[0] != 0 || n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
   const DevParams& P = c->P;
   double rlist = P.rc_max + c->opt.skin;
-  Dev& D = c->D;
-  std::memset(&D, 0, sizeof D);
-  D.n = (int)n;
-  D.nsys = nsys;
-  D.skin = c->opt.skin;
-  c->hsys.resize(nsys);
-  c->hatom_sys.clear();
-  size_t ncell = 0;
+  double lmin = std::max(12.0, rlist);
+  hsys.resize(nsys);
+  ncell = 0;
   for (int k = 0; k < nsys; ++k) {
     if (off[k + 1] < off[k]) return fail(AIREBO_E_ARG, "system offsets must not decrease");
-    SysBox& B = c->hsys[k];
+    SysBox& B = hsys[k];
     std::memset(&B, 0, sizeof B);
     size_t nc_k = 1;
     for (int d = 0; d < 3; ++d) {
@@ -2150,7 +2210,7 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
       B.L[d] = L;
       B.invL[d] = 1.0 / L;
       B.per[d] = pers[3 * k + d] ? 1 : 0;
-      if (B.per[d] && L < std::max({12.0, P.rc_max + c->opt.skin}))
+      if (B.per[d] && L < lmin)
         return fail(AIREBO_E_BOX, "periodic box side must be at least max(12 A, LJ cutoff + skin)");
       B.nc[d] = std::min(std::max(1, (int)std::floor(L / (0.5 * rlist))), 1024);   // cells >= half the list cutoff
       nc_k *= B.nc[d];
@@ -2159,6 +2219,24 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
     B.natoms = (int)(off[k + 1] - off[k]);
     ncell += nc_k;
   }
+  return 0;
+}
+
+int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, hipStream_t s,
+          bool keep_md = false) {
+  // any other use of the context ends an MD session: its captured step holds the buffers set up here
+  if (c->md.on && !keep_md) md_end_impl(c);
+  size_t ncell = 0;
+  int prc = plan_boxes(c, nsys, off, boxes, pers, c->hsys, ncell);
+  if (prc) return prc;
+  int64_t n = off[nsys] - off[0];
+  const DevParams& P = c->P;
+  Dev& D = c->D;
+  std::memset(&D, 0, sizeof D);
+  D.n = (int)n;
+  D.nsys = nsys;
+  D.skin = c->opt.skin;
+  c->hatom_sys.clear();
   c->ncell = (int)ncell;
   for (int p = 0; p < 3; ++p) {
     D.rlist2[p] = (P.rc[p] + c->opt.skin) * (P.rc[p] + c->opt.skin);
@@ -2379,6 +2457,128 @@ int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* box
     return check_flags(c, flags);
   }
   return fail(AIREBO_E_CAPACITY, "list or queue capacity could not be established");
+}
+
+// One evaluation with every work buffer in the device's static work area
+// (no allocation).  The context lends its parameters, streams and events;
+// its own buffers and state are left as they were.
+int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
+                        const int32_t* periodic, double* energy, double* forces, double* virial, hipStream_t s) {
+  if (n > STATIC_MAX_ATOMS)
+    return fail(AIREBO_E_CAPACITY, "airebo_compute_static takes at most " + std::to_string(STATIC_MAX_ATOMS) +
+                                       " atoms (" + std::to_string(n) + " given)");
+  int dev = c->opt.device;
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    base = static_cast<unsigned char*>(g_static_ptr[dev]);
+  }
+  if (!base) return fail(AIREBO_E_DEVICE, "static work area of this device not initialised");
+  HIPCHK(hipSetDevice(dev));
+  if (c->md.on) md_end_impl(c);
+  int64_t off[2] = {0, n};
+  std::vector<SysBox> hsys;
+  size_t ncell = 0;
+  int rc = plan_boxes(c, 1, off, box, periodic, hsys, ncell);
+  if (rc) return rc;
+  if (ncell > (size_t)STATIC_MAX_CELLS)
+    return fail(AIREBO_E_CAPACITY, "cell grid of " + std::to_string(ncell) + " cells exceeds the static limit of " +
+                                       std::to_string(STATIC_MAX_CELLS));
+  const DevParams& P = c->P;
+  Dev saved = c->D;
+  int saved_ncell = c->ncell;
+  Dev& D = c->D;
+  std::memset(&D, 0, sizeof D);
+  const StaticLayout& L = kStatic;
+  D.n = (int)n;
+  D.nsys = 1;
+  D.skin = c->opt.skin;
+  for (int p = 0; p < 3; ++p) {
+    D.rlist2[p] = (P.rc[p] + c->opt.skin) * (P.rc[p] + c->opt.skin);
+    D.rint2[p] = (P.R2[p] + c->opt.skin) * (P.R2[p] + c->opt.skin);
+  }
+  D.sys = reinterpret_cast<SysBox*>(base + L.sys);
+  D.x = reinterpret_cast<double4*>(base + L.x);
+  D.xref = reinterpret_cast<double4*>(base + L.xref);
+  D.xsort = reinterpret_cast<float4*>(base + L.xsort);
+  D.cell_of = reinterpret_cast<int*>(base + L.cell_of);
+  D.cell_count = reinterpret_cast<int*>(base + L.cell_count);
+  D.cell_start = reinterpret_cast<int*>(base + L.cell_start);
+  D.cell_cursor = reinterpret_cast<int*>(base + L.cell_cursor);
+  D.cell_atoms = reinterpret_cast<int*>(base + L.cell_atoms);
+  D.lj_n = reinterpret_cast<int*>(base + L.lj_n);
+  D.lj_e = reinterpret_cast<unsigned*>(base + L.lj_e);
+  D.in_n = reinterpret_cast<int*>(base + L.in_n);
+  D.in_e = reinterpret_cast<int*>(base + L.in_e);
+  D.sn = reinterpret_cast<int*>(base + L.sn);
+  D.sj = reinterpret_cast<int*>(base + L.sj);
+  D.sd = reinterpret_cast<double4*>(base + L.sd);
+  D.sw = reinterpret_cast<double2*>(base + L.sw);
+  D.NCt = reinterpret_cast<double*>(base + L.NCt);
+  D.NHt = reinterpret_cast<double*>(base + L.NHt);
+  D.bcount = reinterpret_cast<int*>(base + L.bcount);
+  D.bonds = reinterpret_cast<int2*>(base + L.bonds);
+  D.bcap = (int)(std::max<int64_t>(n, 1) * SCAP / 2 + 64);
+  D.qcount = reinterpret_cast<int*>(base + L.qcount);
+  D.q = reinterpret_cast<int4*>(base + L.q);
+  D.qcap = (int)(STATIC_QUEUE / NSEG);
+  D.F = forces;
+  D.F32 = c->opt.precision == AIREBO_SINGLE ? reinterpret_cast<float*>(base + L.F32) : nullptr;
+  D.acc = reinterpret_cast<double*>(base + L.acc);
+  D.stats = reinterpret_cast<unsigned long long*>(base + L.stats);
+  D.flags = reinterpret_cast<int*>(base + L.flags);
+  D.step = reinterpret_cast<int*>(base + L.step);
+  c->ncell = (int)ncell;
+  const int64_t nn = std::max<int64_t>(n, 1);
+  D.lj_cap = (int)std::min<int64_t>(256, STATIC_LJ_ENTRIES / nn);
+  auto done = [&](int code) {
+    c->D = saved;
+    c->ncell = saved_ncell;
+    return code;
+  };
+  hipLaunchKernelGGL(k_put_box, dim3(1), dim3(64), 0, s, reinterpret_cast<SysBox*>(base + L.sys), hsys[0]);
+  // the FP32 force sums of single precision start at zero (the array keeps
+  // whatever the last call on this device left)
+  if (D.F32 && n > 0) {
+    hipError_t e = hipMemsetAsync(D.F32, 0, sizeof(float) * 3 * n, s);
+    if (e != hipSuccess) return done(fail(AIREBO_E_DEVICE, std::string("clearing FP32 sums: ") + hipGetErrorString(e)));
+  }
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    hipError_t e = hipMemsetAsync(D.stats, 0, S_N * sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.cell_count, 0, sizeof(int) * ncell, s);
+    if (e != hipSuccess) return done(fail(AIREBO_E_DEVICE, std::string("static clear: ") + hipGetErrorString(e)));
+    hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
+    if (n > 0) {
+      hipLaunchKernelGGL(k_load, dim3(blocks(n, 256)), dim3(256), 0, s, D, pos, species, 0);
+      launch_rebuild(c, s);
+      launch_forces(c, s);
+    } else {
+      hipLaunchKernelGGL(k_zero, dim3(NSLOT * A_N / 256), dim3(256), 0, s, D);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, energy, virial);
+    if (n > 0)
+      hipLaunchKernelGGL(k_max, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, (const int*)D.lj_n, (int)n,
+                         D.lj_cap, D.stats + S_MAXLJ, D.stats + S_LJENT);
+    int flags = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&flags, D.flags, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->host_stats, D.stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(fail(AIREBO_E_DEVICE, std::string("static evaluation: ") + hipGetErrorString(e)));
+    c->host_stats[S_REGROW] = (unsigned long long)attempt;
+    if (flags & F_OV_LJ) {   // a longer LJ row, if the area holds it
+      int64_t need = (int64_t)c->host_stats[S_MAXLJ] + 32;
+      if (need * nn > STATIC_LJ_ENTRIES)
+        return done(fail(AIREBO_E_CAPACITY, "LJ list of " + std::to_string(need) +
+                                                " entries per atom exceeds the static work area"));
+      D.lj_cap = (int)need;
+      continue;
+    }
+    if (flags & F_OV_QUEUE) return done(fail(AIREBO_E_CAPACITY, "deferred-pair queue exceeds the static work area"));
+    return done(check_flags(c, flags));
+  }
+  return done(fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established in the static work area"));
 }
 
 // ---------------------------------------------------------------------------
@@ -2652,6 +2852,14 @@ int airebo_compute(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* 
   if (n < 0) return fail(AIREBO_E_ARG, "n must be >= 0");
   int64_t off[2] = {0, n};
   return compute_impl(c, 1, off, box, periodic, pos, species, energy, forces, virial, stream);
+}
+
+int airebo_compute_static(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
+                          const int32_t* periodic, double* energy, double* forces, double* virial, void* stream) {
+  if (!c || (n > 0 && (!pos || !species || !forces)) || !energy || !virial || !box || !periodic)
+    return fail(AIREBO_E_ARG, "null argument");
+  if (n < 0) return fail(AIREBO_E_ARG, "n must be >= 0");
+  return compute_static_impl(c, n, pos, species, box, periodic, energy, forces, virial, (hipStream_t)stream);
 }
 
 int airebo_compute_host(airebo_ctx_t c, int64_t n, const double* pos, const int32_t* species, const double* box,
