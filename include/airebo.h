@@ -45,7 +45,7 @@ enum {
   AIREBO_E_ARG = -1,       /* null pointer, n < 0, bad option value            */
   AIREBO_E_PARAMS = -2,    /* parameter file missing, malformed or inconsistent */
   AIREBO_E_SPECIES = -3,   /* a species code other than 0 or 1                 */
-  AIREBO_E_BOX = -4,       /* a periodic side below max(12 A, LJ cutoff)       */
+  AIREBO_E_BOX = -4,       /* a periodic side below max(6 max R2, LJ cutoff + skin) */
   AIREBO_E_NONFINITE = -5, /* a non-finite position or result                  */
   AIREBO_E_CAPACITY = -6,  /* a neighbour or work capacity limit was exceeded  */
   AIREBO_E_DEVICE = -7     /* a HIP runtime error (message carries the code)   */
@@ -132,7 +132,10 @@ int airebo_ctx_create_from_params(airebo_params_t params, const airebo_options* 
  *   pos      device [n][3] positions in A; any values (wrapped internally)
  *   species  device [n] int32, 0 = C, 1 = H
  *   box      host [3] orthorhombic box lengths in A (origin 0)
- *   periodic host [3] int32 flags; a periodic side must be >= max(12 A, LJ cutoff)
+ *   periodic host [3] int32 flags; a periodic side must be >= max(6 max R2, LJ cutoff
+ *            + skin), i.e. 12 A and 11.2 A with the shipped parameters and skin: two
+ *            reaches of a three-bond C_ij path, so that one image of an atom only
+ *            is reachable over such a path (Sec. 2.1.2)
  *   energy   device [4] out: total, REBO, LJ, torsion (eV)
  *   forces   device [n][3] out: eV/A, in input order
  *   virial   device [6] out: xx yy zz xy xz yz of sum_a x_a (x) F_a (eV);
@@ -198,7 +201,7 @@ int airebo_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, const int3
  *   sys_off  host [nsys + 1] int64, atoms of system k are [sys_off[k], sys_off[k+1]),
  *            sys_off[0] = 0
  *   boxes    host [nsys][3] box lengths; periodic host [nsys][3] flags (each
- *            periodic side >= max(12 A, LJ cutoff + skin))
+ *            periodic side >= max(6 max R2, LJ cutoff + skin))
  *   pos, species, forces as for airebo_compute over all sys_off[nsys] atoms
  *   energy   device [nsys][4] (total, REBO, LJ, torsion); virial device [nsys][6]
  * Each system's results equal those of airebo_compute on that system alone

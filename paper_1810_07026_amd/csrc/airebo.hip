@@ -2188,7 +2188,9 @@ namespace {
 void md_end_impl(airebo_ctx* c);
 
 // Boxes and cell grids of a batch (atoms of system k are [off[k], off[k+1]));
-// box lengths and periodic flags [nsys][3].
+// box lengths and periodic flags [nsys][3].  A periodic side must hold the
+// LJ list cutoff and twice the reach of a three-bond path (so that a path
+// map keyed by atom index meets one image of each atom only).
 int plan_boxes(const airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers,
                std::vector<SysBox>& hsys, size_t& ncell) {
   if (nsys < 1 || !off || !boxes || !pers) return fail(AIREBO_E_ARG, "null box, periodic or offsets");
@@ -2196,7 +2198,7 @@ int plan_boxes(const airebo_ctx* c, int nsys, const int64_t* off, const double* 
   if (off[0] != 0 || n < 0 || n >= (1ll << 27)) return fail(AIREBO_E_ARG, "n out of range");
   const DevParams& P = c->P;
   double rlist = P.rc_max + c->opt.skin;
-  double lmin = std::max(12.0, rlist);
+  double lmin = std::max(2.0 * P.r_conn, rlist);
   hsys.resize(nsys);
   ncell = 0;
   for (int k = 0; k < nsys; ++k) {
@@ -2211,7 +2213,8 @@ int plan_boxes(const airebo_ctx* c, int nsys, const int64_t* off, const double* 
       B.invL[d] = 1.0 / L;
       B.per[d] = pers[3 * k + d] ? 1 : 0;
       if (B.per[d] && L < lmin)
-        return fail(AIREBO_E_BOX, "periodic box side must be at least max(12 A, LJ cutoff + skin)");
+        return fail(AIREBO_E_BOX, "periodic box side must be at least max(6 max R2, LJ cutoff + skin) = " +
+                                      std::to_string(lmin) + " A");
       B.nc[d] = std::min(std::max(1, (int)std::floor(L / (0.5 * rlist))), 1024);   // cells >= half the list cutoff
       nc_k *= B.nc[d];
     }
