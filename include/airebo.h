@@ -26,10 +26,17 @@
  *   - The caller owns every array it passes; the library never frees or
  *     keeps a caller pointer beyond the call.  A context owns its parameter
  *     copy and all scratch memory.  A context is not thread safe.
- *   - Capacities (LJ list entries per atom, deferred-pair queue) grow on
- *     demand: an evaluation or MD chunk that overflows one is repeated with
- *     the capacity grown.  AIREBO_E_CAPACITY is returned only when a growth
- *     limit is reached or a fixed per-atom limit is exceeded.
+ *   - Per-atom overflow is handled inside the library and counted
+ *     (airebo_stats), not returned (the paper keeps a correct slow path for
+ *     every case its fast kernels do not cover, Sec. 3.2 and Sec. 4.3):
+ *       * list capacities (short REBO list: 8 entries per atom, growing to
+ *         32; intermediate list: 48, growing to 768; LJ list; deferred-pair
+ *         queue) grow on demand: an evaluation or MD chunk that overflows one
+ *         is repeated with the capacity grown;
+ *       * an atom whose C_ij path map (64 atoms reachable over <= 3 bonds,
+ *         kept in LDS) overflows has its pairs within 3 max R2 resolved by a
+ *         sequential path search in the deferred-pair kernel.
+ *     AIREBO_E_CAPACITY is returned only when a growth limit is reached.
  */
 #ifndef AIREBO_H
 #define AIREBO_H
@@ -252,14 +259,19 @@ void airebo_md_end(airebo_ctx_t ctx);
 
 /* Counters of the last airebo_compute / airebo_nve call (host [16] int64):
  *   0 LJ pairs inside the cutoff (each pair once)   1 pairs with C_ij = 0
- *   2 pairs queued for the modified bond order b*   3 b* pairs with dS_b != 0
+ *   2 pairs that need the modified bond order b* (inside the S_r range)
+ *   3 b* pairs with dS_b != 0
  *   4 bonds                                          5 neighbour-list rebuilds
  *   6 max short neighbours of one atom               7 LJ list entries (airebo_compute)
  *   8 max LJ entries of one atom                     9 spline evaluations
  *  10 of those evaluated in FP64 near a knot (AIREBO_MIXED)
  *  11 surrogate steps that fell back to AIREBO (airebo_nn_*)
- *  12 capacity growths (LJ list or queue) of the last call or MD session
- *  13-15 reserved
+ *  12 capacity growths (short, intermediate or LJ list, queue) of the last
+ *     call or MD session
+ *  13 pairs handed to the sequential C_ij search because an atom's path map
+ *     (64 candidates) overflowed (summed over the steps of an MD session)
+ *  14 pairs evaluated by the deferred-pair kernel (0 < C_ij < 1 or inside
+ *     the S_r range)                                15 reserved
  * Slots 0-4 and 9-10 refer to the last force evaluation (every step in NVE). */
 int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
 

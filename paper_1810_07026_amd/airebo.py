@@ -21,7 +21,7 @@ TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
 THERMO_COLUMNS = ("step", "PE", "KE", "Etot", "T", "rebuilds", "P_bar")
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
               "lj_entries", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks",
-              "regrowths"]
+              "regrowths", "slow_path_pairs", "deferred_pairs"]
 
 EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "airebo_compute", "airebo_nve",
            "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name",

@@ -52,9 +52,15 @@
 
 namespace airebo {
 
-constexpr int SCAP = 8;    // short (REBO) neighbours per atom
-constexpr int ICAP = 48;   // intermediate-list entries per atom
-constexpr int PCAP = 64;   // path-map candidates per atom (LDS, per wavefront)
+// Per-atom capacities.  The short and intermediate lists start at SCAP and
+// ICAP entries per atom and grow (the evaluation or MD chunk is repeated)
+// when an atom has more, up to SCAP_MAX and ICAP_MAX; their strides are
+// Dev::scap and Dev::icap.
+constexpr int SCAP = 8;          // short (REBO) neighbours per atom, initial
+constexpr int SCAP_MAX = 32;     // path codes keep 5 bits per bond slot
+constexpr int ICAP = 48;         // intermediate-list entries per atom, initial
+constexpr int ICAP_MAX = 768;
+constexpr int PCAP = 64;   // path-map candidates per atom (LDS, per wavefront); beyond: sequential C_ij search
 constexpr int HCAP = 128;  // slots of the per-wavefront candidate lookup (2 x PCAP)
 static_assert(PCAP == 64, "one path candidate per lane when the lookup is filled");
 __device__ __forceinline__ int hslot(int a) { return (int)(((unsigned)a * 2654435761u) >> 25); }   // 7 bits
@@ -67,7 +73,7 @@ enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16,
 // accumulator quantities; each lives in NSLOT copies (one per group of blocks,
 // one cache line apart) that k_finish / k_thermo add up
 enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_SPL = 13,
-       A_SPL64 = 14, A_N = 16 };
+       A_SPL64 = 14, A_NSKIP = 15, A_NBSTAR = 16, A_N = 24 };
 // mixed precision: a spline argument within this distance of a knot is evaluated in FP64
 // (single precision takes no such branch)
 constexpr double KNOT_DELTA = 1e-3;
@@ -84,7 +90,7 @@ const char* const kKernelNames[K_COUNT] = {
     "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_LJENT = 7,
-       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_N = 16 };
+       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_SLOW = 13, S_QUEUED = 14, S_N = 16 };
 
 // One system of a batch: its own periodic box and cell grid.  A single
 // configuration is a batch of one.
@@ -114,8 +120,10 @@ struct Dev {
   int lj_cap;
   int* lj_n;
   unsigned* lj_e;    // j | shift code << 27
+  int icap;          // intermediate-list stride
   int* in_n;
   int* in_e;
+  int scap, slog2;   // short-list stride (a power of two) and its log2
   int* sn;
   int* sj;
   double4* sd;       // displacement to neighbour and its length
@@ -459,7 +467,7 @@ __device__ __forceinline__ int wave_max(int v) {
 
 template <typename R>
 __device__ __forceinline__ V3<R> nbr_vec(const Dev& D, int a, int q, R& r) {
-  double4 d = D.sd[a * SCAP + q];
+  double4 d = D.sd[a * D.scap + q];
   r = (R)d.w;
   return {(R)d.x, (R)d.y, (R)d.z};
 }
@@ -480,20 +488,20 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
   int n = D.sn[c];
   R NC = 0, NH = 0;
   for (int q = 0; q < n; ++q) {
-    int k = D.sj[c * SCAP + q];
+    int k = D.sj[c * D.scap + q];
     if (k == o) continue;
-    R w = (R)D.sw[c * SCAP + q].x;
+    R w = (R)D.sw[c * D.scap + q].x;
     if (__double2int_rn(D.x[k].w) == 0) NC += w; else NH += w;
   }
   R N = NC + NH;
   R S = 0, conj = 0, SdN = 0;
   for (int q = 0; q < n; ++q) {
-    int k = D.sj[c * SCAP + q];
+    int k = D.sj[c * D.scap + q];
     if (k == o) continue;
     int sk = __double2int_rn(D.x[k].w);
     R r;
     V3<R> d = nbr_vec<R>(D, c, q, r);
-    R w = (R)D.sw[c * SCAP + q].x;
+    R w = (R)D.sw[c * D.scap + q].x;
     R cth = dot(rco, d) / (rlen * r);
     R dgc, dgN;
     R g = gfun(P, sc, cth, N, dgc, dgN, st);
@@ -526,12 +534,12 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
   R GNC = GS * e.dPC + GNt, GNH = GS * e.dPH + GNt;
   R Grlen = 0;
   for (int q = 0; q < n; ++q) {
-    int k = D.sj[c * SCAP + q];
+    int k = D.sj[c * D.scap + q];
     if (k == o) continue;
     int sk = __double2int_rn(D.x[k].w);
     R r;
     V3<R> d = nbr_vec<R>(D, c, q, r);
-    double2 wd = D.sw[c * SCAP + q];
+    double2 wd = D.sw[c * D.scap + q];
     R w = (R)wd.x, dw = (R)wd.y;
     R inv = (R)1 / (rlen * r);
     R cth = dot(rco, d) * inv;
@@ -556,11 +564,11 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
       if (Gx != (R)0) {
         int nk = D.sn[k];
         for (int u = 0; u < nk; ++u) {
-          int m = D.sj[k * SCAP + u];
+          int m = D.sj[k * D.scap + u];
           if (m == c) continue;
           R rm;
           V3<R> dm = nbr_vec<R>(D, k, u, rm);
-          R dwm = (R)D.sw[k * SCAP + u].y;
+          R dwm = (R)D.sw[k * D.scap + u].y;
           if (dwm != (R)0) acc.vec(k, m, dm, (Gx * dwm / rm) * dm);
         }
       }
@@ -583,11 +591,11 @@ __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> r
   int ni = D.sn[i], nj = D.sn[j];
   V3<R> rji = -rij;
   for (int q = 0; q < ni; ++q) {
-    int k = D.sj[i * SCAP + q];
+    int k = D.sj[i * D.scap + q];
     if (k == j) continue;
     R rik_l;
     V3<R> rik = nbr_vec<R>(D, i, q, rik_l);
-    double2 wdk = D.sw[i * SCAP + q];
+    double2 wdk = D.sw[i * D.scap + q];
     R wik = (R)wdk.x, dwik = (R)wdk.y;
     R ci = dot(rij, rik) / (r * rik_l);
     R dgi;
@@ -598,11 +606,11 @@ __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> r
     int sk = __double2int_rn(D.x[k].w);
     V3<R> gik_sum = {0, 0, 0};   // dE/dr_ik summed over l (one force update per k)
     for (int u = 0; u < nj; ++u) {
-      int l = D.sj[j * SCAP + u];
+      int l = D.sj[j * D.scap + u];
       if (l == i || l == k) continue;
       R rjl_l;
       V3<R> rjl = nbr_vec<R>(D, j, u, rjl_l);
-      double2 wdl = D.sw[j * SCAP + u];
+      double2 wdl = D.sw[j * D.scap + u];
       R wjl = (R)wdl.x, dwjl = (R)wdl.y;
       R cj = dot(rji, rjl) / (r * rjl_l);
       R dgj;
@@ -922,15 +930,15 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
     m = __ballot(ok_in);
     if (ok_in) {
       int pos = nin + __popcll(m & below);
-      if (pos < ICAP) D.in_e[i * ICAP + pos] = j;
+      if (pos < D.icap) D.in_e[(size_t)i * D.icap + pos] = j;
     }
     nin += __popcll(m);
   }
   if (lane == 0) {
     D.lj_n[i] = nlj;            // unclamped; readers clamp to lj_cap
-    D.in_n[i] = min(nin, ICAP);
+    D.in_n[i] = min(nin, D.icap);
     if (nlj > D.lj_cap) atomicOr(D.flags, F_OV_LJ);
-    if (nin > ICAP) atomicOr(D.flags, F_OV_INT);
+    if (nin > D.icap) atomicOr(D.flags, F_OV_INT);
   }
 }
 
@@ -987,11 +995,16 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   // SG lanes per atom: lane `sub` of the group takes intermediate entries
   // sub, sub + SG, ...; the valid ones are compacted in entry order
   constexpr int SG = 16;
-  static_assert(ICAP % SG == 0 && WAVE % SG == 0, "short-list groups");
+  static_assert(WAVE % SG == 0 && SCAP_MAX % SG == 0, "short-list groups");
+  // pair class of each short neighbour j > i of the block's atoms (-1: j < i),
+  // read back by slot for the bond list
+  __shared__ signed char s_cls[1024 / SG][SCAP_MAX];
   int lane = threadIdx.x & (WAVE - 1);
   int sub = lane & (SG - 1);
+  int la = threadIdx.x / SG;
   unsigned long long gmask = ((1ull << SG) - 1) << (lane & ~(SG - 1));
   unsigned long long below = lanes_below();
+  const int scap = D.scap, icap = D.icap;
   int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / SG);
   bool live = i < D.n;
   double4 xi = make_double4(0, 0, 0, 0);
@@ -1005,18 +1018,13 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   int mmax = wave_max(m);
   int cnt = 0;                // valid entries of atom i so far (uniform in the group)
   T NC = 0, NH = 0;           // partial sums of this lane
-  int bpos[ICAP / SG], bcls[ICAP / SG];   // this lane's bonds j > i: slot and class (-1: none)
-#pragma unroll
-  for (int k = 0; k < ICAP / SG; ++k) {
-    bpos[k] = -1;
-    bcls[k] = 0;
-    if (k * SG >= mmax) continue;   // wave-uniform
+  for (int k = 0; k * SG < mmax; ++k) {   // wave-uniform trip count
     int e = k * SG + sub;
     bool ok = false;
     int j = 0, p = 0;
     double dx = 0, dy = 0, dz = 0, r = 0, w = 0, dw = 0;
     if (live && e < m) {
-      j = D.in_e[i * ICAP + e];
+      j = D.in_e[(size_t)i * icap + e];
       double4 xj = D.x[j];
       T tx = (T)xj.x - (T)xi.x, ty = (T)xj.y - (T)xi.y, tz = (T)xj.z - (T)xi.z;
       minimg(B, tx, ty, tz);
@@ -1034,11 +1042,11 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
     unsigned long long bal = __ballot(ok) & gmask;
     if (ok) {
       int pos = cnt + __popcll(bal & below);
-      if (pos < SCAP) {
-        D.sj[i * SCAP + pos] = j;
-        D.sd[i * SCAP + pos] = make_double4(dx, dy, dz, r);
-        D.sw[i * SCAP + pos] = make_double2(w, dw);
-        if (j > i) { bpos[k] = pos; bcls[k] = p; }
+      if (pos < scap) {
+        D.sj[i * scap + pos] = j;
+        D.sd[i * scap + pos] = make_double4(dx, dy, dz, r);
+        D.sw[i * scap + pos] = make_double2(w, dw);
+        s_cls[la][pos] = (signed char)(j > i ? p : -1);
       }
     }
     cnt += __popcll(bal);
@@ -1048,8 +1056,8 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
     NH += __shfl_xor(NH, o);
   }
   if (live && sub == 0) {
-    if (cnt > SCAP) atomicOr(D.flags, F_OV_SHORT);
-    D.sn[i] = min(cnt, SCAP);
+    if (cnt > scap) atomicOr(D.flags, F_OV_SHORT);
+    D.sn[i] = min(cnt, scap);
     D.NCt[i] = (double)NC;
     D.NHt[i] = (double)NH;
   }
@@ -1061,10 +1069,12 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
+  const int nslot = live ? min(cnt, scap) : 0;   // slots sub, sub + SG of this atom are this lane's
   int nb[3] = {0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < ICAP / SG; ++k)
-    if (bpos[k] >= 0) nb[bcls[k]]++;
+  for (int t = sub; t < nslot; t += SG) {
+    int q = s_cls[la][t];
+    if (q >= 0) nb[q]++;
+  }
   int base[3];
   for (int q = 0; q < 3; ++q) {
     int incl = nb[q];
@@ -1084,12 +1094,11 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   if (threadIdx.x == 0 && s_max > 0) atomicMax(&D.stats[S_MAXSHORT], (unsigned long long)s_max);
   __syncthreads();
   for (int q = 0; q < 3; ++q) base[q] += s_base[q];
-#pragma unroll
-  for (int k = 0; k < ICAP / SG; ++k) {
-    if (bpos[k] < 0) continue;
-    int q = bcls[k];
+  for (int t = sub; t < nslot; t += SG) {
+    int q = s_cls[la][t];
+    if (q < 0) continue;
     int b = base[q]++;
-    if (b < D.bcap) D.bonds[q * D.bcap + b] = make_int2(i, bpos[k]);
+    if (b < D.bcap) D.bonds[q * D.bcap + b] = make_int2(i, t);
     else atomicOr(D.flags, F_OV_BOND);
   }
 }
@@ -1102,12 +1111,64 @@ __device__ __forceinline__ PathInfo decode_path(const Dev& D, int i, int code) {
   pi.at[0] = i;
   int a = i;
   for (int b = 0; b < pi.len; ++b) {
-    int s = (code >> (2 + 3 * b)) & 7;
+    int s = (code >> (2 + 5 * b)) & 31;
     pi.slot[b] = s;
-    a = D.sj[a * SCAP + s];
+    a = D.sj[a * D.scap + s];
     pi.at[b + 1] = a;
   }
   return pi;
+}
+
+// Path code of a path i -> k (slot q1 of i), -> m (slot q2 of k), -> t (slot
+// q3 of m): the length in the low two bits, then 5 bits per slot.
+__device__ __forceinline__ int path_code(int len, int q1, int q2 = 0, int q3 = 0) {
+  return len | (q1 << 2) | (q2 << 7) | (q3 << 12);
+}
+
+// Largest weight product over the paths of at most three short bonds from i
+// to j that repeat no atom, and the code of the first path attaining it in
+// the order direct, one intermediate, two intermediates (slot order within
+// each).  This is the sequential C_ij search of the paper (Sec. 4.3) for
+// atoms whose path map does not fit in LDS; it visits the same paths as the
+// map with the same multiplication order.
+__device__ void path_search(const Dev& D, int i, int j, double& best, int& bcode) {
+  const int S = D.scap;
+  best = 0.0;
+  bcode = 0;
+  int ni = D.sn[i];
+  for (int q1 = 0; q1 < ni; ++q1) {
+    double w1 = D.sw[i * S + q1].x;
+    if (D.sj[i * S + q1] == j && w1 > best) { best = w1; bcode = path_code(1, q1); }
+  }
+  for (int q1 = 0; q1 < ni; ++q1) {
+    int k = D.sj[i * S + q1];
+    double w1 = D.sw[i * S + q1].x;
+    int nk = D.sn[k];
+    for (int q2 = 0; q2 < nk; ++q2) {
+      int m = D.sj[k * S + q2];
+      if (m == i) continue;
+      double w2 = w1 * D.sw[k * S + q2].x;
+      if (m == j && w2 > best) { best = w2; bcode = path_code(2, q1, q2); }
+    }
+  }
+  for (int q1 = 0; q1 < ni; ++q1) {
+    int k = D.sj[i * S + q1];
+    double w1 = D.sw[i * S + q1].x;
+    int nk = D.sn[k];
+    for (int q2 = 0; q2 < nk; ++q2) {
+      int m = D.sj[k * S + q2];
+      if (m == i) continue;
+      double w2 = w1 * D.sw[k * S + q2].x;
+      if (w2 <= 0.0) continue;
+      int nm = D.sn[m];
+      for (int q3 = 0; q3 < nm; ++q3) {
+        int t = D.sj[m * S + q3];
+        if (t != j || t == k) continue;
+        double w3 = w2 * D.sw[m * S + q3].x;
+        if (w3 > best) { best = w3; bcode = path_code(3, q1, q2, q3); }
+      }
+    }
+  }
 }
 
 // Gradient of E with respect to the path bonds, given dE/dprod.  `half`
@@ -1121,7 +1182,7 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
   for (int b = 0; b < pi.len; ++b) {
     int a = pi.at[b], s = pi.slot[b];
     rv[b] = nbr_vec<R>(D, a, s, rl[b]);
-    double2 wd = D.sw[a * SCAP + s];
+    double2 wd = D.sw[a * D.scap + s];
     w[b] = (R)wd.x;
     dw[b] = (R)wd.y;
   }
@@ -1160,10 +1221,10 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
     int off = g - (seg == 0 ? 0 : (seg == 1 ? n0 : n0 + n1));
     int2 bq = D.bonds[seg * D.bcap + off];
     int i = bq.x, slot = bq.y;
-    int j = D.sj[i * SCAP + slot];
+    int j = D.sj[i * D.scap + slot];
     R r;
     V3<R> rij = nbr_vec<R>(D, i, slot, r);
-    double2 wd = D.sw[i * SCAP + slot];
+    double2 wd = D.sw[i * D.scap + slot];
     R wij = (R)wd.x, dwij = (R)wd.y;
     int p = seg;
     acc.i = i; acc.j = j;
@@ -1404,58 +1465,73 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
   A e = 0;
   A fi[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
   unsigned long long n_in = 0, n_c0 = 0;
+  int n_srch = 0;   // pairs of this wavefront sent to the sequential C_ij search
   if (i < D.n) {
     double4 xi = D.x[i];
     int si = __double2int_rn(xi.w);
     const SysBox& B = box_of(D, i);
     const double Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
-    // ---- path map: levels 1 and 2, one lane per (q1, q2)
+    // ---- path map.  Level 1: one lane per short neighbour k of i.
     int ncand = 0;
+    bool ovf;   // more candidates than the map holds: near pairs go to the sequential search
     {
-      int q1 = lane >> 3, q2 = lane & 7;
-      int ni = D.sn[i];
-      int k = -1, m = -1;
-      double w1 = 0, w2 = 0;
-      if (q1 < ni) {
-        k = D.sj[i * SCAP + q1];
-        w1 = D.sw[i * SCAP + q1].x;
-        if (q2 < D.sn[k]) {
-          m = D.sj[k * SCAP + q2];
-          w2 = w1 * D.sw[k * SCAP + q2].x;
+      const int S = D.scap, sl = D.slog2;
+      const int ni = D.sn[i];
+      {
+        int k = -1;
+        double w1 = 0;
+        if (lane < ni) {
+          k = D.sj[i * S + lane];
+          w1 = D.sw[i * S + lane].x;
         }
+        bool c1 = k >= 0 && w1 > 0.0;
+        unsigned long long b1 = __ballot(c1);
+        if (c1) {
+          int pos = __popcll(b1 & below);
+          c_atom[wv][pos] = k; c_prod[wv][pos] = w1; c_code[wv][pos] = path_code(1, lane); c_k[wv][pos] = i;
+        }
+        ncand = __popcll(b1);
       }
-      bool c1 = q2 == 0 && k >= 0 && w1 > 0.0;
-      unsigned long long b1 = __ballot(c1);
-      if (c1) {
-        int pos = __popcll(b1 & below);
-        c_atom[wv][pos] = k; c_prod[wv][pos] = w1; c_code[wv][pos] = 1 | (q1 << 2); c_k[wv][pos] = i;
+      const int n2start = ncand;
+      // level 2: one lane per (q1, q2)
+      for (int base = 0; base < (ni << sl); base += WAVE) {
+        int t = base + lane, q1 = t >> sl, q2 = t & (S - 1);
+        int k = -1, m = -1;
+        double w2 = 0;
+        if (q1 < ni) {
+          k = D.sj[i * S + q1];
+          double w1 = D.sw[i * S + q1].x;
+          if (q2 < D.sn[k]) {
+            m = D.sj[k * S + q2];
+            w2 = w1 * D.sw[k * S + q2].x;
+          }
+        }
+        bool c2 = m >= 0 && m != i && w2 > 0.0;
+        unsigned long long b2 = __ballot(c2);
+        if (c2) {
+          int pos = ncand + __popcll(b2 & below);
+          if (pos < PCAP) {
+            c_atom[wv][pos] = m; c_prod[wv][pos] = w2; c_code[wv][pos] = path_code(2, q1, q2); c_k[wv][pos] = k;
+          }
+        }
+        ncand += __popcll(b2);
       }
-      ncand = __popcll(b1);
-      bool c2 = m >= 0 && m != i && w2 > 0.0;
-      unsigned long long b2 = __ballot(c2);
-      if (c2) {
-        int pos = ncand + __popcll(b2 & below);
-        if (pos < PCAP) { c_atom[wv][pos] = m; c_prod[wv][pos] = w2; c_code[wv][pos] = 2 | (q1 << 2) | (q2 << 5); c_k[wv][pos] = k; }
-      }
-      int n2start = ncand;
-      ncand += __popcll(b2);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
       int n2end = min(ncand, PCAP);
       // ---- level 3: one lane per (level-2 candidate, q3)
-      for (int base = n2start * 8; base < n2end * 8; base += WAVE) {
-        int c = (base + lane) >> 3, q3 = (base + lane) & 7;
+      for (int base = n2start << sl; base < (n2end << sl); base += WAVE) {
+        int c = (base + lane) >> sl, q3 = (base + lane) & (S - 1);
         bool c3 = false;
         int t = -1, code = 0;
         double w3 = 0;
         if (c < n2end) {
           int mm = c_atom[wv][c], kk = c_k[wv][c];
           if (q3 < D.sn[mm]) {
-            t = D.sj[mm * SCAP + q3];
-            w3 = c_prod[wv][c] * D.sw[mm * SCAP + q3].x;
-            code = c_code[wv][c] | (q3 << 8);
+            t = D.sj[mm * S + q3];
+            w3 = c_prod[wv][c] * D.sw[mm * S + q3].x;
+            code = (c_code[wv][c] & ~3) | 3 | (q3 << 12);
             c3 = t != i && t != kk && w3 > 0.0;
-            code = (code & ~3) | 3;
           }
         }
         unsigned long long b3 = __ballot(c3);
@@ -1467,12 +1543,12 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
-      if (ncand > PCAP && lane == 0) atomicOr(D.flags, F_OV_PATH);
+      ovf = ncand > PCAP;
       ncand = min(ncand, PCAP);
       for (int k = lane; k < HCAP; k += WAVE) { h_key[wv][k] = -1; h_val[wv][k] = 0ull; }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (lane < ncand) {   // PCAP == WAVE: one candidate per lane
+      if (lane < ncand && !ovf) {   // PCAP == WAVE: one candidate per lane
         int a = c_atom[wv][lane];
         unsigned long long v = ((unsigned long long)__double_as_longlong(c_prod[wv][lane]) & ~63ull) |
                                (unsigned long long)(63 - lane);
@@ -1510,7 +1586,14 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
         if ((double)r2 < sel3(K.rc2, p)) {
           if (i < j) ++n_in;
           bool plain = true;
-          if (r2 < K.rconn2) {
+          if (r2 < K.rconn2 && ovf) {
+            // path map incomplete: the deferred kernel searches C_ij for this
+            // pair and takes this end's share of it
+            push = true;
+            pcode = -1;
+            plain = false;
+            ++n_srch;
+          } else if (r2 < K.rconn2) {
             double prod = 0.0;
             int h = hslot(j);
             for (int probe = 0; probe < HCAP; ++probe) {
@@ -1555,6 +1638,8 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
     }
   }
   if (ndq > 0) flush_deferred(D, dq[wv], ndq);
+  for (int o = WAVE / 2; o > 0; o >>= 1) n_srch += __shfl_xor(n_srch, o);
+  if (lane == 0 && n_srch > 0) atomicAdd(&D.stats[S_SLOW], (unsigned long long)n_srch);
   // reduce the force on atom i across the wavefront
   for (int c = 0; c < 3; ++c) {
     A s = fi[c];
@@ -1589,12 +1674,15 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
   AccT<A> acc;
   acc.init(fbuf<A>(D), -1, -1);
   unsigned long long ndsb = 0;
+  unsigned long long nskip = 0, nc0 = 0;   // searched pairs that are not deferred pairs; of them with C_ij = 0
+  unsigned long long nbstar = 0;           // evaluated pairs inside the S_r range (b* needed)
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += gridDim.x * blockDim.x) {
     int g = 0;
     while (seg_start[g + 1] <= t) ++g;
     int4 qe = D.q[(size_t)g * D.qcap + (t - seg_start[g])];
     A W0[6];
     for (int c = 0; c < 6; ++c) W0[c] = acc.W[c];
+    A e0 = e;
     int i = qe.x, j = qe.y, code = qe.z, pcode = qe.w;
     double4 xi = D.x[i], xj = D.x[j];
     const SysBox& B = box_of(D, i);
@@ -1603,47 +1691,74 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
     A dy = (A)xj.y - (A)xi.y + (A)(((code / 3) % 3 - 1) * B.L[1]);
     A dz = (A)xj.z - (A)xi.z + (A)((code % 3 - 1) * B.L[2]);
     int p = __double2int_rn(xi.w) + __double2int_rn(xj.w);
-    A r = xsqrt(dx * dx + dy * dy + dz * dz);
+    A r2 = dx * dx + dy * dy + dz * dz;
+    A r = xsqrt(r2);
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
     A V, dV;
     vdw_pair<A, M>(P, p, r, V, dV);
-    A prod = 0;
-    PathInfo pi;
-    pi.len = 0;
-    if (pcode) {
-      pi = decode_path(D, i, pcode);
-      prod = 1;
-      for (int b = 0; b < pi.len; ++b) prod *= (A)D.sw[pi.at[b] * SCAP + pi.slot[b]].x;
+    bool evaluate = true;
+    if (pcode < 0) {
+      // sequential C_ij search for an atom whose path map overflowed; this
+      // end classifies the pair as the map would have
+      double best;
+      path_search(D, i, j, best, pcode);
+      if (best >= 1.0) {                                   // C_ij = 0
+        if (i < j) ++nc0;
+        evaluate = false;
+      } else if (best > 0.0 || (double)r2 < P.rljmax[p] * P.rljmax[p]) {
+        evaluate = i < j;                                   // a deferred pair: the lower index evaluates it
+      } else {                                              // a plain pair: this end's half
+        A G = dV / r;
+        e += (A)0.5 * V;
+        A g3[3] = {G * dx, G * dy, G * dz};
+        for (int c = 0; c < 3; ++c) acc.fi[c] += g3[c];
+        acc.W[0] -= (A)0.5 * dx * g3[0]; acc.W[1] -= (A)0.5 * dy * g3[1]; acc.W[2] -= (A)0.5 * dz * g3[2];
+        acc.W[3] -= (A)0.5 * dx * g3[1]; acc.W[4] -= (A)0.5 * dx * g3[2]; acc.W[5] -= (A)0.5 * dy * g3[2];
+        acc.flush();
+        evaluate = false;
+      }
+      if (!evaluate) ++nskip;
     }
-    A C = (A)1 - prod;
-    A dSr;
-    A Sr = Sw((r - (A)P.sigma[p]) * (A)P.inv_rlj[p], dSr);
-    dSr *= (A)P.inv_rlj[p];
-    V3<R> rij = {(R)dx, (R)dy, (R)dz};
-    V3<R> gij = {0, 0, 0};
-    A Sb = 1, dSb = 0;
-    BondFwd<R> bf;
-    if (Sr > (A)0) {
-      R bs = bond_order_fwd(P, D, i, j, rij, (R)r, true, bf, acc.st);
-      A inv_b = (A)(1.0 / (P.bmax[p] - P.bmin[p]));
-      Sb = Sw(((A)bs - (A)P.bmin[p]) * inv_b, dSb);
-      dSb *= inv_b;
+    if (evaluate) {
+      A prod = 0;
+      PathInfo pi;
+      pi.len = 0;
+      if (pcode) {
+        pi = decode_path(D, i, pcode);
+        prod = 1;
+        for (int b = 0; b < pi.len; ++b) prod *= (A)D.sw[pi.at[b] * D.scap + pi.slot[b]].x;
+      }
+      A C = (A)1 - prod;
+      A dSr;
+      A Sr = Sw((r - (A)P.sigma[p]) * (A)P.inv_rlj[p], dSr);
+      dSr *= (A)P.inv_rlj[p];
+      V3<R> rij = {(R)dx, (R)dy, (R)dz};
+      V3<R> gij = {0, 0, 0};
+      A Sb = 1, dSb = 0;
+      BondFwd<R> bf;
+      if (Sr > (A)0) {
+        ++nbstar;
+        R bs = bond_order_fwd(P, D, i, j, rij, (R)r, true, bf, acc.st);
+        A inv_b = (A)(1.0 / (P.bmax[p] - P.bmin[p]));
+        Sb = Sw(((A)bs - (A)P.bmin[p]) * inv_b, dSb);
+        dSb *= inv_b;
+      }
+      A Qf = Sr * Sb + (A)1 - Sr;
+      e += Qf * C * V;
+      A Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
+      if (dSb != (A)0) {   // the reverse pass reuses the forward state
+        ++ndsb;
+        R Gb = (R)(Sr * dSb * C * V);
+        bond_order_rev(P, D, i, j, rij, (R)r, true, bf, Gb, gij, acc);
+      }
+      if (prod > (A)0) path_grad<A>(D, pi, -Qf * V, 1.0, 1.0, acc);
+      gij = gij + (R)(Gr / r) * rij;
+      acc.vec(i, j, rij, gij);
+      acc.flush();
     }
-    A Qf = Sr * Sb + (A)1 - Sr;
-    e += Qf * C * V;
-    A Gr = (dSr * Sb - dSr) * C * V + Qf * C * dV;
-    if (dSb != (A)0) {   // the reverse pass reuses the forward state
-      ++ndsb;
-      R Gb = (R)(Sr * dSb * C * V);
-      bond_order_rev(P, D, i, j, rij, (R)r, true, bf, Gb, gij, acc);
-    }
-    if (prod > (A)0) path_grad<A>(D, pi, -Qf * V, 1.0, 1.0, acc);
-    gij = gij + (R)(Gr / r) * rij;
-    acc.vec(i, j, rij, gij);
-    acc.flush();
     if (D.nsys > 1) {
-      double dv[7] = {(double)(Qf * C * V)};
+      double dv[7] = {(double)(e - e0)};
       for (int c = 0; c < 6; ++c) dv[1 + c] = (double)(acc.W[c] - W0[c]);
       int sid = sys_of(D, i);
       for (int q = 0; q < 7; ++q)
@@ -1651,10 +1766,10 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
     }
   }
   __syncthreads();
-  double v13[13] = {(double)e, (double)acc.W[0], (double)acc.W[1], (double)acc.W[2], (double)acc.W[3],
-                    (double)acc.W[4], (double)acc.W[5], 0.0, 0.0, (double)ndsb, 0.0,
-                    (double)acc.st[0], (double)acc.st[1]};
-  block_reduce_add<13>(v13, D.acc + A_ELJ);  // A_ELJ .. A_SPL64
+  double v15[15] = {(double)e, (double)acc.W[0], (double)acc.W[1], (double)acc.W[2], (double)acc.W[3],
+                    (double)acc.W[4], (double)acc.W[5], 0.0, (double)nc0, (double)ndsb, 0.0,
+                    (double)acc.st[0], (double)acc.st[1], (double)nskip, (double)nbstar};
+  block_reduce_add<15>(v15, D.acc + A_ELJ);  // A_ELJ .. A_NBSTAR
 }
 
 // Maximum of per-atom counts into a statistics slot, and the sum of the
@@ -1691,7 +1806,8 @@ __global__ void k_finish(Dev D, double* energy, double* virial) {
     }
     unsigned long long nq = 0;
     for (int g = 0; g < NSEG; ++g) nq += (unsigned long long)min(D.qcount[g * QSTRIDE], D.qcap);
-    D.stats[S_BSTAR] = nq;
+    D.stats[S_BSTAR] = (unsigned long long)tot[A_NBSTAR];
+    D.stats[S_QUEUED] = nq - (unsigned long long)tot[A_NSKIP];
     D.stats[S_BONDS] = (unsigned long long)(D.bcount[0] + D.bcount[1] + D.bcount[2]);
     D.stats[S_INCUT] = (unsigned long long)tot[A_NIN];
     D.stats[S_CIJ0] = (unsigned long long)tot[A_NC0];
@@ -1975,8 +2091,11 @@ struct airebo_ctx {
   size_t c_asys = 0;
   double* sys_acc = nullptr;
   size_t c_sacc = 0;
-  // deferred-pair queue entries reserved per atom (grows on overflow)
+  // deferred-pair queue entries reserved per atom, short-list and
+  // intermediate-list entries per atom (all grow on overflow)
   int q_per_atom = 8;
+  int scap = SCAP;
+  int icap = ICAP;
   // capacity growths of the current call or MD session (statistics slot S_REGROW)
   unsigned long long regrow = 0;
   // molecular-dynamics session (airebo_md_*): the run's parameters, its
@@ -2259,15 +2378,15 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   rc |= grow(c->lj_n, c->c_ljn, N);
   rc |= grow(c->lj_e, c->c_lje, N * (size_t)c->lj_cap);
   rc |= grow(c->in_n, c->c_inn, N);
-  rc |= grow(c->in_e, c->c_ine, N * ICAP);
+  rc |= grow(c->in_e, c->c_ine, N * c->icap);
   rc |= grow(c->sn, c->c_sn, N);
-  rc |= grow(c->sj, c->c_sj, N * SCAP);
-  rc |= grow(c->sd, c->c_sd, N * SCAP);
-  rc |= grow(c->sw, c->c_sw, N * SCAP);
+  rc |= grow(c->sj, c->c_sj, N * c->scap);
+  rc |= grow(c->sd, c->c_sd, N * c->scap);
+  rc |= grow(c->sw, c->c_sw, N * c->scap);
   rc |= grow(c->NCt, c->c_nc, N);
   rc |= grow(c->NHt, c->c_nh, N);
   rc |= grow(c->bcount, c->c_bc, 4);
-  size_t bcap = N * SCAP / 2 + 64;
+  size_t bcap = N * c->scap / 2 + 64;
   rc |= grow(c->bonds, c->c_b, 3 * bcap);
   rc |= grow(c->qcount, c->c_qc, NSEG * QSTRIDE);
   size_t qcap = ((size_t)c->q_per_atom * N + 1024 * NSEG) / NSEG;   // per segment
@@ -2303,6 +2422,9 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   D.x = c->x; D.xref = c->xref; D.xsort = c->xsort; D.cell_of = c->cell_of; D.cell_count = c->cell_count; D.cell_start = c->cell_start;
   D.cell_cursor = c->cell_cursor; D.cell_atoms = c->cell_atoms; D.lj_cap = c->lj_cap; D.lj_n = c->lj_n;
   D.lj_e = c->lj_e; D.in_n = c->in_n; D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
+  D.icap = c->icap;
+  D.scap = c->scap;
+  D.slog2 = 31 - __builtin_clz((unsigned)c->scap);
   D.NCt = c->NCt; D.NHt = c->NHt; D.bcap = (int)bcap; D.bcount = c->bcount; D.bonds = c->bonds;
   D.qcap = (int)qcap; D.qcount = c->qcount;
   D.q = c->q; D.F = c->F; D.F32 = c->F32; D.acc = c->acc; D.stats = c->stats; D.flags = c->flags; D.step = c->step;
@@ -2388,8 +2510,11 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
 int check_flags(airebo_ctx* c, int flags) {
   if (flags & F_BADSPEC) return fail(AIREBO_E_SPECIES, "species codes must be 0 (C) or 1 (H)");
   if (flags & F_NONFINITE) return fail(AIREBO_E_NONFINITE, "non-finite position or energy");
-  if (flags & F_OV_SHORT) return fail(AIREBO_E_CAPACITY, "an atom has more than 8 REBO neighbours");
-  if (flags & F_OV_INT) return fail(AIREBO_E_CAPACITY, "intermediate REBO list capacity exceeded");
+  if (flags & F_OV_SHORT)
+    return fail(AIREBO_E_CAPACITY, "an atom has more than " + std::to_string(c->scap) + " REBO neighbours");
+  if (flags & F_OV_INT)
+    return fail(AIREBO_E_CAPACITY, "an atom has more than " + std::to_string(c->icap) +
+                                       " atoms within the REBO cutoff plus skin");
   if (flags & F_OV_PATH) return fail(AIREBO_E_CAPACITY, "path map capacity exceeded");
   if (flags & F_OV_BOND) return fail(AIREBO_E_CAPACITY, "bond list capacity exceeded");
   if (flags & F_OV_QUEUE) return fail(AIREBO_E_CAPACITY, "b* queue capacity exceeded");
@@ -2398,11 +2523,23 @@ int check_flags(airebo_ctx* c, int flags) {
   return 0;
 }
 
-// Capacity growth after an overflow reported in `flags`: the LJ list to the
+// Capacities that grow when an evaluation or MD chunk overflows them.
+constexpr int F_GROW = F_OV_LJ | F_OV_QUEUE | F_OV_SHORT | F_OV_INT;
+
+// Capacity growth after an overflow reported in `flags`: the short and
+// intermediate lists to twice their entries per atom, the LJ list to the
 // largest row seen (plus headroom), the deferred-pair queue to twice its
 // entries per atom.  Returns nonzero when a limit is reached.
 int grow_caps(airebo_ctx* c, int flags) {
   ++c->regrow;
+  if (flags & F_OV_SHORT) {
+    if (c->scap >= SCAP_MAX) return 1;
+    c->scap *= 2;
+  }
+  if (flags & F_OV_INT) {
+    if (c->icap >= ICAP_MAX) return 1;
+    c->icap = std::min(2 * c->icap, ICAP_MAX);
+  }
   if (flags & F_OV_LJ) {
     if (c->lj_cap >= (1 << 16)) return 1;
     unsigned long long need = c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32;
@@ -2453,13 +2590,13 @@ int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* box
     HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     c->host_stats[S_REGROW] = c->regrow;
-    if (flags & (F_OV_LJ | F_OV_QUEUE)) {   // grow the LJ list or the queue and evaluate again
-      if (grow_caps(c, flags)) return fail(AIREBO_E_CAPACITY, "list or queue capacity limit reached");
+    if ((flags & F_GROW) && !(flags & (F_BADSPEC | F_NONFINITE))) {   // grow what overflowed and evaluate again
+      if (grow_caps(c, flags)) return check_flags(c, flags);
       continue;
     }
     return check_flags(c, flags);
   }
-  return fail(AIREBO_E_CAPACITY, "list or queue capacity could not be established");
+  return fail(AIREBO_E_CAPACITY, "list or queue capacities could not be established");
 }
 
 // One evaluation with every work buffer in the device's static work area
@@ -2513,6 +2650,10 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
   D.lj_e = reinterpret_cast<unsigned*>(base + L.lj_e);
   D.in_n = reinterpret_cast<int*>(base + L.in_n);
   D.in_e = reinterpret_cast<int*>(base + L.in_e);
+  D.icap = ICAP;
+  D.scap = SCAP;
+  D.slog2 = 3;
+  static_assert(SCAP == 8, "static short-list stride");
   D.sn = reinterpret_cast<int*>(base + L.sn);
   D.sj = reinterpret_cast<int*>(base + L.sj);
   D.sd = reinterpret_cast<double4*>(base + L.sd);
@@ -2579,6 +2720,9 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
       continue;
     }
     if (flags & F_OV_QUEUE) return done(fail(AIREBO_E_CAPACITY, "deferred-pair queue exceeds the static work area"));
+    if (flags & (F_OV_SHORT | F_OV_INT))
+      return done(fail(AIREBO_E_CAPACITY, "more than 8 short or 48 intermediate neighbours of an atom exceed the "
+                                          "static work area"));
     return done(check_flags(c, flags));
   }
   return done(fail(AIREBO_E_CAPACITY, "LJ list capacity could not be established in the static work area"));
@@ -2778,10 +2922,10 @@ int md_run_impl(airebo_ctx* c, int64_t nsteps, int64_t every, double* thermo, hi
     HIPCHK(hipMemcpyAsync(md.vel, md.vsave, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, cs));
     HIPCHK(hipMemcpyAsync(c->stats, md.ssave, sizeof(unsigned long long) * S_N, hipMemcpyDeviceToDevice, cs));
     HIPCHK(hipMemcpyAsync(c->step, md.ssave + S_N, sizeof(int), hipMemcpyDeviceToDevice, cs));
-    bool capacity = (flags & (F_OV_LJ | F_OV_QUEUE)) && !(flags & (F_ERRORS & ~(F_OV_LJ | F_OV_QUEUE)));
+    bool capacity = (flags & F_GROW) && !(flags & (F_ERRORS & ~F_GROW));
     if (capacity) {
-      if (++regrow > 8 || grow_caps(c, flags)) {
-        rc = fail(AIREBO_E_CAPACITY, "list or queue capacity limit reached during MD");
+      if (++regrow > 12 || grow_caps(c, flags)) {
+        rc = check_flags(c, flags);
       } else {
         rc = md_setup(c, cs);
       }

@@ -1285,8 +1285,8 @@ int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species,
     HIPCHK(hipMemcpyAsync(&flags, c->flags, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(c->host_stats, c->stats, sizeof c->host_stats, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (flags & (F_OV_LJ | F_OV_QUEUE)) {
-      if (grow_caps(c, flags)) return fail(AIREBO_E_CAPACITY, "list or queue capacity limit reached");
+    if ((flags & F_GROW) && !(flags & (F_BADSPEC | F_NONFINITE))) {
+      if (grow_caps(c, flags)) return check_flags(c, flags);
       continue;
     }
     return check_flags(c, flags);
