@@ -83,14 +83,14 @@ constexpr int NSEG = 64, QSTRIDE = 32;
 // kernel ids for per-kernel timing
 enum { K_LOAD, K_BIN, K_SCAN, K_FILL, K_BUILD, K_BUILD_DONE, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
        K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_PACK,
-       K_NN_ENS, K_NN_DECIDE, K_FOLD32, K_COUNT };
+       K_NN_ENS, K_NN_DECIDE, K_FOLD32, K_LJF, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {
     "k_load", "k_bin", "k_scan", "k_fill", "k_build", "k_build_done", "k_zero", "k_short", "k_bond",
     "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo", "nn_zero", "nn_order", "nn_desc",
-    "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32"};
+    "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32", "k_ljf"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_LJENT = 7,
-       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_SLOW = 13, S_QUEUED = 14, S_N = 16 };
+       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_SLOW = 13, S_QUEUED = 14, S_MAXLF = 15, S_N = 16 };
 
 // One system of a batch: its own periodic box and cell grid.  A single
 // configuration is a batch of one.
@@ -117,9 +117,17 @@ struct Dev {
   int* cell_start;
   int* cell_cursor;
   int* cell_atoms;
+  // LJ list in two parts, both full (every pair from both ends): near
+  // pairs (within 3 max R2 + skin at the build, where C_ij < 1 and the S_r
+  // range can occur) and far pairs (plain LJ for the list's lifetime)
+  double rnear;      // near / far boundary at the build: 3 max R2 + skin
+  int minimg;        // every periodic side >= 2 (LJ list cutoff + skin): far pairs by minimum image
   int lj_cap;
   int* lj_n;
-  unsigned* lj_e;    // j | shift code << 27
+  unsigned* lj_e;    // near: j | shift code << 27
+  int lf_cap;
+  int* lf_n;
+  unsigned* lf_e;    // far: j | shift code << 27
   int icap;          // intermediate-list stride
   int* in_n;
   int* in_e;
@@ -884,9 +892,13 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
     rlf[p] = a * a;
     rif[p] = b * b;
   }
+  // a pair goes to the far part only if its FP32 distance is beyond the
+  // boundary by more than the FP32 rounding, so every pair that can come
+  // within 3 max R2 before the next build is in the near part
+  const float rnf = ((float)D.rnear + 1e-3f) * ((float)D.rnear + 1e-3f);
   float xix = (float)xi.x, xiy = (float)xi.y, xiz = (float)xi.z;
   float Lx = (float)B.L[0], Ly = (float)B.L[1], Lz = (float)B.L[2];
-  int nlj = 0, nin = 0;
+  int nlj = 0, nlf = 0, nin = 0;
   unsigned long long below = lanes_below();
   int j_n = -1;
   float4 x_n = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -908,7 +920,7 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
       j_n = D.cell_atoms[slot];
       x_n = D.xsort[slot];
     }
-    bool ok_lj = false, ok_in = false;
+    bool ok_lj = false, ok_in = false, far = false;
     if (v < total) {
       float dx = xj.x + (float)((int)(cd / 9) - 1) * Lx - xix;
       float dy = xj.y + (float)((int)((cd / 3) % 3) - 1) * Ly - xiy;
@@ -920,13 +932,20 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
       bool self = (j == i) && cd == 13;
       ok_lj = !self && r2 < rl;
       ok_in = !self && r2 < ri;
+      far = r2 >= rnf;
     }
-    unsigned long long m = __ballot(ok_lj);
-    if (ok_lj) {
+    unsigned long long m = __ballot(ok_lj && !far);
+    if (ok_lj && !far) {
       int pos = nlj + __popcll(m & below);
       if (pos < D.lj_cap) D.lj_e[(size_t)i * D.lj_cap + pos] = (unsigned)j | (cd << 27);
     }
     nlj += __popcll(m);
+    m = __ballot(ok_lj && far);
+    if (ok_lj && far) {
+      int pos = nlf + __popcll(m & below);
+      if (pos < D.lf_cap) D.lf_e[(size_t)i * D.lf_cap + pos] = (unsigned)j | (cd << 27);
+    }
+    nlf += __popcll(m);
     m = __ballot(ok_in);
     if (ok_in) {
       int pos = nin + __popcll(m & below);
@@ -935,9 +954,10 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
     nin += __popcll(m);
   }
   if (lane == 0) {
-    D.lj_n[i] = nlj;            // unclamped; readers clamp to lj_cap
+    D.lj_n[i] = nlj;            // unclamped; readers clamp to lj_cap / lf_cap
+    D.lf_n[i] = nlf;
     D.in_n[i] = min(nin, D.icap);
-    if (nlj > D.lj_cap) atomicOr(D.flags, F_OV_LJ);
+    if (nlj > D.lj_cap || nlf > D.lf_cap) atomicOr(D.flags, F_OV_LJ);
     if (nin > D.icap) atomicOr(D.flags, F_OV_INT);
   }
 }
@@ -1374,21 +1394,40 @@ struct PairConst {
 };
 __device__ __forceinline__ double sel3(const double (&a)[3], int p) { return p == 0 ? a[0] : (p == 1 ? a[1] : a[2]); }
 
+// FP64 reciprocal and reciprocal square root for the plain pair loops: the
+// hardware estimate refined by one Newton-Raphson step, which doubles its
+// correct bits; the result is within a few ulp of the correctly rounded
+// value at a fraction of the cost of the IEEE division and square root
+// sequences.  FP32 keeps the compiler's operations.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);   // y <- y (1 + e / 2), e = 1 - x y^2
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rcp_nr(float x) { return 1.0f / x; }
+__device__ __forceinline__ float rsq_nr(float x) { return 1.0f / sqrtf(x); }
+
 // Plain LJ pair from r^2 with the pair-class constants already selected:
 // sg2 = sigma^2, e4 = 4 eps, r0 = start of the outer switch.
 template <typename R>
 __device__ __forceinline__ void lj_pair_r2c(R r2, R sg2, R e4, R r0, R isw, R& V, R& G) {
-  R ir2 = (R)1 / r2;
+  R ir2 = rcp_nr(r2);
   R s2 = sg2 * ir2;
   R s6 = s2 * s2 * s2;
   R v = e4 * (s6 * s6 - s6);
   R gv = e4 * ((R)-12 * s6 * s6 + (R)6 * s6) * ir2;
   if (r2 > r0 * r0) {
-    R r = sqrt(r2);
+    R ir = rsq_nr(r2);
+    R r = r2 * ir;
     R dS;
     R S = Sw((r - r0) * isw, dS);
     V = v * S;
-    G = gv * S + v * dS * isw / r;
+    G = gv * S + v * dS * isw * ir;
   } else {
     V = v;
     G = gv;
@@ -1413,30 +1452,31 @@ __device__ __forceinline__ void vdw_pair_r2(const DevParams& P, int p, R r2, R& 
   }
 }
 
-// LJ term (Alg. 3), one wavefront per atom over its full list.
+// LJ term (Alg. 3), near pairs: one wavefront per atom over the near part of
+// its list (the far part is k_ljf's).
 //
 // The wavefront first maps every atom reachable from i over at most three
 // short bonds (no atom repeated) into LDS, with the weight product of the
 // path and the path itself (the reversed C_ij search: map once per atom, then
 // look up per pair).  Candidates are kept per path; a lookup takes the
 // largest product over the candidates of an atom (first one on ties, direct
-// before one intermediate before two).  Then, over the full list, pairs
+// before one intermediate before two).  Then, over the near list, pairs
 // beyond 3 max R2 are plain LJ; nearer pairs look up C_ij: C = 0 is skipped,
 // C = 1 outside the S_r range is plain LJ, and every other pair (0 < C < 1 or
 // inside the S_r range) is deferred to a queue that k_bstar evaluates in
 // full.  Each pair is seen from both ends: each end adds half the energy and
 // virial and the full force on its own atom.
-// Minimum waves per SIMD asked of the compiler for the LJ kernel: the FP32
-// instantiations fit six (80 VGPRs) without spilling; FP64 keeps five; the
-// Morse form (a square root and an exponential more per pair) four, where
-// five would spill.
-template <typename R, bool M>
+// Minimum waves per SIMD asked of the compiler for the near LJ kernel:
+// single precision fits six (80 VGPRs) without spilling; FP64 and mixed
+// precision (FP64 sums) keep five; the Morse form (a square root and an
+// exponential more per pair) four, where five would spill.
+template <typename R, typename A, bool M>
 struct LjWaves {
-  static constexpr int value = M ? 4 : (std::is_same<R, float>::value ? 6 : 5);
+  static constexpr int value = M ? 4 : (std::is_same<A, float>::value ? 6 : 5);
 };
 
 template <typename R, typename A, bool M>
-__global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R, M>::value, 8))) void k_lj(
+__global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWaves<R, A, M>::value, 8))) void k_lj(
     Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
@@ -1649,6 +1689,105 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
   // each pair is seen from both ends: half the energy, minus half the virial
   double v9[9] = {0.5 * (double)e, -0.5 * (double)W[0], -0.5 * (double)W[1], -0.5 * (double)W[2],
                   -0.5 * (double)W[3], -0.5 * (double)W[4], -0.5 * (double)W[5], (double)n_in, (double)n_c0};
+  if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v9, A_ELJ, i < D.n);
+  block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
+}
+
+// Far LJ pairs: beyond 3 max R2 + skin at the list build, so beyond 3 max R2
+// for the list's lifetime, where no path of three short bonds reaches
+// (C_ij = 1) and the S_r switch is 0: the plain pair term with its outer
+// cutoff switch (Alg. 3 with C = 1, S_r = 0).  LJF_G lanes per atom take its
+// entries in turn, LJF_U at a time, every list entry and position of the
+// LJF_U requested before any is used, so that a wavefront keeps many
+// position gathers in flight; no LDS path map, few registers, high
+// occupancy.  Each pair is seen from both ends, as in the near kernel.
+#ifndef LJF_UNROLL
+#define LJF_UNROLL 2
+#endif
+#ifndef LJF_MIN_WAVES
+#define LJF_MIN_WAVES 5
+#endif
+constexpr int LJF_G = 16, LJF_U = LJF_UNROLL, LJF_WAVES = LJF_MIN_WAVES;
+// MI: every periodic side is at least twice the list cutoff plus twice the
+// skin, so each listed pair stays closer than half a side and its relative
+// vector is the minimum image (no shift code decoded).
+template <typename R, typename A, bool M, bool MI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M ? 4 : LJF_WAVES, 8))) void k_ljf(
+    Dev D, const DevParams* __restrict__ Pp) {
+  if (D.skip && *D.skip) return;
+  const DevParams& P = *Pp;
+  __shared__ PairConst K;
+  if (threadIdx.x == 0) K.load(P);
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int sub = lane & (LJF_G - 1);
+  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LJF_G);
+  constexpr unsigned NONE = 0xFFFFFFFFu;   // no entry (a real entry has shift code <= 26)
+  A e = 0;
+  A fi[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long n_in = 0;
+  if (i < D.n) {
+    const double4 xi = D.x[i];
+    const int si = __double2int_rn(xi.w);
+    const SysBox& B = box_of(D, i);
+    const double Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
+    // minimum image: inverse sides of the periodic directions, 0 otherwise
+    const A iLx = B.per[0] ? (A)B.invL[0] : (A)0, iLy = B.per[1] ? (A)B.invL[1] : (A)0,
+            iLz = B.per[2] ? (A)B.invL[2] : (A)0;
+    const int nl = min(D.lf_n[i], D.lf_cap);
+    const unsigned* list = D.lf_e + (size_t)i * D.lf_cap;
+    for (int k0 = sub; k0 < nl; k0 += LJF_G * LJF_U) {
+      unsigned ent[LJF_U];
+      double4 xj[LJF_U];
+#pragma unroll
+      for (int u = 0; u < LJF_U; ++u) {
+        int k = k0 + u * LJF_G;
+        ent[u] = k < nl ? list[k] : NONE;
+      }
+      // unconditional loads (a missing entry reads atom i's own position)
+#pragma unroll
+      for (int u = 0; u < LJF_U; ++u) xj[u] = D.x[ent[u] != NONE ? (int)(ent[u] & 0x7FFFFFFu) : i];
+#pragma unroll
+      for (int u = 0; u < LJF_U; ++u) {
+        if (ent[u] == NONE) continue;
+        const int j = (int)(ent[u] & 0x7FFFFFFu), code = (int)(ent[u] >> 27);
+        A dx, dy, dz;
+        if constexpr (MI) {
+          dx = (A)xj[u].x - (A)xi.x;
+          dy = (A)xj[u].y - (A)xi.y;
+          dz = (A)xj[u].z - (A)xi.z;
+          dx -= (A)Lx * xrint(dx * iLx);
+          dy -= (A)Ly * xrint(dy * iLy);
+          dz -= (A)Lz * xrint(dz * iLz);
+        } else {
+          dx = (A)xj[u].x - (A)xi.x + (A)((code / 9 - 1) * Lx);
+          dy = (A)xj[u].y - (A)xi.y + (A)(((code / 3) % 3 - 1) * Ly);
+          dz = (A)xj[u].z - (A)xi.z + (A)((code % 3 - 1) * Lz);
+        }
+        A r2 = dx * dx + dy * dy + dz * dz;
+        int p = si + __double2int_rn(xj[u].w);
+        if ((double)r2 < sel3(K.rc2, p)) {
+          if (i < j) ++n_in;
+          R V, g;   // dE/dr_ij vector = g * d
+          if constexpr (M) vdw_pair_r2<R, M>(P, p, (R)r2, V, g);
+          else lj_pair_r2c<R>((R)r2, (R)sel3(K.sg2, p), (R)sel3(K.e4, p), (R)sel3(K.r0, p), (R)K.isw, V, g);
+          e += (A)V;
+          R fx = g * (R)dx, fy = g * (R)dy, fz = g * (R)dz;
+          fi[0] += (A)fx; fi[1] += (A)fy; fi[2] += (A)fz;
+          W[0] += (A)(fx * (R)dx); W[1] += (A)(fy * (R)dy); W[2] += (A)(fz * (R)dz);
+          W[3] += (A)(fy * (R)dx); W[4] += (A)(fz * (R)dx); W[5] += (A)(fz * (R)dy);
+        }
+      }
+    }
+  }
+  // force on atom i: reduce over its LJF_G lanes
+  for (int c = 0; c < 3; ++c) {
+    A v = fi[c];
+    for (int o = LJF_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (sub == 0 && i < D.n && v != 0) atomic_add(&fbuf<A>(D)[3 * i + c], v);
+  }
+  double v9[9] = {0.5 * (double)e, -0.5 * (double)W[0], -0.5 * (double)W[1], -0.5 * (double)W[2],
+                  -0.5 * (double)W[3], -0.5 * (double)W[4], -0.5 * (double)W[5], (double)n_in, 0.0};
   if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v9, A_ELJ, i < D.n);
   block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
 }
@@ -1947,14 +2086,15 @@ __global__ void k_set_flags(Dev D, int v) {
 // file-scope device array at fixed offsets.
 // ---------------------------------------------------------------------------
 constexpr int64_t STATIC_MAX_ATOMS = 8192;
-constexpr int64_t STATIC_LJ_ENTRIES = STATIC_MAX_ATOMS * 512;   // LJ list entries (512 per atom at the maximum)
+constexpr int64_t STATIC_LJ_ENTRIES = STATIC_MAX_ATOMS * 224;   // near LJ entries (224 per atom at the maximum)
+constexpr int64_t STATIC_LF_ENTRIES = STATIC_MAX_ATOMS * 384;   // far LJ entries (384 per atom at the maximum)
 constexpr int64_t STATIC_MAX_CELLS = 32768;
 constexpr int64_t STATIC_QUEUE = 16 * STATIC_MAX_ATOMS + 1024 * NSEG;   // deferred-pair queue entries
 constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct StaticLayout {
-  size_t x, xref, xsort, cell_of, cell_count, cell_start, cell_cursor, cell_atoms, lj_n, lj_e, in_n, in_e, sn, sj,
-      sd, sw, NCt, NHt, bcount, bonds, qcount, q, F32, acc, stats, flags, step, sys, total;
+  size_t x, xref, xsort, cell_of, cell_count, cell_start, cell_cursor, cell_atoms, lj_n, lj_e, lf_n, lf_e, in_n, in_e,
+      sn, sj, sd, sw, NCt, NHt, bcount, bonds, qcount, q, F32, acc, stats, flags, step, sys, total;
 };
 constexpr StaticLayout static_layout() {
   StaticLayout L{};
@@ -1962,11 +2102,11 @@ constexpr StaticLayout static_layout() {
   const size_t N = STATIC_MAX_ATOMS, C = STATIC_MAX_CELLS;
   const size_t bcap = N * SCAP / 2 + 64;
   size_t* fields[] = {&L.x, &L.xref, &L.xsort, &L.cell_of, &L.cell_count, &L.cell_start, &L.cell_cursor,
-                      &L.cell_atoms, &L.lj_n, &L.lj_e, &L.in_n, &L.in_e, &L.sn, &L.sj, &L.sd, &L.sw, &L.NCt,
+                      &L.cell_atoms, &L.lj_n, &L.lj_e, &L.lf_n, &L.lf_e, &L.in_n, &L.in_e, &L.sn, &L.sj, &L.sd, &L.sw, &L.NCt,
                       &L.NHt, &L.bcount, &L.bonds, &L.qcount, &L.q, &L.F32, &L.acc, &L.stats, &L.flags, &L.step,
                       &L.sys};
   const size_t bytes[] = {32 * N, 32 * N, 16 * N, 4 * N, 4 * C, 4 * (C + 1), 4 * C, 4 * N, 4 * N,
-                          4 * (size_t)STATIC_LJ_ENTRIES, 4 * N, 4 * N * ICAP, 4 * N, 4 * N * SCAP, 32 * N * SCAP,
+                          4 * (size_t)STATIC_LJ_ENTRIES, 4 * N, 4 * (size_t)STATIC_LF_ENTRIES, 4 * N, 4 * N * ICAP, 4 * N, 4 * N * SCAP, 32 * N * SCAP,
                           16 * N * SCAP, 8 * N, 8 * N, 16, 8 * 3 * bcap, 4 * NSEG * QSTRIDE,
                           16 * (size_t)STATIC_QUEUE, 12 * N, 8 * NSLOT * A_N, 8 * S_N, 16, 16, sizeof(SysBox)};
   for (size_t k = 0; k < sizeof(bytes) / sizeof(bytes[0]); ++k) {
@@ -2048,6 +2188,11 @@ struct airebo_ctx {
   size_t c_ljn = 0;
   unsigned* lj_e = nullptr;
   size_t c_lje = 0;
+  int lf_cap = 0;
+  int* lf_n = nullptr;
+  size_t c_lfn = 0;
+  unsigned* lf_e = nullptr;
+  size_t c_lfe = 0;
   int *in_n = nullptr, *in_e = nullptr, *sn = nullptr, *sj = nullptr;
   size_t c_inn = 0, c_ine = 0, c_sn = 0, c_sj = 0;
   double4* sd = nullptr;
@@ -2289,7 +2434,7 @@ void airebo_ctx_free(airebo_ctx_t c) {
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   void* ptrs[] = {c->dP, c->dtri, c->x, c->xref, c->xsort, c->cell_of, c->cell_count, c->cell_start, c->cell_cursor,
-                  c->cell_atoms, c->lj_n, c->lj_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
+                  c->cell_atoms, c->lj_n, c->lj_e, c->lf_n, c->lf_e, c->in_n, c->in_e, c->sn, c->sj, c->sd, c->sw, c->NCt, c->NHt,
                   c->bcount, c->bonds, c->qcount, c->q, c->F, c->F32, c->acc, c->dsys, c->atom_sys, c->sys_acc,
                   c->stats, c->flags, c->step, c->hx, c->hs};
   for (void* p : ptrs)
@@ -2344,6 +2489,16 @@ int plan_boxes(const airebo_ctx* c, int nsys, const int64_t* off, const double* 
   return 0;
 }
 
+// Whether every periodic side holds twice the LJ list cutoff plus twice the
+// skin (listed pairs never reach half a side before the next build).
+int minimum_image_ok(const airebo_ctx* c, const std::vector<SysBox>& hsys) {
+  double need = 2.0 * (c->P.rc_max + 2.0 * c->opt.skin);
+  for (const SysBox& B : hsys)
+    for (int d = 0; d < 3; ++d)
+      if (B.per[d] && B.L[d] < need) return 0;
+  return 1;
+}
+
 int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, const int32_t* pers, hipStream_t s,
           bool keep_md = false) {
   // any other use of the context ends an MD session: its captured step holds the buffers set up here
@@ -2364,7 +2519,8 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
     D.rlist2[p] = (P.rc[p] + c->opt.skin) * (P.rc[p] + c->opt.skin);
     D.rint2[p] = (P.R2[p] + c->opt.skin) * (P.R2[p] + c->opt.skin);
   }
-  if (c->lj_cap == 0) c->lj_cap = c->opt.lj_cap > 0 ? c->opt.lj_cap : 256;
+  if (c->lj_cap == 0) c->lj_cap = c->opt.lj_cap > 0 ? c->opt.lj_cap : 160;
+  if (c->lf_cap == 0) c->lf_cap = c->opt.lj_cap > 0 ? c->opt.lj_cap : 320;
   size_t N = (size_t)std::max<int64_t>(n, 1);
   int rc = 0;
   rc |= grow(c->x, c->cx, N);
@@ -2377,6 +2533,8 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   rc |= grow(c->cell_atoms, c->c_ca, N);
   rc |= grow(c->lj_n, c->c_ljn, N);
   rc |= grow(c->lj_e, c->c_lje, N * (size_t)c->lj_cap);
+  rc |= grow(c->lf_n, c->c_lfn, N);
+  rc |= grow(c->lf_e, c->c_lfe, N * (size_t)c->lf_cap);
   rc |= grow(c->in_n, c->c_inn, N);
   rc |= grow(c->in_e, c->c_ine, N * c->icap);
   rc |= grow(c->sn, c->c_sn, N);
@@ -2421,7 +2579,9 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   D.sys_acc = nsys > 1 ? c->sys_acc : nullptr;
   D.x = c->x; D.xref = c->xref; D.xsort = c->xsort; D.cell_of = c->cell_of; D.cell_count = c->cell_count; D.cell_start = c->cell_start;
   D.cell_cursor = c->cell_cursor; D.cell_atoms = c->cell_atoms; D.lj_cap = c->lj_cap; D.lj_n = c->lj_n;
-  D.lj_e = c->lj_e; D.in_n = c->in_n; D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
+  D.lj_e = c->lj_e; D.lf_cap = c->lf_cap; D.lf_n = c->lf_n; D.lf_e = c->lf_e; D.in_n = c->in_n;
+  D.rnear = P.r_conn + c->opt.skin;
+  D.minimg = minimum_image_ok(c, c->hsys); D.in_e = c->in_e; D.sn = c->sn; D.sj = c->sj; D.sd = c->sd; D.sw = c->sw;
   D.icap = c->icap;
   D.scap = c->scap;
   D.slog2 = 31 - __builtin_clz((unsigned)c->scap);
@@ -2458,49 +2618,76 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
   int sblk = c->opt.short_block ? c->opt.short_block : 1024;
   const int prec = c->opt.precision;
   const bool single = prec == AIREBO_SINGLE;
-  if (single) LAUNCH(c, K_SHORT, k_short<true>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), s, D, P);
-  else LAUNCH(c, K_SHORT, k_short<false>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), s, D, P);  // 16 lanes per atom
   int bblk = c->opt.bond_block ? c->opt.bond_block : 64;
   int nb = c->opt.bond_grid ? c->opt.bond_grid : std::min(blocks((int64_t)D.n * 2, bblk), 8192);
   int qblk = c->opt.defer_block ? c->opt.defer_block : 64;
-  bool bonded = mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION);
+  const bool bonded = mask & (AIREBO_TERM_REBO | AIREBO_TERM_TORSION);
+  const bool lj = mask & AIREBO_TERM_LJ;
   // arithmetic type R, accumulation type A: FP64 (double, double), mixed
   // (float, double), single (float, float)
   const bool morse = c->opt.vdw == AIREBO_VDW_MORSE;   // FP64 only (checked at context creation)
-  if (mask & AIREBO_TERM_LJ) {
+  auto far_pairs = [&](hipStream_t st) {
+    dim3 glf(blocks((int64_t)D.n * LJF_G, 256));
+    if (D.minimg) {
+      if (morse) LAUNCH(c, K_LJF, (k_ljf<double, double, true, true>), glf, dim3(256), st, D, P);
+      else if (prec == AIREBO_MIXED) LAUNCH(c, K_LJF, (k_ljf<float, double, false, true>), glf, dim3(256), st, D, P);
+      else if (single) LAUNCH(c, K_LJF, (k_ljf<float, float, false, true>), glf, dim3(256), st, D, P);
+      else LAUNCH(c, K_LJF, (k_ljf<double, double, false, true>), glf, dim3(256), st, D, P);
+    } else {
+      if (morse) LAUNCH(c, K_LJF, (k_ljf<double, double, true, false>), glf, dim3(256), st, D, P);
+      else if (prec == AIREBO_MIXED) LAUNCH(c, K_LJF, (k_ljf<float, double, false, false>), glf, dim3(256), st, D, P);
+      else if (single) LAUNCH(c, K_LJF, (k_ljf<float, float, false, false>), glf, dim3(256), st, D, P);
+      else LAUNCH(c, K_LJF, (k_ljf<double, double, false, false>), glf, dim3(256), st, D, P);
+    }
+  };
+  auto short_list = [&](hipStream_t st) {   // 16 lanes per atom
+    if (single) LAUNCH(c, K_SHORT, k_short<true>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), st, D, P);
+    else LAUNCH(c, K_SHORT, k_short<false>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), st, D, P);
+  };
+  auto near_pairs = [&](hipStream_t st) {
     dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
-    if (morse) LAUNCH(c, K_LJ, (k_lj<double, double, true>), glj, dim3(LJ_BLOCK), s, D, P);
-    else if (prec == AIREBO_MIXED) LAUNCH(c, K_LJ, (k_lj<float, double, false>), glj, dim3(LJ_BLOCK), s, D, P);
-    else if (single) LAUNCH(c, K_LJ, (k_lj<float, float, false>), glj, dim3(LJ_BLOCK), s, D, P);
-    else LAUNCH(c, K_LJ, (k_lj<double, double, false>), glj, dim3(LJ_BLOCK), s, D, P);
-  }
-  // The LJ kernel fills the device on its own (a wavefront per atom); the
-  // bonded kernel (a lane per bond) and the deferred b* pairs (a lane per
-  // pair) are both latency-bound at low occupancy, so they run side by side
-  // on two streams after it.  (The profiler's per-kernel events keep
-  // everything on one stream.)
-  bool fork = !c->prof && (mask & AIREBO_TERM_LJ) && bonded;
-  hipStream_t sb = s;
-  if (fork) {
-    (void)hipEventRecord(c->ev_fork, s);
-    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    sb = c->side;
-  }
-  if (bonded) {
-    if (prec == AIREBO_MIXED) LAUNCH(c, K_BOND, (k_bond<float, double>), dim3(nb), dim3(bblk), sb, D, P, mask);
-    else if (single) LAUNCH(c, K_BOND, (k_bond<float, float>), dim3(nb), dim3(bblk), sb, D, P, mask);
-    else LAUNCH(c, K_BOND, (k_bond<double, double>), dim3(nb), dim3(bblk), sb, D, P, mask);
-  }
-  if (mask & AIREBO_TERM_LJ) {
+    if (morse) LAUNCH(c, K_LJ, (k_lj<double, double, true>), glj, dim3(LJ_BLOCK), st, D, P);
+    else if (prec == AIREBO_MIXED) LAUNCH(c, K_LJ, (k_lj<float, double, false>), glj, dim3(LJ_BLOCK), st, D, P);
+    else if (single) LAUNCH(c, K_LJ, (k_lj<float, float, false>), glj, dim3(LJ_BLOCK), st, D, P);
+    else LAUNCH(c, K_LJ, (k_lj<double, double, false>), glj, dim3(LJ_BLOCK), st, D, P);
+  };
+  auto bond_terms = [&](hipStream_t st) {
+    if (prec == AIREBO_MIXED) LAUNCH(c, K_BOND, (k_bond<float, double>), dim3(nb), dim3(bblk), st, D, P, mask);
+    else if (single) LAUNCH(c, K_BOND, (k_bond<float, float>), dim3(nb), dim3(bblk), st, D, P, mask);
+    else LAUNCH(c, K_BOND, (k_bond<double, double>), dim3(nb), dim3(bblk), st, D, P, mask);
+  };
+  auto deferred_pairs = [&](hipStream_t st) {
     // one lane per expected deferred pair (about 3 per atom in dense melts), so
     // that the latency-bound b* work is spread over many wavefronts
     dim3 gq(std::min(blocks(4 * (int64_t)D.n, qblk), 16384));
-    if (morse) LAUNCH(c, K_BSTAR, (k_bstar<double, double, true>), gq, dim3(qblk), s, D, P);
-    else if (prec == AIREBO_MIXED) LAUNCH(c, K_BSTAR, (k_bstar<float, double, false>), gq, dim3(qblk), s, D, P);
-    else if (single) LAUNCH(c, K_BSTAR, (k_bstar<float, float, false>), gq, dim3(qblk), s, D, P);
-    else LAUNCH(c, K_BSTAR, (k_bstar<double, double, false>), gq, dim3(qblk), s, D, P);
+    if (morse) LAUNCH(c, K_BSTAR, (k_bstar<double, double, true>), gq, dim3(qblk), st, D, P);
+    else if (prec == AIREBO_MIXED) LAUNCH(c, K_BSTAR, (k_bstar<float, double, false>), gq, dim3(qblk), st, D, P);
+    else if (single) LAUNCH(c, K_BSTAR, (k_bstar<float, float, false>), gq, dim3(qblk), st, D, P);
+    else LAUNCH(c, K_BSTAR, (k_bstar<double, double, false>), gq, dim3(qblk), st, D, P);
+  };
+  // Two streams.  The main stream runs the short list, the near LJ pairs
+  // (they need the short list for the path maps) and the deferred pairs;
+  // after the near pairs the second stream runs the bonded terms and then
+  // the far LJ pairs beside them.  The latency-bound bonded and deferred
+  // kernels (one lane per bond or pair, one wavefront per SIMD) overlap each
+  // other and the far pairs; overlapping the near pairs slowed the step.
+  // (The profiler's per-kernel events keep everything on one stream.)
+  const bool two = !c->prof && lj && bonded;
+  if (!two) {
+    short_list(s);
+    if (lj) { near_pairs(s); far_pairs(s); }
+    if (bonded) bond_terms(s);
+    if (lj) deferred_pairs(s);
+  } else {
+    short_list(s);
+    near_pairs(s);
+    (void)hipEventRecord(c->ev_fork, s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    bond_terms(c->side);
+    far_pairs(c->side);
+    deferred_pairs(s);
   }
-  if (fork) {
+  if (two) {
     (void)hipEventRecord(c->ev_join, c->side);
     (void)hipStreamWaitEvent(s, c->ev_join, 0);
   }
@@ -2540,11 +2727,14 @@ int grow_caps(airebo_ctx* c, int flags) {
     if (c->icap >= ICAP_MAX) return 1;
     c->icap = std::min(2 * c->icap, ICAP_MAX);
   }
-  if (flags & F_OV_LJ) {
-    if (c->lj_cap >= (1 << 16)) return 1;
-    unsigned long long need = c->host_stats[S_MAXLJ] + c->host_stats[S_MAXLJ] / 4 + 32;
-    c->lj_cap = (int)std::min<unsigned long long>(std::max<unsigned long long>(need, c->lj_cap + c->lj_cap / 2 + 32),
-                                                  1u << 16);
+  if (flags & F_OV_LJ) {   // both parts of the LJ list
+    if (c->lj_cap >= (1 << 16) && c->lf_cap >= (1 << 16)) return 1;
+    auto up = [](int cap, unsigned long long mx) {
+      unsigned long long need = mx + mx / 4 + 32;
+      return (int)std::min<unsigned long long>(std::max<unsigned long long>(need, cap + cap / 2 + 32), 1u << 16);
+    };
+    c->lj_cap = up(c->lj_cap, c->host_stats[S_MAXLJ]);
+    c->lf_cap = up(c->lf_cap, c->host_stats[S_MAXLF]);
   }
   if (flags & F_OV_QUEUE) {
     if (c->q_per_atom >= 1024) return 1;
@@ -2582,6 +2772,8 @@ int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* box
     if (n > 0) {
       int g = std::min(blocks(n, 256), 1024);
       hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.lj_cap, D.stats + S_MAXLJ,
+                         D.stats + S_LJENT);
+      hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lf_n, (int)n, D.lf_cap, D.stats + S_MAXLF,
                          D.stats + S_LJENT);
     }
     HIPCHK(hipGetLastError());
@@ -2648,6 +2840,10 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
   D.cell_atoms = reinterpret_cast<int*>(base + L.cell_atoms);
   D.lj_n = reinterpret_cast<int*>(base + L.lj_n);
   D.lj_e = reinterpret_cast<unsigned*>(base + L.lj_e);
+  D.lf_n = reinterpret_cast<int*>(base + L.lf_n);
+  D.lf_e = reinterpret_cast<unsigned*>(base + L.lf_e);
+  D.rnear = P.r_conn + c->opt.skin;
+  D.minimg = minimum_image_ok(c, hsys);
   D.in_n = reinterpret_cast<int*>(base + L.in_n);
   D.in_e = reinterpret_cast<int*>(base + L.in_e);
   D.icap = ICAP;
@@ -2674,7 +2870,8 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
   D.step = reinterpret_cast<int*>(base + L.step);
   c->ncell = (int)ncell;
   const int64_t nn = std::max<int64_t>(n, 1);
-  D.lj_cap = (int)std::min<int64_t>(256, STATIC_LJ_ENTRIES / nn);
+  D.lj_cap = (int)std::min<int64_t>(160, STATIC_LJ_ENTRIES / nn);
+  D.lf_cap = (int)std::min<int64_t>(320, STATIC_LF_ENTRIES / nn);
   auto done = [&](int code) {
     c->D = saved;
     c->ncell = saved_ncell;
@@ -2700,9 +2897,12 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
       hipLaunchKernelGGL(k_zero, dim3(NSLOT * A_N / 256), dim3(256), 0, s, D);
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, energy, virial);
-    if (n > 0)
+    if (n > 0) {
       hipLaunchKernelGGL(k_max, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, (const int*)D.lj_n, (int)n,
                          D.lj_cap, D.stats + S_MAXLJ, D.stats + S_LJENT);
+      hipLaunchKernelGGL(k_max, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, (const int*)D.lf_n, (int)n,
+                         D.lf_cap, D.stats + S_MAXLF, D.stats + S_LJENT);
+    }
     int flags = 0;
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&flags, D.flags, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -2711,12 +2911,14 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return done(fail(AIREBO_E_DEVICE, std::string("static evaluation: ") + hipGetErrorString(e)));
     c->host_stats[S_REGROW] = (unsigned long long)attempt;
-    if (flags & F_OV_LJ) {   // a longer LJ row, if the area holds it
-      int64_t need = (int64_t)c->host_stats[S_MAXLJ] + 32;
-      if (need * nn > STATIC_LJ_ENTRIES)
-        return done(fail(AIREBO_E_CAPACITY, "LJ list of " + std::to_string(need) +
-                                                " entries per atom exceeds the static work area"));
+    if (flags & F_OV_LJ) {   // longer LJ rows, if the area holds them
+      int64_t need = (int64_t)c->host_stats[S_MAXLJ] + 32, needf = (int64_t)c->host_stats[S_MAXLF] + 32;
+      if (need * nn > STATIC_LJ_ENTRIES || needf * nn > STATIC_LF_ENTRIES)
+        return done(fail(AIREBO_E_CAPACITY, "LJ list of " + std::to_string(need) + " near and " +
+                                                std::to_string(needf) + " far entries per atom exceeds the static "
+                                                "work area"));
       D.lj_cap = (int)need;
+      D.lf_cap = (int)needf;
       continue;
     }
     if (flags & F_OV_QUEUE) return done(fail(AIREBO_E_CAPACITY, "deferred-pair queue exceeds the static work area"));
@@ -2841,9 +3043,12 @@ int md_begin_impl(airebo_ctx* c, int nsys, const int64_t* off, const double* box
   int rc = size();
   if (rc) return rc;
   // room for list growth between rebuilds
-  unsigned long long mx = c->host_stats[S_MAXLJ];
-  unsigned long long slack = c->opt.lj_slack > 0 ? (unsigned long long)c->opt.lj_slack : mx / 4 + 32;
-  c->lj_cap = (int)std::min<unsigned long long>(std::max<unsigned long long>(mx + slack, 1), 1u << 16);
+  auto sized = [&](unsigned long long mx) {
+    unsigned long long slack = c->opt.lj_slack > 0 ? (unsigned long long)c->opt.lj_slack : mx / 4 + 32;
+    return (int)std::min<unsigned long long>(std::max<unsigned long long>(mx + slack, 1), 1u << 16);
+  };
+  c->lj_cap = sized(c->host_stats[S_MAXLJ]);
+  c->lf_cap = sized(c->host_stats[S_MAXLF]);
   auto& md = c->md;
   md.nsys = nsys;
   md.off.assign(off, off + nsys + 1);

@@ -115,11 +115,28 @@ struct FarAcc {
   float e, f[3], W[6];
 };
 
+// Far-field pair term of one list entry beyond FAR0 and inside the LJ
+// cutoff (FP32 arithmetic on the FP64 pair vector): half the energy and
+// virial per side, the force on the centre.
+__device__ __forceinline__ void far_pair(const DevParams& P, int p, double r2, float dx, float dy, float dz, float r,
+                                         FarAcc& far) {
+  if (!(r2 > FAR0 * FAR0 && r2 < P.rc2[p])) return;
+  float V, dV, ds;
+  lj_pair<float>(P, p, r, V, dV);
+  float sw = 1.0f - Sw((r - (float)FAR0) * (float)(1.0 / (FAR1 - FAR0)), ds);
+  ds = -ds * (float)(1.0 / (FAR1 - FAR0));
+  float gr = (ds * V + sw * dV) * frcp(r);   // (dE_pair/dr) / r
+  far.e += 0.5f * sw * V;
+  far.f[0] += gr * dx; far.f[1] += gr * dy; far.f[2] += gr * dz;
+  far.W[0] -= 0.5f * gr * dx * dx; far.W[1] -= 0.5f * gr * dy * dy; far.W[2] -= 0.5f * gr * dz * dz;
+  far.W[3] -= 0.5f * gr * dx * dy; far.W[4] -= 0.5f * gr * dx * dz; far.W[5] -= 0.5f * gr * dy * dz;
+}
+
 // Stage the neighbours of atom i within RAD_CUT (image-resolved, from the LJ
-// list, in list order) in LDS, with the per-neighbour factors of the angular
-// terms.  One wavefront.  With a far-field accumulator, the same pass adds
-// the far-field pair term of every list entry beyond FAR0 (FP32 arithmetic on
-// the FP64 pair vector).
+// list's near part, in list order) in LDS, with the per-neighbour factors of
+// the angular terms.  One wavefront.  With a far-field accumulator, the same
+// pass adds the far-field pair term of every list entry beyond FAR0, and a
+// second pass that of every entry of the list's far part.
 __device__ void stage_nb(const Dev& D, int i, NbList& nb, const DevParams* P = nullptr, FarAcc* far = nullptr) {
   int lane = threadIdx.x & (WAVE - 1);
   unsigned long long below = lanes_below();
@@ -154,20 +171,7 @@ __device__ void stage_nb(const Dev& D, int i, NbList& nb, const DevParams* P = n
       oka = r2 < (double)ANG_CUT * ANG_CUT;
       dx = (float)ddx; dy = (float)ddy; dz = (float)ddz; r = (float)sqrt(r2);
       sj = __double2int_rn(xj.w) == 0 ? 0 : 1;   // invalid codes are reported by k_load
-      if (far) {
-        int p = si + sj;
-        if (r2 > FAR0 * FAR0 && r2 < P->rc2[p]) {
-          float V, dV, ds;
-          lj_pair<float>(*P, p, r, V, dV);
-          float sw = 1.0f - Sw((r - (float)FAR0) * (float)(1.0 / (FAR1 - FAR0)), ds);
-          ds = -ds * (float)(1.0 / (FAR1 - FAR0));
-          float gr = (ds * V + sw * dV) * frcp(r);   // (dE_pair/dr) / r
-          far->e += 0.5f * sw * V;
-          far->f[0] += gr * dx; far->f[1] += gr * dy; far->f[2] += gr * dz;
-          far->W[0] -= 0.5f * gr * dx * dx; far->W[1] -= 0.5f * gr * dy * dy; far->W[2] -= 0.5f * gr * dz * dz;
-          far->W[3] -= 0.5f * gr * dx * dy; far->W[4] -= 0.5f * gr * dx * dz; far->W[5] -= 0.5f * gr * dy * dz;
-        }
-      }
+      if (far) far_pair(*P, si + sj, r2, dx, dy, dz, r, *far);
     }
     unsigned long long m = __ballot(ok);
     unsigned long long ma = __ballot(oka);
@@ -194,6 +198,22 @@ __device__ void stage_nb(const Dev& D, int i, NbList& nb, const DevParams* P = n
     }
     cnt += __popcll(m);
     cna += __popcll(ma);
+  }
+  // the far part of the LJ list (beyond 3 max R2 > RAD_CUT): far field only
+  if (far) {
+    const int nf = min(D.lf_n[i], D.lf_cap);
+    const unsigned* lf = D.lf_e + (size_t)i * D.lf_cap;
+    for (int e = lane; e < nf; e += WAVE) {
+      unsigned ent = lf[e];
+      double4 xj = D.x[ent & 0x7FFFFFFu];
+      int code = (int)(ent >> 27);
+      double ddx = xj.x - xi.x + (code / 9 - 1) * B.L[0];
+      double ddy = xj.y - xi.y + ((code / 3) % 3 - 1) * B.L[1];
+      double ddz = xj.z - xi.z + (code % 3 - 1) * B.L[2];
+      double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+      int sj = __double2int_rn(xj.w) == 0 ? 0 : 1;
+      far_pair(*P, si + sj, r2, (float)ddx, (float)ddy, (float)ddz, (float)sqrt(r2), *far);
+    }
   }
   if (lane == 0) {
     if (cnt > MAXNB || cna > MAXANG) atomicOr(D.flags, F_OV_NN);
@@ -1277,6 +1297,8 @@ int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species,
     launch_rebuild(c, s);
     int g = std::min(blocks(n, 256), 1024);
     hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.lj_cap, D.stats + S_MAXLJ,
+                       D.stats + S_LJENT);
+    hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lf_n, (int)n, D.lf_cap, D.stats + S_MAXLF,
                        D.stats + S_LJENT);
     rc = body(D);
     if (rc) return rc;
