@@ -195,6 +195,48 @@ def atom_energies(nets, norm, G, s):
     return E
 
 
+def bf16(t):
+    """Round to BF16 (through FP32, nearest even) and back to FP64."""
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def dsilu(a):
+    sg = torch.sigmoid(a)
+    return sg * (1 + a * (1 - sg))
+
+
+def atom_energies_bf16(nets, norm, G, s):
+    """Per-atom energies and dE/dG of one ensemble member with every
+    matrix-product operand rounded to BF16, as the matrix-core networks take
+    them: the normalised descriptors, the weights W1..W3, the hidden
+    activations, and on the input-gradient chain the gradients with respect
+    to the pre-activations (dE/da3 = w4 s'(a3), then dE/da2, dE/da1) and the
+    weights again.  Biases, w4 and the SiLU arithmetic are unrounded; sums
+    are exact (FP64 here, FP32 on the matrix cores).  Written out without
+    autograd: gh_k = dE/dh_k, ga_k = dE/da_k.  Returns (E [n], dEdG [n, 112])."""
+    mean, istd, scale, shift = norm
+    s = torch.as_tensor(np.asarray(s), dtype=torch.long)
+    istd_t = torch.as_tensor(istd, dtype=torch.float64)
+    x = bf16((G - torch.as_tensor(mean, dtype=torch.float64)) * istd_t)
+    E = torch.zeros(G.shape[0], dtype=torch.float64)
+    dEdG = torch.zeros_like(G)
+    for sp in range(2):
+        rows = torch.nonzero(s == sp).flatten()
+        if len(rows) == 0:
+            continue
+        p = nets[sp]
+        W1, W2, W3 = bf16(p["W1"]), bf16(p["W2"]), bf16(p["W3"])
+        a1 = x[rows] @ W1.T + p["b1"]
+        a2 = bf16(silu(a1)) @ W2.T + p["b2"]
+        a3 = bf16(silu(a2)) @ W3.T + p["b3"]
+        E[rows] = scale * (silu(a3) @ p["w4"] + p["b4"][0]) + shift[sp]
+        ga3 = p["w4"] * dsilu(a3)
+        ga2 = (bf16(ga3) @ W3) * dsilu(a2)
+        ga1 = (bf16(ga2) @ W2) * dsilu(a1)
+        dEdG[rows] = (bf16(ga1) @ W1) * scale * istd_t
+    return E, dEdG
+
+
 def far_energy_from_pairs(s, I, J, d, lj):
     """Sum over ordered pairs / 2 of s_f(r) V_LJ(r) S_cut(r)."""
     sig, eps, rc, sw = lj
@@ -231,13 +273,15 @@ class Model:
         return (self.mean, self.istd, self.scale, self.shift)
 
 
-def evaluate(model, x, s, box, per, lj=None, want_virial=False):
+def evaluate(model, x, s, box, per, lj=None, want_virial=False, bf16_operands=False):
     """Per-member network energies and forces, far field, ensemble mean.
 
     Returns a dict with E_nn [nm], F_nn [nm, n, 3], E_far, F_far [n, 3],
     E_atom [nm, n], dEdG [nm, n, 112], and optionally the virial [6] of the
     ensemble-mean NN part plus the far field (W_ab = -dE/d eps_ab under
-    d -> (I + eps) d of every pair vector), as numpy float64."""
+    d -> (I + eps) d of every pair vector), as numpy float64.  With
+    bf16_operands the networks are those of atom_energies_bf16 (forces are
+    still the exact descriptor derivative applied to their dE/dG)."""
     lj = lj or lj_params()
     n = len(s)
     x = torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
@@ -252,8 +296,12 @@ def evaluate(model, x, s, box, per, lj=None, want_virial=False):
     e_mean = 0.0
     for m in range(model.nm):
         nets = unpack(model.params[m])
-        Ea = atom_energies(nets, model.norm(), Gl, s)
-        dEdG, = torch.autograd.grad(Ea.sum(), Gl)
+        if bf16_operands:
+            with torch.no_grad():
+                Ea, dEdG = atom_energies_bf16(nets, model.norm(), G.detach(), s)
+        else:
+            Ea = atom_energies(nets, model.norm(), Gl, s)
+            dEdG, = torch.autograd.grad(Ea.sum(), Gl)
         E = (G * dEdG).sum()          # same gradient as sum(Ea) through G
         F, = torch.autograd.grad(E, x, retain_graph=True)
         out["E_nn"].append(Ea.sum().item())
@@ -325,4 +373,110 @@ def loss_and_grad(model, x, s, box, per, f_ref, e_ref, w_force, w_energy, lj=Non
         g, = torch.autograd.grad(L, flat)
         losses.append(L.item())
         grads.append(g.numpy())
+    return np.array(losses), np.array(grads)
+
+
+def loss_and_grad_bf16(model, x, s, box, per, f_ref, e_ref, w_force, w_energy, lj=None):
+    """loss_and_grad with the networks of atom_energies_bf16 and the weight
+    gradient written out through the same BF16 operand rounding as the
+    matrix-core training chain.  The gradient of
+
+      L_m = w_force sum_a |F_m,a - t_a|^2 + w_energy (E_m + E_far - e_ref)^2,
+      F_m,a = -sum_(i,f) dE/dG_if dG_if/dx_a,  t = f_ref - F_far,
+
+    is sum_(i,f) u_if d(dE/dG_if)/dtheta + e_adj dE_m/dtheta with
+    u = (dG/dx) w, w_a = -2 w_force (F_m,a - t_a) (a descriptor JVP, exact
+    here) and e_adj = 2 w_energy (E_m + E_far - e_ref).  Per atom, with
+    un = u scale istd, x the normalised descriptors, h_k = s(a_k), gh_k and
+    ga_k = dE/dh_k, dE/da_k of atom_energies_bf16 and s', s'' the SiLU
+    derivatives, the tangent of the input gradient along un and its adjoint:
+
+      q1 = W1 un,  p1 = s'(a1) q1,  q2 = W2 p1,  p2 = s'(a2) q2,  q3 = W3 p2
+      r1 = q1 gh1 s''(a1),  r2 = q2 gh2 s''(a2)
+      A3 = e_adj scale ga3 + q3 w4 s''(a3)
+      A2 = (W3^T A3) s'(a2) + r2,  A1 = (W2^T A2) s'(a1) + r1
+      dW1 = A1 x^T + ga1 un^T,  dW2 = A2 h1^T + ga2 p1^T,  dW3 = A3 h2^T + ga3 p2^T
+      db_k = A_k,  dw4 = e_adj scale h3 + s'(a3) q3,  db4 = e_adj scale
+
+    summed over atoms.  The operands of the products with W (un, p1, p2, A3,
+    A2) and the weights are rounded to BF16; the outer products take
+    unrounded values.  Returns (loss [nm], grad [nm, 2, NPAR])."""
+    lj = lj or lj_params()
+    n = len(s)
+    xt = torch.as_tensor(np.asarray(x, dtype=np.float64)).clone().requires_grad_(True)
+    I, J, d = pair_vectors(xt, box, per, max(RAD_CUT, max(lj[2])))
+    r = torch.sqrt((d.detach() * d.detach()).sum(1))
+    near = torch.nonzero(r < RAD_CUT).flatten()
+    G = descriptors_from_pairs(n, s, I[near], J[near], d[near])
+    ef = far_energy_from_pairs(s, I, J, d, lj)
+    Ff = -torch.autograd.grad(ef, xt, retain_graph=True)[0].detach()
+    target = torch.as_tensor(np.asarray(f_ref, dtype=np.float64)) - Ff
+    mean, istd, scale, shift = model.norm()
+    istd_t = torch.as_tensor(istd, dtype=torch.float64)
+    Gd = G.detach()
+    xn = (Gd - torch.as_tensor(mean, dtype=torch.float64)) * istd_t
+    sl = torch.as_tensor(np.asarray(s), dtype=torch.long)
+
+    def d2silu(a):
+        sg = torch.sigmoid(a)
+        return sg * (1 - sg) * (2 + a * (1 - 2 * sg))
+
+    losses, grads = [], []
+    for m in range(model.nm):
+        nets = unpack(model.params[m])
+        with torch.no_grad():
+            Ea, dEdG = atom_energies_bf16(nets, model.norm(), Gd, s)
+        F = -torch.autograd.grad((G * dEdG).sum(), xt, retain_graph=True)[0]
+        res = (F - target).detach()
+        E = Ea.sum()
+        L = w_force * (res ** 2).sum() + w_energy * (E + ef.detach() - e_ref) ** 2
+        w = -2.0 * w_force * res
+        _, u = torch.autograd.functional.jvp(
+            lambda y: descriptors_from_pairs(n, s, *pair_vectors(y, box, per, RAD_CUT)),
+            xt.detach(), w)
+        un = u * scale * istd_t
+        e_adj = (2.0 * w_energy * (E + ef.detach() - e_ref)).item() * scale
+        g = np.zeros((2, NPAR))
+        with torch.no_grad():
+            for sp in range(2):
+                rows = torch.nonzero(sl == sp).flatten()
+                if len(rows) == 0:
+                    continue
+                p = nets[sp]
+                W1, W2, W3 = bf16(p["W1"]), bf16(p["W2"]), bf16(p["W3"])
+                x0 = bf16(xn[rows])
+                a1 = x0 @ W1.T + p["b1"]
+                h1 = silu(a1)
+                a2 = bf16(h1) @ W2.T + p["b2"]
+                h2 = silu(a2)
+                a3 = bf16(h2) @ W3.T + p["b3"]
+                h3 = silu(a3)
+                ga3 = p["w4"] * dsilu(a3)
+                gh2 = bf16(ga3) @ W3
+                ga2 = gh2 * dsilu(a2)
+                gh1 = bf16(ga2) @ W2
+                ga1 = gh1 * dsilu(a1)
+                u0 = un[rows]
+                q1 = bf16(u0) @ W1.T
+                p1 = q1 * dsilu(a1)
+                r1 = q1 * gh1 * d2silu(a1)
+                q2 = bf16(p1) @ W2.T
+                p2 = q2 * dsilu(a2)
+                r2 = q2 * gh2 * d2silu(a2)
+                q3 = bf16(p2) @ W3.T
+                A3 = e_adj * ga3 + q3 * p["w4"] * d2silu(a3)
+                A2 = (bf16(A3) @ W3) * dsilu(a2) + r2
+                A1 = (bf16(A2) @ W2) * dsilu(a1) + r1
+                blocks = {"W1": A1.T @ xn[rows] + ga1.T @ u0, "b1": A1.sum(0),
+                          "W2": A2.T @ h1 + ga2.T @ p1, "b2": A2.sum(0),
+                          "W3": A3.T @ h2 + ga3.T @ p2, "b3": A3.sum(0),
+                          "w4": (e_adj * h3 + dsilu(a3) * q3).sum(0),
+                          "b4": torch.full((1,), e_adj * len(rows), dtype=torch.float64)}
+                off = 0
+                for name, shape in LAYOUT:
+                    k = int(np.prod(shape))
+                    g[sp, off:off + k] = blocks[name].reshape(-1).numpy()
+                    off += k
+        losses.append(L.item())
+        grads.append(g)
     return np.array(losses), np.array(grads)

@@ -223,3 +223,46 @@ def test_loss_gradient_fd():
                               LJ)[0][m]
         fd = (Lp - Lm) / (2 * h)
         assert g[m, sp, k] == pytest.approx(fd, rel=2e-5, abs=1e-6 * max(1.0, abs(L[m])))
+
+
+def test_bf16_chain_is_the_exact_derivative_without_rounding(monkeypatch):
+    """atom_energies_bf16 writes the input gradient out by hand; with the BF16
+    rounding switched off it must equal the plain network and autograd's
+    dE/dG, and with it on it must stay within the BF16 rounding of them."""
+    import torch
+    x, s, box, per = cluster(periodic=True)
+    w, mean, istd, scale, shift = model_arrays(2, 9, 1.0)
+    M = sr.Model(w, mean, istd, scale, shift)
+    G = sr.descriptors(x, s, box, per)
+    for m in range(2):
+        nets = sr.unpack(M.params[m])
+        Gl = G.clone().requires_grad_(True)
+        E = sr.atom_energies(nets, M.norm(), Gl, s)
+        dEdG, = torch.autograd.grad(E.sum(), Gl)
+        Eb, dEb = sr.atom_energies_bf16(nets, M.norm(), G, s)
+        assert np.abs(Eb.numpy() - E.detach().numpy()).max() <= 2e-2 * np.abs(E.detach().numpy()).max()
+        assert np.abs(dEb.numpy() - dEdG.numpy()).max() <= 2e-2 * np.abs(dEdG.numpy()).max()
+        with monkeypatch.context() as mp:
+            mp.setattr(sr, "bf16", lambda t: t)
+            E0, dE0 = sr.atom_energies_bf16(nets, M.norm(), G, s)
+        assert np.abs(E0.numpy() - E.detach().numpy()).max() <= 1e-12 * np.abs(E.detach().numpy()).max()
+        assert np.abs(dE0.numpy() - dEdG.numpy()).max() <= 1e-12 * np.abs(dEdG.numpy()).max()
+
+
+def test_bf16_training_chain_without_rounding_is_autograd(monkeypatch):
+    """loss_and_grad_bf16 writes the double backward out by hand; with the
+    BF16 rounding switched off it equals torch's double backward of the
+    plain definition (loss_and_grad)."""
+    x, s, box, per = cluster(periodic=True)
+    w, mean, istd, scale, shift = model_arrays(2, 13, 1.0)
+    M = sr.Model(w, mean, istd, scale, shift)
+    rng = np.random.default_rng(17)
+    f_ref = rng.normal(0, 1.0, (len(s), 3))
+    L, g = sr.loss_and_grad(M, x, s, box, per, f_ref, -40.0, 0.25, 0.01)
+    with monkeypatch.context() as mp:
+        mp.setattr(sr, "bf16", lambda t: t)
+        L0, g0 = sr.loss_and_grad_bf16(M, x, s, box, per, f_ref, -40.0, 0.25, 0.01)
+    assert np.allclose(L0, L, rtol=1e-10)
+    assert np.abs(g0 - g).max() <= 1e-9 * np.abs(g).max()
+    Lb, gb = sr.loss_and_grad_bf16(M, x, s, box, per, f_ref, -40.0, 0.25, 0.01)
+    assert np.linalg.norm(gb - g) <= 5e-2 * np.linalg.norm(g)
