@@ -95,9 +95,9 @@ typedef struct {
   int32_t lj_cap;      /* LJ list entries per atom; 0 = automatic (grows on demand)   */
   int32_t device;      /* HIP device ordinal (default 0)                              */
   /* launch shapes (0 = default); chosen by the autotuner for a workload class */
-  int32_t bond_block;  /* threads per block of the bonded kernel: 64, 128 or 256 (64)  */
+  int32_t bond_block;  /* threads per block of the bonded kernel: 0 or 64 (64)         */
   int32_t bond_grid;   /* blocks of the bonded kernel's persistent grid (auto)        */
-  int32_t defer_block; /* threads per block of the deferred-pair kernel: 64..256 (64) */
+  int32_t defer_block; /* threads per block of the deferred-pair kernel: 0 or 64 (64) */
   int32_t short_block; /* threads per block of the short-list kernel: 256, 512, 1024 (1024) */
   int32_t vdw;         /* AIREBO_VDW_LJ (default) or AIREBO_VDW_MORSE (AIREBO-M)      */
   int32_t lj_slack;    /* LJ list entries per atom kept free beyond the largest row when an

@@ -1,6 +1,7 @@
 """Launch-shape autotuner for the AIREBO kernels.
 
-Tunables (airebo_options): threads per block of the bonded kernel, the size
+Tunables (airebo_options): threads per block of the bonded kernel (one
+wavefront: its LDS stage is sized for 64 threads), the size
 of its persistent grid, threads per block of the deferred-pair kernel and of
 the short-list kernel.  Tuning is a coordinate search: starting from the
 defaults, each tunable in turn is swept over its candidates with the others
@@ -18,9 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tune_cache.json")
 
 CANDIDATES = {
-    "bond_block": [64, 128, 256],
+    "bond_block": [64],
     "bond_grid": [0, 256, 512, 1024, 2048, 4096],
-    "defer_block": [64, 128, 256],
+    "defer_block": [64],
     "short_block": [256, 512, 1024],
 }
 

@@ -176,6 +176,24 @@ __device__ __forceinline__ float xexp(float a) { return expf(a); }
 __device__ __forceinline__ void xsincospi(double a, double* s, double* c) { sincospi(a, s, c); }
 __device__ __forceinline__ void xsincospi(float a, float* s, float* c) { sincospif(a, s, c); }
 
+// FP64 reciprocal and reciprocal square root: the hardware estimate refined
+// by one Newton-Raphson step, which doubles its correct bits; the result is
+// within a few ulp of the correctly rounded value at a fraction of the cost
+// (and of the dependent latency) of the IEEE division and square root
+// sequences.  FP32 keeps the compiler's operations.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);   // y <- y (1 + e / 2), e = 1 - x y^2
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rcp_nr(float x) { return 1.0f / x; }
+__device__ __forceinline__ float rsq_nr(float x) { return 1.0f / sqrtf(x); }
+
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
@@ -213,7 +231,7 @@ __device__ __forceinline__ R cosstep(R x, double lo, double hi, R& d) {
 template <typename R>
 __device__ __forceinline__ R guard(const DevParams& P, R c, R& d) {
   R a = c < (R)0 ? -c : c;
-  R inv = (R)(1.0 / (P.guard_off - P.guard_on));
+  R inv = (R)P.inv_guard;
   R ds;
   R s = Sw((a - (R)P.guard_on) * inv, ds);
   d = ds * inv * (c < (R)0 ? (R)-1 : (R)1);
@@ -481,9 +499,113 @@ __device__ __forceinline__ V3<R> nbr_vec(const Dev& D, int a, int q, R& r) {
 }
 
 // ---------------------------------------------------------------------------
-// Bond order b_ij (Sec. 2.1.3).  One end at a time: centre c with partner o
-// along r_co.  With bstar, r_ij is replaced by R1_ij where a bond length i-j
-// enters (the lambda exponent); directions are kept.
+// Neighbourhood of one bond (or deferred pair) i-j staged in LDS.  The
+// bond-order passes (both ends forward, the dihedral loops, both ends
+// reverse, the torsion) visit the short lists of i and j several times; read
+// from memory each visit costs two dependent round trips per neighbour
+// (list entry, then the neighbour's species and N).  The stage issues all of
+// them at once per bond, so that a lane's dependent chain holds two round
+// trips instead of about a hundred.  The first NB neighbours of each end are
+// staged (every atom of a hydrocarbon at ordinary conditions); further ones
+// are read from memory.  Layout [slot][thread] (slot = end * NB + q), so
+// that a wavefront's accesses are consecutive.
+// ---------------------------------------------------------------------------
+constexpr int NB = 4;
+template <typename R> struct alignas(4 * sizeof(R)) Q4 { R x, y, z, w; };
+template <typename R> struct alignas(2 * sizeof(R)) Q2 { R x, y; };
+
+// Bytes of the stage per thread.
+template <typename R>
+constexpr int stage_bytes() { return 2 * NB * (int)(sizeof(Q4<R>) + sizeof(Q2<R>) + sizeof(R) + sizeof(int)); }
+
+// One neighbour k of an end centre c: its index and species, r_ck and its
+// length, w_ck and dw/dr, and N_k (all neighbours of k, weighted).
+template <typename R>
+struct Nb {
+  int k, s;
+  V3<R> d;
+  R r, w, dw, nt;
+};
+
+template <typename R>
+struct Stage {
+  Q4<R>* d;    // r_ck, |r_ck|
+  Q2<R>* w;    // w_ck, dw_ck/dr
+  R* nt;       // N_k
+  int* ks;     // 2 k + species of k
+  int T, t;             // threads of the block, this thread
+  int c0, c1, n0, n1;   // end centres i, j and their list lengths
+  __device__ int len(int e) const { return e ? n1 : n0; }
+  __device__ void init(unsigned char* base) {
+    T = blockDim.x;
+    t = threadIdx.x;
+    d = reinterpret_cast<Q4<R>*>(base);
+    w = reinterpret_cast<Q2<R>*>(d + 2 * NB * T);
+    nt = reinterpret_cast<R*>(w + 2 * NB * T);
+    ks = reinterpret_cast<int*>(nt + 2 * NB * T);
+  }
+  // Stage the lists of i and j.
+  __device__ void fill(const Dev& D, int i, int j) {
+    c0 = i; c1 = j;
+    n0 = D.sn[i]; n1 = D.sn[j];
+    int kk[2 * NB];
+#pragma unroll
+    for (int u = 0; u < 2 * NB; ++u) {
+      const int e = u / NB, q = u % NB;
+      kk[u] = -1;
+      if (q < (e ? n1 : n0)) {
+        const int idx = (e ? c1 : c0) * D.scap + q;
+        kk[u] = D.sj[idx];
+        const double4 a = D.sd[idx];
+        const double2 b = D.sw[idx];
+        d[u * T + t] = {(R)a.x, (R)a.y, (R)a.z, (R)a.w};
+        w[u * T + t] = {(R)b.x, (R)b.y};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * NB; ++u) {
+      const int k = kk[u];
+      if (k >= 0) {
+        ks[u * T + t] = 2 * k + __double2int_rn(D.x[k].w);
+        nt[u * T + t] = (R)(D.NCt[k] + D.NHt[k]);
+      }
+    }
+  }
+  // Neighbour q of end e (0: i, 1: j).
+  __device__ Nb<R> get(const Dev& D, int e, int q) const {
+    Nb<R> b;
+    if (q < NB) {
+      const int u = (e * NB + q) * T + t;
+      const Q4<R> a = d[u];
+      const Q2<R> v = w[u];
+      const int x = ks[u];
+      b.k = x >> 1;
+      b.s = x & 1;
+      b.d = {a.x, a.y, a.z};
+      b.r = a.w;
+      b.w = v.x;
+      b.dw = v.y;
+      b.nt = nt[u];
+    } else {
+      const int idx = (e ? c1 : c0) * D.scap + q;
+      b.k = D.sj[idx];
+      const double4 a = D.sd[idx];
+      const double2 v = D.sw[idx];
+      b.s = __double2int_rn(D.x[b.k].w);
+      b.d = {(R)a.x, (R)a.y, (R)a.z};
+      b.r = (R)a.w;
+      b.w = (R)v.x;
+      b.dw = (R)v.y;
+      b.nt = (R)(D.NCt[b.k] + D.NHt[b.k]);
+    }
+    return b;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Bond order b_ij (Sec. 2.1.3).  One end at a time: end e (0: i, 1: j),
+// centre c with partner o along r_co.  With bstar, r_ij is replaced by R1_ij
+// where a bond length i-j enters (the lambda exponent); directions are kept.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct EndF {
@@ -491,26 +613,25 @@ struct EndF {
 };
 
 template <typename R>
-__device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, int so, V3<R> rco, R rlen, R rlam,
-                        EndF<R>& e, int* st) {
-  int n = D.sn[c];
+__device__ void end_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG, int ee, int sc, int o, int so, V3<R> rco,
+                        R rlen, R rlam, EndF<R>& e, int* st) {
+  const int n = SG.len(ee);
   R NC = 0, NH = 0;
   for (int q = 0; q < n; ++q) {
-    int k = D.sj[c * D.scap + q];
-    if (k == o) continue;
-    R w = (R)D.sw[c * D.scap + q].x;
-    if (__double2int_rn(D.x[k].w) == 0) NC += w; else NH += w;
+    const Nb<R> b = SG.get(D, ee, q);
+    if (b.k == o) continue;
+    if (b.s == 0) NC += b.w; else NH += b.w;
   }
   R N = NC + NH;
   R S = 0, conj = 0, SdN = 0;
+  const R irlen = rcp_nr(rlen);
   for (int q = 0; q < n; ++q) {
-    int k = D.sj[c * D.scap + q];
-    if (k == o) continue;
-    int sk = __double2int_rn(D.x[k].w);
-    R r;
-    V3<R> d = nbr_vec<R>(D, c, q, r);
-    R w = (R)D.sw[c * D.scap + q].x;
-    R cth = dot(rco, d) / (rlen * r);
+    const Nb<R> b = SG.get(D, ee, q);
+    if (b.k == o) continue;
+    const int sk = b.s;
+    const R r = b.r, w = b.w;
+    const V3<R> d = b.d;
+    R cth = dot(rco, d) * (irlen * rcp_nr(r));
     R dgc, dgN;
     R g = gfun(P, sc, cth, N, dgc, dgN, st);
     R el = 1;
@@ -518,7 +639,7 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
     S += w * g * el;
     SdN += w * el * dgN;
     if (sk == 0) {
-      R xk = (R)(D.NCt[k] + D.NHt[k]) - w;
+      R xk = b.nt - w;
       R dF;
       conj += w * cosstep(xk, P.conj_lo, P.conj_hi, dF);
     }
@@ -526,7 +647,7 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
   R Pv = 0, dPC = 0, dPH = 0;
   if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH, st, P.knot_delta);
   e.NC = NC; e.NH = NH; e.N = N; e.S = S; e.P = Pv; e.dPC = dPC; e.dPH = dPH;
-  e.p = (R)1 / xsqrt((R)1 + S + Pv);
+  e.p = rsq_nr((R)1 + S + Pv);
   e.conj = conj;
   e.SdN = SdN;
 }
@@ -534,22 +655,24 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, int c, int sc, int o, 
 // Reverse pass of one end.  Gp = dE/dp, GN = dE/dN_co from outside the end,
 // Gconj = dE/d(conjugation sum of this end).  Returns dE/dr_co in gco.
 template <typename R, typename AC>
-__device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, int so, V3<R> rco, R rlen, R rlam,
-                        bool bstar, const EndF<R>& e, R Gp, R GN, R Gconj, V3<R>& gco, AC& acc) {
-  int n = D.sn[c];
+__device__ void end_rev(const DevParams& P, const Dev& D, const Stage<R>& SG, int ee, int c, int sc, int o, int so,
+                        V3<R> rco, R rlen, R rlam, bool bstar, const EndF<R>& e, R Gp, R GN, R Gconj, V3<R>& gco,
+                        AC& acc) {
+  const int n = SG.len(ee);
   R GS = (R)-0.5 * e.p * e.p * e.p * Gp;
   R GNt = GN + GS * e.SdN;
   R GNC = GS * e.dPC + GNt, GNH = GS * e.dPH + GNt;
   R Grlen = 0;
+  const R irlen = rcp_nr(rlen);
   for (int q = 0; q < n; ++q) {
-    int k = D.sj[c * D.scap + q];
+    const Nb<R> b = SG.get(D, ee, q);
+    const int k = b.k;
     if (k == o) continue;
-    int sk = __double2int_rn(D.x[k].w);
-    R r;
-    V3<R> d = nbr_vec<R>(D, c, q, r);
-    double2 wd = D.sw[c * D.scap + q];
-    R w = (R)wd.x, dw = (R)wd.y;
-    R inv = (R)1 / (rlen * r);
+    const int sk = b.s;
+    const R r = b.r, w = b.w, dw = b.dw;
+    const V3<R> d = b.d;
+    const R ir = rcp_nr(r);
+    R inv = irlen * ir;
     R cth = dot(rco, d) * inv;
     R dgc, dgN;
     R g = gfun(P, sc, cth, e.N, dgc, dgN, acc.st);
@@ -564,7 +687,7 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
     R Gw = GS * g * el + (sk == 0 ? GNC : GNH);
     R Gcos = GS * w * el * dgc;
     if (sk == 0) {
-      R xk = (R)(D.NCt[k] + D.NHt[k]) - w;
+      R xk = b.nt - w;
       R dF;
       R Fv = cosstep(xk, P.conj_lo, P.conj_hi, dF);
       Gw += Gconj * Fv;
@@ -577,16 +700,16 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
           R rm;
           V3<R> dm = nbr_vec<R>(D, k, u, rm);
           R dwm = (R)D.sw[k * D.scap + u].y;
-          if (dwm != (R)0) acc.vec(k, m, dm, (Gx * dwm / rm) * dm);
+          if (dwm != (R)0) acc.vec(k, m, dm, (Gx * dwm * rcp_nr(rm)) * dm);
         }
       }
     }
     Gr += Gw * dw;
-    V3<R> gk = (Gr / r) * d + Gcos * (inv * rco - (cth / (r * r)) * d);
-    gco = gco + Gcos * (inv * d - (cth / (rlen * rlen)) * rco);
+    V3<R> gk = (Gr * ir) * d + Gcos * (inv * rco - (cth * ir * ir) * d);
+    gco = gco + Gcos * (inv * d - (cth * irlen * irlen) * rco);
     acc.vec(c, k, d, gk);
   }
-  gco = gco + (Grlen / rlen) * rco;
+  gco = gco + (Grlen * irlen) * rco;
 }
 
 // Dihedral loop over k in N(i)\{j}, l in N(j)\{i,k} of a C-C bond: forward
@@ -594,46 +717,48 @@ __device__ void end_rev(const DevParams& P, const Dev& D, int c, int sc, int o, 
 // energy w_ik w_ij w_jl s_i s_j V(omega); with rev, the reverse pass given
 // GSdh = dE/d(sum) and the torsion's own derivatives.
 template <typename R, typename AC>
-__device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, R wij, bool tors, bool rev,
-                         R GSdh, R& Sdh, R& Et, V3<R>& gij, R& Gwij, AC& acc) {
-  int ni = D.sn[i], nj = D.sn[j];
+__device__ void dihedral(const DevParams& P, const Dev& D, const Stage<R>& SG, int i, int j, V3<R> rij, R r, R wij,
+                         bool tors, bool rev, R GSdh, R& Sdh, R& Et, V3<R>& gij, R& Gwij, AC& acc) {
+  const int ni = SG.n0, nj = SG.n1;
   V3<R> rji = -rij;
+  const R ir = rcp_nr(r);
   for (int q = 0; q < ni; ++q) {
-    int k = D.sj[i * D.scap + q];
+    const Nb<R> bk = SG.get(D, 0, q);
+    const int k = bk.k;
     if (k == j) continue;
-    R rik_l;
-    V3<R> rik = nbr_vec<R>(D, i, q, rik_l);
-    double2 wdk = D.sw[i * D.scap + q];
-    R wik = (R)wdk.x, dwik = (R)wdk.y;
-    R ci = dot(rij, rik) / (r * rik_l);
+    const R rik_l = bk.r, wik = bk.w, dwik = bk.dw;
+    const V3<R> rik = bk.d;
+    const R irik = rcp_nr(rik_l);
+    R ci = dot(rij, rik) * (ir * irik);
     R dgi;
     R gi = guard(P, ci, dgi);
     if (gi == (R)0) continue;
     V3<R> a = cross(rij, rik);
     R na2 = dot(a, a);
-    int sk = __double2int_rn(D.x[k].w);
+    const R ina = rsq_nr(na2);   // |a| > 0: the guard vanishes for collinear bonds
+    const int sk = bk.s;
     V3<R> gik_sum = {0, 0, 0};   // dE/dr_ik summed over l (one force update per k)
     for (int u = 0; u < nj; ++u) {
-      int l = D.sj[j * D.scap + u];
+      const Nb<R> bl = SG.get(D, 1, u);
+      const int l = bl.k;
       if (l == i || l == k) continue;
-      R rjl_l;
-      V3<R> rjl = nbr_vec<R>(D, j, u, rjl_l);
-      double2 wdl = D.sw[j * D.scap + u];
-      R wjl = (R)wdl.x, dwjl = (R)wdl.y;
-      R cj = dot(rji, rjl) / (r * rjl_l);
+      const R rjl_l = bl.r, wjl = bl.w, dwjl = bl.dw;
+      const V3<R> rjl = bl.d;
+      const R irjl = rcp_nr(rjl_l);
+      R cj = dot(rji, rjl) * (ir * irjl);
       R dgj;
       R gj = guard(P, cj, dgj);
       if (gj == (R)0) continue;
       V3<R> b = cross(rij, rjl);
       R nb2 = dot(b, b);
-      R inab = (R)1 / xsqrt(na2 * nb2);
+      const R inb = rsq_nr(nb2);
+      R inab = ina * inb;
       R cw = dot(a, b) * inab;
       R ww = wik * wjl * gi * gj;
       Sdh += ((R)1 - cw * cw) * ww;
       R V = 0, dV = 0;
       if (tors) {
-        int sl = __double2int_rn(D.x[l].w);
-        R eps = (R)P.tors_eps[sk + sl];
+        R eps = (R)P.tors_eps[sk + bl.s];
         R h = (R)0.5 * ((R)1 + cw);
         R h2 = h * h, h4 = h2 * h2;
         V = eps * ((R)(256.0 / 405.0) * h4 * h - (R)0.1);
@@ -646,13 +771,13 @@ __device__ void dihedral(const DevParams& P, const Dev& D, int i, int j, V3<R> r
       Gwij += ww * V;
       R Gwik = Gww * wjl * gi * gj, Gwjl = Gww * wik * gi * gj;
       R Gci = Gww * wik * wjl * gj * dgi, Gcj = Gww * wik * wjl * gi * dgj;
-      V3<R> Ga = Gc * (inab * b - (cw / na2) * a);
-      V3<R> Gb = Gc * (inab * a - (cw / nb2) * b);
-      R iik = (R)1 / (r * rik_l), ijl = (R)1 / (r * rjl_l);
-      V3<R> gik = cross(Ga, rij) + (Gwik * dwik / rik_l) * rik + Gci * (iik * rij - (ci / (rik_l * rik_l)) * rik);
-      V3<R> gjl = cross(Gb, rij) + (Gwjl * dwjl / rjl_l) * rjl + Gcj * (ijl * rji - (cj / (rjl_l * rjl_l)) * rjl);
-      gij = gij + cross(rik, Ga) + cross(rjl, Gb) + Gci * (iik * rik - (ci / (r * r)) * rij);
-      gij = gij - Gcj * (ijl * rjl - (cj / (r * r)) * rji);
+      V3<R> Ga = Gc * (inab * b - (cw * ina * ina) * a);
+      V3<R> Gb = Gc * (inab * a - (cw * inb * inb) * b);
+      R iik = ir * irik, ijl = ir * irjl;
+      V3<R> gik = cross(Ga, rij) + (Gwik * dwik * irik) * rik + Gci * (iik * rij - (ci * irik * irik) * rik);
+      V3<R> gjl = cross(Gb, rij) + (Gwjl * dwjl * irjl) * rjl + Gcj * (ijl * rji - (cj * irjl * irjl) * rjl);
+      gij = gij + cross(rik, Ga) + cross(rjl, Gb) + Gci * (iik * rik - (ci * ir * ir) * rij);
+      gij = gij - Gcj * (ijl * rjl - (cj * ir * ir) * rji);
       gik_sum = gik_sum + gik;
       acc.vec(j, l, rjl, gjl);
     }
@@ -671,15 +796,15 @@ struct BondFwd {
 
 // Bond order b_ij, forward pass only; fills the state of the reverse pass.
 template <typename R>
-__device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar,
-                            BondFwd<R>& f, int* st) {
+__device__ R bond_order_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG, int i, int j, V3<R> rij, R r,
+                            bool bstar, BondFwd<R>& f, int* st) {
   int si = __double2int_rn(D.x[i].w), sj = __double2int_rn(D.x[j].w);
   int p = si + sj;
   f.si = si; f.sj = sj;
   f.rlam = (bstar && P.bstar_use_R1) ? (R)P.R1[p] : r;
   V3<R> rji = -rij;
-  end_fwd(P, D, i, si, j, sj, rij, r, f.rlam, f.ei, st);
-  end_fwd(P, D, j, sj, i, si, rji, r, f.rlam, f.ej, st);
+  end_fwd(P, D, SG, 0, si, j, sj, rij, r, f.rlam, f.ei, st);
+  end_fwd(P, D, SG, 1, sj, i, si, rji, r, f.rlam, f.ej, st);
   R Nconj = (R)1 + f.ei.conj * f.ei.conj + f.ej.conj * f.ej.conj;
   R dFa, dFb;
   R pirc;
@@ -697,7 +822,7 @@ __device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R
       R Et = 0, Gwij = 0;
       AccT<double> none;   // forward only: nothing is accumulated
       none.st[0] = none.st[1] = 0;
-      dihedral(P, D, i, j, rij, r, (R)0, false, false, (R)0, f.Sdh, Et, dummy, Gwij, none);
+      dihedral(P, D, SG, i, j, rij, r, (R)0, false, false, (R)0, f.Sdh, Et, dummy, Gwij, none);
     }
   }
   return (R)0.5 * (f.ei.p + f.ej.p) + pirc + f.Tv * f.Sdh;
@@ -707,17 +832,20 @@ __device__ R bond_order_fwd(const DevParams& P, const Dev& D, int i, int j, V3<R
 // With dihedral_done, the caller takes the pi^dh part of the dihedral loop
 // (dE/dSdh = Gb T_ij) together with its own pass over the same loop.
 template <typename R, typename AC>
-__device__ void bond_order_rev(const DevParams& P, const Dev& D, int i, int j, V3<R> rij, R r, bool bstar,
-                               const BondFwd<R>& f, R Gb, V3<R>& gij, AC& acc, bool dihedral_done = false) {
+__device__ void bond_order_rev(const DevParams& P, const Dev& D, const Stage<R>& SG, int i, int j, V3<R> rij, R r,
+                               bool bstar, const BondFwd<R>& f, R Gb, V3<R>& gij, AC& acc,
+                               bool dihedral_done = false) {
   R GNij = Gb * (f.Fij + f.Sdh * f.dTa), GNji = Gb * (f.Fji + f.Sdh * f.dTb), GNc = Gb * (f.dFc + f.Sdh * f.dTc);
   if (f.dh && !dihedral_done) {
     R s2 = 0, Et = 0, Gwij = 0;
-    dihedral(P, D, i, j, rij, r, (R)0, false, true, Gb * f.Tv, s2, Et, gij, Gwij, acc);
+    dihedral(P, D, SG, i, j, rij, r, (R)0, false, true, Gb * f.Tv, s2, Et, gij, Gwij, acc);
   }
   V3<R> gi = {0, 0, 0}, gj = {0, 0, 0};
   V3<R> rji = -rij;
-  end_rev(P, D, i, f.si, j, f.sj, rij, r, f.rlam, bstar, f.ei, (R)0.5 * Gb, GNij, GNc * (R)2 * f.ei.conj, gi, acc);
-  end_rev(P, D, j, f.sj, i, f.si, rji, r, f.rlam, bstar, f.ej, (R)0.5 * Gb, GNji, GNc * (R)2 * f.ej.conj, gj, acc);
+  end_rev(P, D, SG, 0, i, f.si, j, f.sj, rij, r, f.rlam, bstar, f.ei, (R)0.5 * Gb, GNij, GNc * (R)2 * f.ei.conj, gi,
+          acc);
+  end_rev(P, D, SG, 1, j, f.sj, i, f.si, rji, r, f.rlam, bstar, f.ej, (R)0.5 * Gb, GNji, GNc * (R)2 * f.ej.conj, gj,
+          acc);
   gij = gij + gi - gj;
 }
 
@@ -1225,7 +1353,7 @@ __device__ void path_grad(const Dev& D, const PathInfo& pi, R GP, double scale_a
 
 // REBO pair + bond order + torsion, one lane per bond (Alg. 1 and 2 merged).
 template <typename R, typename A>
-__global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
+__global__ __launch_bounds__(64) void k_bond(Dev D, const DevParams* __restrict__ Pp, int mask) {
   if (D.skip && *D.skip) return;
   __shared__ DevParams sP;
   stage_params(sP, Pp);
@@ -1236,6 +1364,9 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
   A er = 0, et = 0;
   AccT<A> acc;
   acc.init(fbuf<A>(D), -1, -1);
+  extern __shared__ __align__(16) unsigned char stage_mem[];
+  Stage<R> SG;
+  SG.init(stage_mem);
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
     int seg = g < n0 ? 0 : (g < n0 + n1 ? 1 : 2);
     int off = g - (seg == 0 ? 0 : (seg == 1 ? n0 : n0 + n1));
@@ -1247,6 +1378,7 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
     double2 wd = D.sw[i * D.scap + slot];
     R wij = (R)wd.x, dwij = (R)wd.y;
     int p = seg;
+    SG.fill(D, i, j);
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
     A er0 = er, et0 = et, W0[6];
@@ -1256,10 +1388,11 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
     const bool tors = (mask & AIREBO_TERM_TORSION) && p == 0;
     R GSdh = 0;   // dE/d(pi^dh dihedral sum), taken in the torsion's pass over the same loop
     if (mask & AIREBO_TERM_REBO) {
+      const R ir = rcp_nr(r);
       R ea = (R)P.alpha[p];
       R eR = xexp(-ea * r) * (R)P.A[p];
-      R VR = ((R)1 + (R)P.Q[p] / r) * eR;
-      R dVR = -((R)P.Q[p] / (r * r)) * eR - ea * VR;
+      R VR = ((R)1 + (R)P.Q[p] * ir) * eR;
+      R dVR = -((R)P.Q[p] * ir * ir) * eR - ea * VR;
       R VA = 0, dVA = 0;
       for (int m = 0; m < 3; ++m) {
         if (P.B[p][m] == 0.0) continue;
@@ -1269,19 +1402,19 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
       }
       R Gb = -wij * VA;
       BondFwd<R> bf;
-      R b = bond_order_fwd(P, D, i, j, rij, r, false, bf, acc.st);
-      bond_order_rev(P, D, i, j, rij, r, false, bf, Gb, gij, acc, tors);
+      R b = bond_order_fwd(P, D, SG, i, j, rij, r, false, bf, acc.st);
+      bond_order_rev(P, D, SG, i, j, rij, r, false, bf, Gb, gij, acc, tors);
       if (tors && bf.dh) GSdh = Gb * bf.Tv;
       er += (A)(wij * (VR - b * VA));
       Gr += dwij * (VR - b * VA) + wij * (dVR - b * dVA);
     }
     if (tors) {
       R Sdh = 0, Et = 0, Gwij = 0;
-      dihedral(P, D, i, j, rij, r, wij, true, true, GSdh, Sdh, Et, gij, Gwij, acc);
+      dihedral(P, D, SG, i, j, rij, r, wij, true, true, GSdh, Sdh, Et, gij, Gwij, acc);
       et += (A)Et;
       Gr += Gwij * dwij;
     }
-    gij = gij + (Gr / r) * rij;
+    gij = gij + (Gr * rcp_nr(r)) * rij;
     acc.vec(i, j, rij, gij);
     acc.flush();
     if (D.nsys > 1) {
@@ -1300,12 +1433,13 @@ __global__ __launch_bounds__(256) void k_bond(Dev D, const DevParams* __restrict
 
 template <typename R>
 __device__ __forceinline__ void lj_pair(const DevParams& P, int p, R r, R& V, R& dV) {
-  R s = (R)P.sigma[p] / r;
+  const R ir = rcp_nr(r);
+  R s = (R)P.sigma[p] * ir;
   R s2 = s * s, s6 = s2 * s2 * s2;
   R e4 = (R)(4.0 * P.eps[p]);
   R v = e4 * (s6 * s6 - s6);
-  R dv = e4 * ((R)-12 * s6 * s6 + (R)6 * s6) / r;
-  R isw = (R)(1.0 / P.lj_sw);
+  R dv = e4 * ((R)-12 * s6 * s6 + (R)6 * s6) * ir;
+  R isw = (R)P.inv_lj_sw;
   R t = (r - (R)(P.rc[p] - P.lj_sw)) * isw, dS;
   R S = Sw(t, dS);
   V = v * S;
@@ -1348,7 +1482,7 @@ __device__ __forceinline__ void lj_pair_r2(const DevParams& P, int p, R r2, R& V
   R r0 = (R)(P.rc[p] - P.lj_sw);
   if (r2 > r0 * r0) {
     R r = sqrt(r2);
-    R isw = (R)(1.0 / P.lj_sw), dS;
+    R isw = (R)P.inv_lj_sw, dS;
     R S = Sw((r - r0) * isw, dS);
     V = v * S;
     G = gv * S + v * dS * isw / r;
@@ -1367,7 +1501,7 @@ __device__ __forceinline__ void morse_pair(const DevParams& P, int p, R r, R& V,
   R e = (R)P.m_eps[p];
   R v = e * (ex * ex - (R)2 * ex);
   R dv = (R)2 * a * e * (ex - ex * ex);
-  R isw = (R)(1.0 / P.lj_sw);
+  R isw = (R)P.inv_lj_sw;
   R t = (r - (R)(P.rc[p] - P.lj_sw)) * isw, dS;
   R S = Sw(t, dS);
   V = v * S;
@@ -1394,23 +1528,6 @@ struct PairConst {
 };
 __device__ __forceinline__ double sel3(const double (&a)[3], int p) { return p == 0 ? a[0] : (p == 1 ? a[1] : a[2]); }
 
-// FP64 reciprocal and reciprocal square root for the plain pair loops: the
-// hardware estimate refined by one Newton-Raphson step, which doubles its
-// correct bits; the result is within a few ulp of the correctly rounded
-// value at a fraction of the cost of the IEEE division and square root
-// sequences.  FP32 keeps the compiler's operations.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  return fma(y, e, y);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);   // y <- y (1 + e / 2), e = 1 - x y^2
-  return fma(0.5 * y, e, y);
-}
-__device__ __forceinline__ float rcp_nr(float x) { return 1.0f / x; }
-__device__ __forceinline__ float rsq_nr(float x) { return 1.0f / sqrtf(x); }
 
 // Plain LJ pair from r^2 with the pair-class constants already selected:
 // sg2 = sigma^2, e4 = 4 eps, r0 = start of the outer switch.
@@ -1796,7 +1913,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M ? 4 : LJF
 // bond order b* enters through S_b): energy and the full gradient, including
 // the path atoms of C_ij and, where 0 < t_b < 1, the b* neighbourhood.
 template <typename R, typename A, bool M>
-__global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
+__global__ __launch_bounds__(64) void k_bstar(Dev D, const DevParams* __restrict__ Pp) {
   if (D.skip && *D.skip) return;
   __shared__ DevParams sP;
   stage_params(sP, Pp);
@@ -1815,6 +1932,9 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
   unsigned long long ndsb = 0;
   unsigned long long nskip = 0, nc0 = 0;   // searched pairs that are not deferred pairs; of them with C_ij = 0
   unsigned long long nbstar = 0;           // evaluated pairs inside the S_r range (b* needed)
+  extern __shared__ __align__(16) unsigned char stage_mem[];
+  Stage<R> SG;
+  SG.init(stage_mem);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nq; t += gridDim.x * blockDim.x) {
     int g = 0;
     while (seg_start[g + 1] <= t) ++g;
@@ -1831,7 +1951,7 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
     A dz = (A)xj.z - (A)xi.z + (A)((code % 3 - 1) * B.L[2]);
     int p = __double2int_rn(xi.w) + __double2int_rn(xj.w);
     A r2 = dx * dx + dy * dy + dz * dz;
-    A r = xsqrt(r2);
+    A r = r2 * rsq_nr(r2);
     acc.i = i; acc.j = j;
     for (int c = 0; c < 3; ++c) acc.fi[c] = acc.fj[c] = 0;
     A V, dV;
@@ -1848,7 +1968,7 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
       } else if (best > 0.0 || (double)r2 < P.rljmax[p] * P.rljmax[p]) {
         evaluate = i < j;                                   // a deferred pair: the lower index evaluates it
       } else {                                              // a plain pair: this end's half
-        A G = dV / r;
+        A G = dV * rcp_nr(r);
         e += (A)0.5 * V;
         A g3[3] = {G * dx, G * dy, G * dz};
         for (int c = 0; c < 3; ++c) acc.fi[c] += g3[c];
@@ -1878,8 +1998,9 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
       BondFwd<R> bf;
       if (Sr > (A)0) {
         ++nbstar;
-        R bs = bond_order_fwd(P, D, i, j, rij, (R)r, true, bf, acc.st);
-        A inv_b = (A)(1.0 / (P.bmax[p] - P.bmin[p]));
+        SG.fill(D, i, j);
+        R bs = bond_order_fwd(P, D, SG, i, j, rij, (R)r, true, bf, acc.st);
+        A inv_b = (A)P.inv_db[p];
         Sb = Sw(((A)bs - (A)P.bmin[p]) * inv_b, dSb);
         dSb *= inv_b;
       }
@@ -1889,10 +2010,10 @@ __global__ __launch_bounds__(256) void k_bstar(Dev D, const DevParams* __restric
       if (dSb != (A)0) {   // the reverse pass reuses the forward state
         ++ndsb;
         R Gb = (R)(Sr * dSb * C * V);
-        bond_order_rev(P, D, i, j, rij, (R)r, true, bf, Gb, gij, acc);
+        bond_order_rev(P, D, SG, i, j, rij, (R)r, true, bf, Gb, gij, acc);
       }
       if (prod > (A)0) path_grad<A>(D, pi, -Qf * V, 1.0, 1.0, acc);
-      gij = gij + (R)(Gr / r) * rij;
+      gij = gij + (R)(Gr * rcp_nr(r)) * rij;
       acc.vec(i, j, rij, gij);
       acc.flush();
     }
@@ -2274,18 +2395,19 @@ struct airebo_ctx {
 };
 
 // Launch a kernel; in profile mode bracket it with a pair of HIP events.
-#define LAUNCH(C, KID, KER, GRID, BLOCK, STREAM, ...)                                     \
+#define LAUNCH(C, KID, KER, GRID, BLOCK, STREAM, ...) LAUNCH_SHM(C, KID, KER, GRID, BLOCK, 0, STREAM, __VA_ARGS__)
+#define LAUNCH_SHM(C, KID, KER, GRID, BLOCK, SHM, STREAM, ...)                            \
   do {                                                                                     \
     if ((C)->prof) {                                                                       \
       airebo_ctx::Ev e_{KID, nullptr, nullptr};                                            \
       (void)hipEventCreate(&e_.a);                                                         \
       (void)hipEventCreate(&e_.b);                                                         \
       (void)hipEventRecord(e_.a, STREAM);                                                  \
-      hipLaunchKernelGGL(KER, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                        \
+      hipLaunchKernelGGL(KER, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                      \
       (void)hipEventRecord(e_.b, STREAM);                                                  \
       (C)->ev.push_back(e_);                                                               \
     } else {                                                                               \
-      hipLaunchKernelGGL(KER, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                        \
+      hipLaunchKernelGGL(KER, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                      \
     }                                                                                      \
   } while (0)
 
@@ -2323,10 +2445,12 @@ int check_options(const airebo_options& o) {
     return fail(AIREBO_E_ARG, "the Morse (AIREBO-M) form is evaluated in FP64 only");
   if (o.lj_cap < 0 || o.lj_slack < 0 || o.queue_per_atom < 0 || o.queue_per_atom > 1024)
     return fail(AIREBO_E_ARG, "bad lj_cap, lj_slack or queue_per_atom");
-  auto okb = [](int b) { return b == 0 || b == 64 || b == 128 || b == 192 || b == 256; };
+  // the bond-order kernels are one wavefront per block (their LDS stage is
+  // sized for 64 threads)
+  auto okb = [](int b) { return b == 0 || b == 64; };
   auto oks = [](int b) { return b == 0 || b == 256 || b == 512 || b == 1024; };
   if (!okb(o.bond_block) || !okb(o.defer_block) || !oks(o.short_block) || o.bond_grid < 0)
-    return fail(AIREBO_E_ARG, "launch shapes: bond and deferred blocks 0 or 64, 128, 192, 256 threads; "
+    return fail(AIREBO_E_ARG, "launch shapes: bond and deferred blocks 0 or 64 threads; "
                               "short-list block 0 or 256, 512, 1024 threads");
   return 0;
 }
@@ -2651,19 +2775,23 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
     else if (single) LAUNCH(c, K_LJ, (k_lj<float, float, false>), glj, dim3(LJ_BLOCK), st, D, P);
     else LAUNCH(c, K_LJ, (k_lj<double, double, false>), glj, dim3(LJ_BLOCK), st, D, P);
   };
+  // the bond-order kernels stage each lane's neighbourhood in LDS (dynamic size)
+  const size_t sh32 = (size_t)stage_bytes<float>(), sh64 = (size_t)stage_bytes<double>();
   auto bond_terms = [&](hipStream_t st) {
-    if (prec == AIREBO_MIXED) LAUNCH(c, K_BOND, (k_bond<float, double>), dim3(nb), dim3(bblk), st, D, P, mask);
-    else if (single) LAUNCH(c, K_BOND, (k_bond<float, float>), dim3(nb), dim3(bblk), st, D, P, mask);
-    else LAUNCH(c, K_BOND, (k_bond<double, double>), dim3(nb), dim3(bblk), st, D, P, mask);
+    if (prec == AIREBO_MIXED)
+      LAUNCH_SHM(c, K_BOND, (k_bond<float, double>), dim3(nb), dim3(bblk), bblk * sh32, st, D, P, mask);
+    else if (single) LAUNCH_SHM(c, K_BOND, (k_bond<float, float>), dim3(nb), dim3(bblk), bblk * sh32, st, D, P, mask);
+    else LAUNCH_SHM(c, K_BOND, (k_bond<double, double>), dim3(nb), dim3(bblk), bblk * sh64, st, D, P, mask);
   };
   auto deferred_pairs = [&](hipStream_t st) {
     // one lane per expected deferred pair (about 3 per atom in dense melts), so
     // that the latency-bound b* work is spread over many wavefronts
     dim3 gq(std::min(blocks(4 * (int64_t)D.n, qblk), 16384));
-    if (morse) LAUNCH(c, K_BSTAR, (k_bstar<double, double, true>), gq, dim3(qblk), st, D, P);
-    else if (prec == AIREBO_MIXED) LAUNCH(c, K_BSTAR, (k_bstar<float, double, false>), gq, dim3(qblk), st, D, P);
-    else if (single) LAUNCH(c, K_BSTAR, (k_bstar<float, float, false>), gq, dim3(qblk), st, D, P);
-    else LAUNCH(c, K_BSTAR, (k_bstar<double, double, false>), gq, dim3(qblk), st, D, P);
+    if (morse) LAUNCH_SHM(c, K_BSTAR, (k_bstar<double, double, true>), gq, dim3(qblk), qblk * sh64, st, D, P);
+    else if (prec == AIREBO_MIXED)
+      LAUNCH_SHM(c, K_BSTAR, (k_bstar<float, double, false>), gq, dim3(qblk), qblk * sh32, st, D, P);
+    else if (single) LAUNCH_SHM(c, K_BSTAR, (k_bstar<float, float, false>), gq, dim3(qblk), qblk * sh32, st, D, P);
+    else LAUNCH_SHM(c, K_BSTAR, (k_bstar<double, double, false>), gq, dim3(qblk), qblk * sh64, st, D, P);
   };
   // Two streams.  The main stream runs the short list, the near LJ pairs
   // (they need the short list for the path maps) and the deferred pairs;

@@ -163,6 +163,7 @@ bool build_params_text(const char* text, size_t len, DevParams& P, double* tri, 
         return false;
     if (!(P.R1[p] > 0 && P.R2[p] > P.R1[p])) { err = "REBO cutoffs must satisfy 0 < R1 < R2"; return false; }
     if (!(P.bmax[p] > P.bmin[p])) { err = "bmax must exceed bmin"; return false; }
+    P.inv_db[p] = 1.0 / (P.bmax[p] - P.bmin[p]);
     P.inv_dR[p] = 1.0 / (P.R2[p] - P.R1[p]);
   }
   double sCC, sHH, eCC, eHH, cut, bs;
@@ -178,6 +179,8 @@ bool build_params_text(const char* text, size_t len, DevParams& P, double* tri, 
     err = "switch ranges must be increasing"; return false;
   }
   P.bstar_use_R1 = bs != 0;
+  P.inv_guard = 1.0 / (P.guard_off - P.guard_on);
+  P.inv_lj_sw = 1.0 / P.lj_sw;
   // Morse pair term of AIREBO-M: all nine records or none
   P.morse_ok = 0;
   if (sc.count("morse_eps_CC")) {

@@ -37,11 +37,11 @@ struct DevParams {
   double gC_lo, gC_hi, conj_lo, conj_hi;
   GSpline gC, gammaC, gH;
   double Pc[2][4][4][16];       // [s_j][cNC][cNH][a*4+b]: sum c_ab tC^a tH^b
-  double guard_on, guard_off;
+  double guard_on, guard_off, inv_guard;   // inv_guard = 1 / (guard_off - guard_on)
   double tors_eps[3];           // by number of H among the two end atoms
   double sigma[3], eps[3], rc[3], rc2[3], rljmax[3], inv_rlj[3];
-  double lj_sw;
-  double bmin[3], bmax[3];
+  double lj_sw, inv_lj_sw;
+  double bmin[3], bmax[3], inv_db[3];   // inv_db = 1 / (bmax - bmin)
   int bstar_use_R1;
   double rc_max;                // largest LJ cutoff
   double r_conn;                // no path of three bonds reaches beyond this (3 max R2)
