@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--thermo-out", default="",
                     help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds P) to this text file")
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA-loop peak measurement")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -113,6 +114,12 @@ def main():
 
     import torch
     from paper_1810_07026_amd import airebo, synth
+
+    peaks = None
+    if not args.no_peaks:
+        peaks = airebo.measured_peaks()
+        log(f"bench: measured peaks {json.dumps({k: round(v_, 1) for k, v_ in peaks.items()})}")
+    args.peaks = peaks
 
     if args.copy_calib_mb:
         a = torch.ones(args.copy_calib_mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
@@ -177,7 +184,7 @@ def main():
         prof = ctx.profile_nve(xp, vp, d["species"], box, per, nsteps=args.profile_steps)
         kern = {k: {"total_ms": ms_, "launches": c, "avg_us": 1e3 * ms_ / c if c else 0.0}
                 for k, (ms_, c) in prof.items() if c}
-        roof = roofline(kern, st, prec, args)
+        roof = roofline(kern, st, prec, args, args.peaks)
         log(f"bench: kernels {json.dumps({k: round(v_['avg_us'], 2) for k, v_ in kern.items()})}")
 
     cpu = None
@@ -254,7 +261,8 @@ def main():
         "accuracy_vs_oracle": ferr,
         "energy_drift": {"slope_eV_per_atom_per_ps": slope, "max_rel": maxrel, "rebuilds": rebuilds,
                          "T_start_K": float(th[0, 4]), "T_end_K": float(th[-1, 4])},
-        "work": {k: st[k] for k in ("lj_in_cut", "lj_entries", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds")},
+        "work": {k: st[k] for k in ("lj_in_cut", "lj_in_cut_far", "lj_entries", "lj_entries_far", "cij_zero",
+                                    "bstar_queued", "dsb_nonzero", "bonds")},
         "kernels_us": {k: round(v_["avg_us"], 3) for k, v_ in kern.items()},
         "forms": forms,
     }
@@ -287,27 +295,50 @@ def timed_session(begin, ctx, n, steps, warmup, every=0):
     return n * steps / sec, 1e3 * sec / steps, th
 
 
-def roofline(kern, st, prec, args):
-    """Roofline record of the kernel that dominates the step.  Algorithmic
-    work of the LJ kernel: 45 flop per LJ pair inside its cutoff (each pair
-    once) and 8 per list pair outside it (distance test only); of the
-    bonded kernel: 4,000 flop per bond (forward and reverse bond order, pair
-    term, torsion)."""
-    from paper_1810_07026_amd import airebo
-    skin_pairs = max(st["lj_entries"] // 2 - st["lj_in_cut"], 0)
-    work = {"k_lj": FLOP_PER_LJ_PAIR * st["lj_in_cut"] + FLOP_PER_SKIN_PAIR * skin_pairs,
+def kernel_work(st):
+    """Algorithmic FP operations per launch of the kernels with a work model.
+    The LJ pairs (each pair once) split at the list build into near pairs
+    (within 3 max R2 + skin: k_lj) and far pairs (k_ljf): 45 flop per pair
+    inside its cutoff, 8 per list pair outside it (distance test only).
+    The bonded kernel: 4,000 flop per bond (forward and reverse bond order,
+    pair term, torsion)."""
+    far_in, far_pairs = st["lj_in_cut_far"], st["lj_entries_far"] // 2
+    near_in, near_pairs = st["lj_in_cut"] - far_in, (st["lj_entries"] - st["lj_entries_far"]) // 2
+    return {"k_lj": FLOP_PER_LJ_PAIR * near_in + FLOP_PER_SKIN_PAIR * max(near_pairs - near_in, 0),
+            "k_ljf": FLOP_PER_LJ_PAIR * far_in + FLOP_PER_SKIN_PAIR * max(far_pairs - far_in, 0),
             "k_bond": FLOP_PER_BOND * st["bonds"]}
+
+
+def roofline(kern, st, prec, args, peaks=None):
+    """Roofline record of the kernel with a work model that takes the most
+    time per step (the near-pair LJ kernel on the melt), against the
+    published vector peak of the arithmetic type and against the measured
+    FMA-loop peak; the other modelled kernels in `kernels`."""
+    from paper_1810_07026_amd import airebo
+    work = kernel_work(st)
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    cand = dom if dom in work else max(work, key=lambda k: kern.get(k, {"total_ms": 0})["total_ms"])
-    avg_s = kern[cand]["avg_us"] * 1e-6
     peak = FP64_VALU_PEAK if prec == airebo.FP64 else FP32_VALU_PEAK
-    ach = work[cand] / avg_s
-    return {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": ach / 1e12,
-            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
+    mpeak = None
+    if peaks:
+        mpeak = 1e12 * (peaks["fp64_fma_TFLOPs"] if prec == airebo.FP64 else peaks["fp32_fma_TFLOPs"])
+    rows = {}
+    for k, w in work.items():
+        if k not in kern or not kern[k]["launches"]:
+            continue
+        ach = w / (kern[k]["avg_us"] * 1e-6)
+        rows[k] = {"achieved": ach / 1e12, "frac": ach / peak, "frac_measured_peak": ach / mpeak if mpeak else None,
+                   "flop_per_launch": w, "avg_launch_us": kern[k]["avg_us"],
+                   "time_ms_per_step": kern[k]["total_ms"] / max(args.profile_steps, 1)}
+    cand = max(rows, key=lambda k: kern[k]["total_ms"])
+    r = rows[cand]
+    return {"bound": "alu", "kernel": cand, "dominant_kernel_by_time": dom, "achieved": r["achieved"],
+            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": r["frac"],
             # the committed counter profile is of the melt workload
             "traffic": (counter_traffic(cand, args.precision)
                         if args.workload == "pe_melt_32k" and args.potential == "airebo" else None),
-            "flop_per_launch": work[cand], "avg_launch_us": kern[cand]["avg_us"]}
+            "peak_measured": mpeak / 1e12 if mpeak else None, "frac_measured_peak": r["frac_measured_peak"],
+            "flop_per_launch": r["flop_per_launch"], "avg_launch_us": r["avg_launch_us"],
+            "kernels": rows, "measured_peaks": peaks}
 
 
 def prepare_melt(d, x, v, log):

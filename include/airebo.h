@@ -271,9 +271,16 @@ void airebo_md_end(airebo_ctx_t ctx);
  *  13 pairs handed to the sequential C_ij search because an atom's path map
  *     (64 candidates) overflowed (summed over the steps of an MD session)
  *  14 pairs evaluated by the deferred-pair kernel (0 < C_ij < 1 or inside
- *     the S_r range)                                15 reserved
- * Slots 0-4 and 9-10 refer to the last force evaluation (every step in NVE). */
+ *     the S_r range)
+ *  15 of slot 0, the far pairs (beyond 3 max R2 + skin at the list build)
+ * Slots 0-4, 9-10 and 15 refer to the last force evaluation (every step in
+ * NVE). */
 int airebo_stats(airebo_ctx_t ctx, int64_t* out16);
+/* The same counters and more (host [n] int64; slots beyond the last filled
+ * are set to 0): slots 0-15 as above, then
+ *  16 far LJ list entries (of slot 7)               17 max far entries of one atom
+ * Returns the number of slots filled (at most 18), or an error code. */
+int airebo_stats_n(airebo_ctx_t ctx, int64_t* out, int32_t n);
 
 /* Per-kernel timing of the velocity-Verlet path: runs nsteps steps like
  * airebo_nve (same arguments, no thermo output) but launches every kernel
@@ -288,6 +295,19 @@ int airebo_profile_nve(airebo_ctx_t ctx, int64_t n, double* pos, double* vel, co
                        double* ms_out, int64_t* launches_out, void* stream);
 int airebo_kernel_count(void);
 const char* airebo_kernel_name(int k);
+
+/* Measured device peaks for roofline fractions (measurement support, not
+ * part of the potential).
+ * airebo_peak_copy: `reps` streaming copies of `bytes` (a multiple of 32)
+ *   from src to dst (device pointers, caller-owned, not overlapping) after
+ *   one warm-up copy; *gbs (host) = bytes read + written per second / 1e9.
+ * airebo_peak_fma: a loop of eight independent fused multiply-add chains per
+ *   lane over 16 wavefronts per SIMD (FP64 when fp64 != 0, else FP32), `iters`
+ *   rounds after a warm-up launch; *tflops (host) = 16 iters flops per lane
+ *   per second / 1e12.  Allocates and frees its own small output buffer.
+ * Both run on `stream`, synchronise it, and return 0 or an error code. */
+int airebo_peak_copy(const void* src, void* dst, int64_t bytes, int32_t reps, double* gbs, void* stream);
+int airebo_peak_fma(int32_t fp64, int32_t iters, double* tflops, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned surrogate.  Not part of the paper: an approximation of the

@@ -21,16 +21,16 @@ TERM_REBO, TERM_LJ, TERM_TORSION, TERM_ALL = 1, 2, 4, 7
 THERMO_COLUMNS = ("step", "PE", "KE", "Etot", "T", "rebuilds", "P_bar")
 STAT_NAMES = ["lj_in_cut", "cij_zero", "bstar_queued", "dsb_nonzero", "bonds", "rebuilds", "max_short",
               "lj_entries", "max_lj", "spline_evals", "spline_evals_fp64", "nn_fallbacks",
-              "regrowths", "slow_path_pairs", "deferred_pairs"]
+              "regrowths", "slow_path_pairs", "deferred_pairs", "lj_in_cut_far", "lj_entries_far", "max_lj_far"]
 
 EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "airebo_compute", "airebo_nve",
-           "airebo_stats", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name",
+           "airebo_stats", "airebo_stats_n", "airebo_last_error", "airebo_profile_nve", "airebo_kernel_count", "airebo_kernel_name",
            "airebo_batch_compute", "airebo_batch_nve",
            "airebo_nn_create", "airebo_nn_free", "airebo_nn_sizes", "airebo_nn_models", "airebo_nn_set_params",
            "airebo_nn_get_params", "airebo_nn_get_grad", "airebo_nn_set_norm", "airebo_nn_get_norm",
            "airebo_nn_moments", "airebo_nn_descriptors", "airebo_nn_descriptor_jvp", "airebo_nn_descriptor_vjp",
            "airebo_nn_compute", "airebo_nn_gradient", "airebo_nn_adam", "airebo_nn_nve", "airebo_nn_profile_nve",
-           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check",
+           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check", "airebo_peak_copy", "airebo_peak_fma",
            "airebo_params_load", "airebo_params_parse", "airebo_params_free", "airebo_ctx_create_from_params",
            "airebo_compute_host", "airebo_nn_train_step",
            "airebo_md_begin", "airebo_batch_md_begin", "airebo_md_run", "airebo_md_state", "airebo_md_end",
@@ -96,6 +96,8 @@ def load_library(path=LIB_PATH):
     L.airebo_nve.restype = ctypes.c_int
     L.airebo_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.airebo_stats.restype = ctypes.c_int
+    L.airebo_stats_n.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    L.airebo_stats_n.restype = ctypes.c_int
     L.airebo_profile_nve.argtypes = L.airebo_nve.argtypes[:10] + [ctypes.POINTER(ctypes.c_double),
                                                                    ctypes.POINTER(ctypes.c_int64), vp]
     L.airebo_profile_nve.restype = ctypes.c_int
@@ -155,6 +157,8 @@ def load_library(path=LIB_PATH):
         "airebo_nn_save": [vp, ctypes.c_char_p],
         "airebo_nn_load": [ctypes.c_char_p, c_i32, ctypes.POINTER(ctypes.c_void_p)],
         "airebo_nn_mfma_check": [dp, dp, dp, vp],
+        "airebo_peak_copy": [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp],
+        "airebo_peak_fma": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -446,9 +450,11 @@ class Context:
         self._md_nn = None
 
     def stats(self):
-        out = (ctypes.c_int64 * 16)()
-        _check(self.L, self.L.airebo_stats(self.h, out))
-        return dict(zip(STAT_NAMES, list(out)[:len(STAT_NAMES)]))
+        out = (ctypes.c_int64 * len(STAT_NAMES))()
+        rc = self.L.airebo_stats_n(self.h, out, len(STAT_NAMES))
+        if rc < 0:
+            _check(self.L, rc)
+        return dict(zip(STAT_NAMES, list(out)))
 
 
 def _p(t):
@@ -669,3 +675,21 @@ def mfma_check(A, B):
     _check(L, L.airebo_nn_mfma_check(_p(A), _p(B), _p(D),
                                       ctypes.c_void_p(torch.cuda.current_stream(A.device).cuda_stream)))
     return D
+
+
+def measured_peaks(copy_mib=1024, fma_iters=8192):
+    """Measured device peaks: streaming-copy bandwidth (GB/s, bytes read +
+    written) and FP64 / FP32 fused multiply-add throughput (TFLOP/s)."""
+    import torch
+    L = load_library()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    n = copy_mib * (1 << 20)
+    a = torch.empty(n // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    gbs = ctypes.c_double()
+    _check(L, L.airebo_peak_copy(_p(a), _p(b), n, 5, ctypes.byref(gbs), st))
+    del a, b
+    f64, f32 = ctypes.c_double(), ctypes.c_double()
+    _check(L, L.airebo_peak_fma(1, fma_iters, ctypes.byref(f64), st))
+    _check(L, L.airebo_peak_fma(0, fma_iters, ctypes.byref(f32), st))
+    return {"copy_GBps": gbs.value, "fp64_fma_TFLOPs": f64.value, "fp32_fma_TFLOPs": f32.value}

@@ -73,7 +73,7 @@ enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16,
 // accumulator quantities; each lives in NSLOT copies (one per group of blocks,
 // one cache line apart) that k_finish / k_thermo add up
 enum { A_EREBO = 0, A_ETORS = 1, A_ELJ = 2, A_VIR = 3, A_NIN = 9, A_NC0 = 10, A_NDSB = 11, A_KE = 12, A_SPL = 13,
-       A_SPL64 = 14, A_NSKIP = 15, A_NBSTAR = 16, A_N = 24 };
+       A_SPL64 = 14, A_NSKIP = 15, A_NBSTAR = 16, A_NINF = 17, A_N = 24 };
 // mixed precision: a spline argument within this distance of a knot is evaluated in FP64
 // (single precision takes no such branch)
 constexpr double KNOT_DELTA = 1e-3;
@@ -90,7 +90,8 @@ const char* const kKernelNames[K_COUNT] = {
     "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32", "k_ljf"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_LJENT = 7,
-       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_SLOW = 13, S_QUEUED = 14, S_MAXLF = 15, S_N = 16 };
+       S_MAXLJ = 8, S_SPL = 9, S_SPL64 = 10, S_FALLBACK = 11, S_REGROW = 12, S_SLOW = 13, S_QUEUED = 14, S_INCUTF = 15,
+       S_LFENT = 16, S_MAXLF = 17, S_N = 18 };
 
 // One system of a batch: its own periodic box and cell grid.  A single
 // configuration is a batch of one.
@@ -1903,10 +1904,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(M ? 4 : LJF
     for (int o = LJF_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (sub == 0 && i < D.n && v != 0) atomic_add(&fbuf<A>(D)[3 * i + c], v);
   }
-  double v9[9] = {0.5 * (double)e, -0.5 * (double)W[0], -0.5 * (double)W[1], -0.5 * (double)W[2],
-                  -0.5 * (double)W[3], -0.5 * (double)W[4], -0.5 * (double)W[5], (double)n_in, 0.0};
-  if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v9, A_ELJ, i < D.n);
-  block_reduce_add<9>(v9, D.acc + A_ELJ);   // A_ELJ, A_VIR..A_VIR+5, A_NIN, A_NC0 are consecutive
+  double v16[16] = {0.5 * (double)e, -0.5 * (double)W[0], -0.5 * (double)W[1], -0.5 * (double)W[2],
+                    -0.5 * (double)W[3], -0.5 * (double)W[4], -0.5 * (double)W[5]};
+  v16[A_NINF - A_ELJ] = (double)n_in;   // far pairs inside the cutoff, counted apart from the near ones
+  if (D.nsys > 1) sys_add<7>(D, i < D.n ? sys_of(D, i) : 0, *(const double(*)[7])v16, A_ELJ, i < D.n);
+  block_reduce_add<16>(v16, D.acc + A_ELJ);   // A_ELJ .. A_NINF
 }
 
 // Deferred LJ pairs (0 < C_ij < 1, or inside the S_r range where the modified
@@ -2035,7 +2037,7 @@ __global__ __launch_bounds__(64) void k_bstar(Dev D, const DevParams* __restrict
 // Maximum of per-atom counts into a statistics slot, and the sum of the
 // counts clamped to `cap` into another (one atomic each per wavefront).
 __global__ void k_max(const int* __restrict__ a, int n, int cap, unsigned long long* out_max,
-                      unsigned long long* out_sum) {
+                      unsigned long long* out_sum, unsigned long long* out_sum2) {
   int m = 0;
   unsigned long long sum = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
@@ -2045,7 +2047,10 @@ __global__ void k_max(const int* __restrict__ a, int n, int cap, unsigned long l
   m = wave_max(m);
   sum = wave_sum(sum);
   if ((threadIdx.x & (WAVE - 1)) == 0 && m > 0) atomicMax(out_max, (unsigned long long)m);
-  if ((threadIdx.x & (WAVE - 1)) == 0 && sum > 0) atomicAdd(out_sum, sum);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && sum > 0) {
+    atomicAdd(out_sum, sum);
+    if (out_sum2) atomicAdd(out_sum2, sum);
+  }
 }
 
 __global__ void k_finish(Dev D, double* energy, double* virial) {
@@ -2069,7 +2074,8 @@ __global__ void k_finish(Dev D, double* energy, double* virial) {
     D.stats[S_BSTAR] = (unsigned long long)tot[A_NBSTAR];
     D.stats[S_QUEUED] = nq - (unsigned long long)tot[A_NSKIP];
     D.stats[S_BONDS] = (unsigned long long)(D.bcount[0] + D.bcount[1] + D.bcount[2]);
-    D.stats[S_INCUT] = (unsigned long long)tot[A_NIN];
+    D.stats[S_INCUT] = (unsigned long long)(tot[A_NIN] + tot[A_NINF]);
+    D.stats[S_INCUTF] = (unsigned long long)tot[A_NINF];
     D.stats[S_CIJ0] = (unsigned long long)tot[A_NC0];
     D.stats[S_DSB] = (unsigned long long)tot[A_NDSB];
     D.stats[S_SPL] = (unsigned long long)tot[A_SPL];
@@ -2900,9 +2906,9 @@ int compute_impl(airebo_ctx_t c, int nsys, const int64_t* off, const double* box
     if (n > 0) {
       int g = std::min(blocks(n, 256), 1024);
       hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.lj_cap, D.stats + S_MAXLJ,
-                         D.stats + S_LJENT);
+                         D.stats + S_LJENT, (unsigned long long*)nullptr);
       hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lf_n, (int)n, D.lf_cap, D.stats + S_MAXLF,
-                         D.stats + S_LJENT);
+                         D.stats + S_LJENT, D.stats + S_LFENT);
     }
     HIPCHK(hipGetLastError());
     int flags = 0;
@@ -3027,9 +3033,9 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, D, energy, virial);
     if (n > 0) {
       hipLaunchKernelGGL(k_max, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, (const int*)D.lj_n, (int)n,
-                         D.lj_cap, D.stats + S_MAXLJ, D.stats + S_LJENT);
+                         D.lj_cap, D.stats + S_MAXLJ, D.stats + S_LJENT, (unsigned long long*)nullptr);
       hipLaunchKernelGGL(k_max, dim3(std::min(blocks(n, 256), 1024)), dim3(256), 0, s, (const int*)D.lf_n, (int)n,
-                         D.lf_cap, D.stats + S_MAXLF, D.stats + S_LJENT);
+                         D.lf_cap, D.stats + S_MAXLF, D.stats + S_LJENT, D.stats + S_LFENT);
     }
     int flags = 0;
     e = hipGetLastError();
@@ -3457,12 +3463,16 @@ int airebo_kernel_count(void) { return K_COUNT; }
 
 const char* airebo_kernel_name(int k) { return (k >= 0 && k < K_COUNT) ? kKernelNames[k] : ""; }
 
-int airebo_stats(airebo_ctx_t c, int64_t* out) {
+int airebo_stats(airebo_ctx_t c, int64_t* out) { return airebo_stats_n(c, out, 16); }
+
+int airebo_stats_n(airebo_ctx_t c, int64_t* out, int n) {
   if (!c || !out) return fail(AIREBO_E_ARG, "null argument");
-  for (int k = 0; k < 16; ++k) out[k] = (int64_t)c->host_stats[k];
-  return 0;
+  if (n < 0) return fail(AIREBO_E_ARG, "negative count");
+  for (int k = 0; k < n; ++k) out[k] = k < S_N ? (int64_t)c->host_stats[k] : 0;
+  return std::min(n, (int)S_N);
 }
 
 }  // extern "C"
 
 #include "surrogate.hip"
+#include "peaks.hip"

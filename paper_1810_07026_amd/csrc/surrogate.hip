@@ -1297,9 +1297,9 @@ int nn_eval(airebo_ctx* c, int64_t n, const double* pos, const int32_t* species,
     launch_rebuild(c, s);
     int g = std::min(blocks(n, 256), 1024);
     hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lj_n, (int)n, D.lj_cap, D.stats + S_MAXLJ,
-                       D.stats + S_LJENT);
+                       D.stats + S_LJENT, (unsigned long long*)nullptr);
     hipLaunchKernelGGL(k_max, dim3(g), dim3(256), 0, s, (const int*)D.lf_n, (int)n, D.lf_cap, D.stats + S_MAXLF,
-                       D.stats + S_LJENT);
+                       D.stats + S_LJENT, D.stats + S_LFENT);
     rc = body(D);
     if (rc) return rc;
     HIPCHK(hipGetLastError());

@@ -9,6 +9,8 @@ of exp / cos / sqrt between the device and host math libraries.
 import math
 
 import numpy as np
+
+from paper_1810_07026_amd.airebo import DEFAULT_PARAMS
 import pytest
 
 from paper_1810_07026_amd import synth
@@ -147,6 +149,42 @@ def test_stats_match_oracle(ctxs, oracle):
     assert st["cij_zero"] == so["cij_zero"]
     assert st["bstar_queued"] == so["bstar_needed"]
     assert st["dsb_nonzero"] == so["dsb_nonzero"]
+
+
+def test_far_pair_counts(ctxs):
+    """The LJ pairs inside the cutoff split at the list build into near pairs
+    and far pairs (beyond 3 max R2 + skin + 1e-3 A, the margin of the FP32
+    distance the build uses): the far count equals a brute-force count over
+    all periodic images of pairs with that boundary <= r < 3 sigma_ij (the
+    list is built from the same positions), up to pairs within 1e-4 A of the
+    boundary, and the far list entries hold every far pair from both ends."""
+    d = synth.pe_small()   # 20 A box: pairs can meet within the cutoff through several images
+    run_gpu(ctxs[7], d)
+    st = ctxs[7].stats()
+    sc = {}
+    for line in open(DEFAULT_PARAMS):
+        f = line.split("#")[0].split()
+        if len(f) == 2:
+            sc[f[0]] = float(f[1])
+    sig = np.array([[sc["sigma_CC"], 0.5 * (sc["sigma_CC"] + sc["sigma_HH"])],
+                    [0.5 * (sc["sigma_CC"] + sc["sigma_HH"]), sc["sigma_HH"]]])
+    rnear = 3 * max(sc["R2_CC"], sc["R2_CH"], sc["R2_HH"]) + 1.0 + 1e-3   # default skin 1 A
+    x, s, L = d["x"], d["species"], np.asarray(d["box"], float)
+    per = np.asarray(d["periodic"], float)
+    xw = x - L * np.floor(x / L) * per
+    shifts = [np.array([u, v, w]) for u in range(-2, 3) for v in range(-2, 3) for w in range(-2, 3)
+              if all(per[c] or (u, v, w)[c] == 0 for c in range(3))]
+    far = edge = 0
+    for a in range(len(s) - 1):
+        rc = sc["LJ_cut_sigma"] * sig[s[a], s[a + 1:]]
+        for sh in shifts:   # every periodic image of every pair a < b
+            dv = xw[a + 1:] + sh * L - xw[a]
+            r = np.sqrt((dv ** 2).sum(1))
+            far += int(((r >= rnear) & (r < rc)).sum())
+            edge += int((np.abs(r - rnear) < 1e-4).sum())
+    assert abs(st["lj_in_cut_far"] - far) <= edge, (st["lj_in_cut_far"], far, edge)
+    assert 0 < st["lj_in_cut_far"] < st["lj_in_cut"]
+    assert 2 * st["lj_in_cut_far"] <= st["lj_entries_far"] <= st["lj_entries"]
 
 
 def test_nve_matches_oracle(oracle):
