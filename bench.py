@@ -103,6 +103,8 @@ def main():
                     help="conservation workload: also write the thermo rows (step PE KE Etot T rebuilds P) to this text file")
     ap.add_argument("--tune", default="", help="JSON launch shapes (batch512 workload)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FMA-loop peak measurement")
+    ap.add_argument("--save-state", default="", help="melt: write the prepared positions and velocities (npz)")
+    ap.add_argument("--state", default="", help="melt: start from positions and velocities saved by --save-state")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -148,8 +150,16 @@ def main():
     x = torch.tensor(d["x"], dtype=torch.float64, device=dev)
     v = torch.tensor(d["v"], dtype=torch.float64, device=dev)
 
-    if args.workload == "pe_melt_32k" and not args.no_prep:
+    if args.workload == "pe_melt_32k" and args.state:
+        st_ = np.load(args.state)
+        x = torch.tensor(st_["x"], dtype=torch.float64, device=dev)
+        v = torch.tensor(st_["v"], dtype=torch.float64, device=dev)
+        log(f"bench: state read from {args.state}")
+    elif args.workload == "pe_melt_32k" and not args.no_prep:
         x, v = prepare_melt(d, x, v, log)
+    if args.save_state:
+        np.savez(args.save_state, x=x.cpu().numpy(), v=v.cpu().numpy())
+        log(f"bench: prepared state written to {args.save_state}")
     elif args.workload == "hybrid_1m":
         x, v = prepare_hybrid(d, x, v, log)
     # the timed region holds exactly `steps` velocity-Verlet steps of a session
