@@ -165,15 +165,17 @@ int airebo_compute_host(airebo_ctx_t ctx, int64_t n, const double* pos, const in
 /* airebo_compute for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments and results, with every work buffer of the evaluation
- * taken from one static device array of 27.4 MiB that the library holds on
+ * taken from one static device array of 28.9 MiB that the library holds on
  * each device it runs on until the process ends (set up when the first
  * context on that device is created).  The call allocates nothing; the
  * context lends its parameters, streams and events and keeps its own
  * buffers and state (an MD session of the context is ended).
  * Limits: n <= 8192 atoms, a cell grid of at most 32768 cells (cells are at
- * least half the LJ cutoff plus skin), at most 4,194,304 LJ list entries in
- * all (512 per atom at 8192 atoms) and 196,608 deferred pairs; beyond any of
- * them the call returns AIREBO_E_CAPACITY and does no work.  Every call on
+ * least half the LJ cutoff plus skin), LJ list entries of at most 1,835,008
+ * near pairs (within 3 max R2 + skin: 224 per atom at 8192 atoms) and
+ * 3,145,728 far pairs (384 per atom at 8192 atoms), and 196,608 deferred
+ * pairs; beyond any of them the call returns AIREBO_E_CAPACITY and does no
+ * work.  Every call on
  * one device shares that device's array: calls that overlap on one device
  * (from several threads or contexts, on different streams) race and must
  * be serialised by the caller.  Synchronous like airebo_compute.  Errors
