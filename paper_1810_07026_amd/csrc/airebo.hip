@@ -10,7 +10,7 @@
 //
 // GPU design (one process, one device; everything stays in HBM):
 //   rebuild (when any atom moved more than half the skin):
-//     k_bin / k_scan / k_fill   counting sort of atoms into cells >= half of LJ cutoff + skin
+//     k_bin / k_fill             counting sort of atoms into cells >= half of LJ cutoff + skin
 //     k_build                    one wavefront per atom: full LJ list (with image
 //                                shift codes) and the intermediate REBO list
 //                                (R2 + skin), both filled by wave-ballot compaction
@@ -81,12 +81,12 @@ constexpr int NSLOT = 64;
 // deferred-pair queue: NSEG segments with separate counters (QSTRIDE ints apart)
 constexpr int NSEG = 64, QSTRIDE = 32;
 // kernel ids for per-kernel timing
-enum { K_LOAD, K_BIN, K_SCAN, K_FILL, K_BUILD, K_BUILD_DONE, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
-       K_FINISH, K_KICK_DRIFT, K_KICK, K_THERMO, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_PACK,
+enum { K_LOAD, K_BIN, K_FILL, K_BUILD, K_ZERO, K_SHORT, K_BOND, K_LJ, K_BSTAR,
+       K_FINISH, K_KICK_DRIFT, K_KICK, K_NN_ZERO, K_NN_ORDER, K_NN_DESC, K_NN_MLP, K_NN_FORCE, K_NN_PACK,
        K_NN_ENS, K_NN_DECIDE, K_FOLD32, K_LJF, K_COUNT };
 const char* const kKernelNames[K_COUNT] = {
-    "k_load", "k_bin", "k_scan", "k_fill", "k_build", "k_build_done", "k_zero", "k_short", "k_bond",
-    "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "k_thermo", "nn_zero", "nn_order", "nn_desc",
+    "k_load", "k_bin", "k_fill", "k_build", "k_zero", "k_short", "k_bond",
+    "k_lj", "k_bstar", "k_finish", "k_kick_drift", "k_kick", "nn_zero", "nn_order", "nn_desc",
     "nn_mlp", "nn_desc_force", "nn_pack", "nn_ens", "nn_decide", "k_fold32", "k_ljf"};
 // statistics slots (unsigned long long)
 enum { S_INCUT = 0, S_CIJ0 = 1, S_BSTAR = 2, S_DSB = 3, S_BONDS = 4, S_REBUILD = 5, S_MAXSHORT = 6, S_LJENT = 7,
@@ -882,38 +882,56 @@ __global__ void k_load(Dev D, const double* __restrict__ pos, const int* __restr
   D.x[i] = x;
 }
 
-__global__ void k_bin(Dev D) {
-  if (!(*D.flags & F_REBUILD)) return;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
-  double4 x = D.x[i];
-  double* xc = &x.x;
-  const SysBox& B = box_of(D, i);
-  for (int c = 0; c < 3; ++c) {
-    if (B.per[c]) {
-      xc[c] -= B.L[c] * floor(xc[c] * B.invL[c]);
-      if (xc[c] >= B.L[c]) xc[c] -= B.L[c];
-      if (xc[c] < 0) xc[c] = 0;
-    }
-  }
-  D.x[i] = x;
-  D.xref[i] = x;
-  int c = B.cell_off + (cell_coord(x.x, B.invL[0], B.nc[0]) * B.nc[1] + cell_coord(x.y, B.invL[1], B.nc[1])) * B.nc[2] +
-          cell_coord(x.z, B.invL[2], B.nc[2]);
-  D.cell_of[i] = c;
-  atomicAdd(&D.cell_count[c], 1);
+// Counters of the last-block patterns (D.step[1], D.step[2]): every block
+// of a kernel adds one after its own work; the block that brings the count
+// to gridDim.x finishes the kernel's sequential tail and resets the count.
+// Each thread's writes are released at device scope before the block's
+// barrier and the counter update, and acquired again by the last block, so
+// the tail sees every block's atomics (the usual threadfence reduction).
+__device__ __forceinline__ bool last_block(int* counter) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    is_last = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  return true;
 }
 
-// Exclusive scan of cell counts (one block); resets the counts for the next build.
-__global__ void k_scan(Dev D, int ncell) {
-  if (!(*D.flags & F_REBUILD)) return;
+// Binning of a rebuild (wrapped positions, reference positions, cell of
+// every atom, cell counts); the last block to finish turns the counts into
+// cell starts (exclusive scan) and clears them for the next build.
+__global__ void k_bin(Dev D, int ncell) {
+  if (!(*D.flags & F_REBUILD)) return;   // the same on every block
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D.n) {
+    double4 x = D.x[i];
+    double* xc = &x.x;
+    const SysBox& B = box_of(D, i);
+    for (int c = 0; c < 3; ++c) {
+      if (B.per[c]) {
+        xc[c] -= B.L[c] * floor(xc[c] * B.invL[c]);
+        if (xc[c] >= B.L[c]) xc[c] -= B.L[c];
+        if (xc[c] < 0) xc[c] = 0;
+      }
+    }
+    D.x[i] = x;
+    D.xref[i] = x;
+    int c = B.cell_off + (cell_coord(x.x, B.invL[0], B.nc[0]) * B.nc[1] + cell_coord(x.y, B.invL[1], B.nc[1])) * B.nc[2] +
+            cell_coord(x.z, B.invL[2], B.nc[2]);
+    D.cell_of[i] = c;
+    atomicAdd(&D.cell_count[c], 1);
+  }
+  if (!last_block(D.step + 2)) return;
   __shared__ int part[1024];
   int t = threadIdx.x, nt = blockDim.x;
   int per = (ncell + nt - 1) / nt;
   int lo = t * per, hi = min(ncell, lo + per);
-  int s = 0;
-  for (int c = lo; c < hi; ++c) s += D.cell_count[c];
-  part[t] = s;
+  int sum = 0;
+  for (int c = lo; c < hi; ++c) sum += D.cell_count[c];
+  part[t] = sum;
   __syncthreads();
   if (t == 0) {
     int run = 0;
@@ -927,7 +945,10 @@ __global__ void k_scan(Dev D, int ncell) {
     run += D.cell_count[c];
     D.cell_count[c] = 0;
   }
-  if (t == 0) D.cell_start[ncell] = D.n;
+  if (t == 0) {
+    D.cell_start[ncell] = D.n;
+    D.step[2] = 0;
+  }
 }
 
 __global__ void k_fill(Dev D) {
@@ -1091,13 +1112,6 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
   }
 }
 
-__global__ void k_build_done(Dev D) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && (*D.flags & F_REBUILD)) {
-    atomicAnd(D.flags, ~F_REBUILD);
-    D.stats[S_REBUILD] += 1;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Kernels: per-step force evaluation
 // ---------------------------------------------------------------------------
@@ -1139,6 +1153,12 @@ __device__ __forceinline__ void minimg(const SysBox& B, T& dx, T& dy, T& dz) {
 template <bool S>
 __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restrict__ Pp) {
   using T = typename std::conditional<S, float, double>::type;
+  // the lists of this step's rebuild (if any) are complete: count it and
+  // clear the flag (the list kernels are the only ones that read it)
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (*D.flags & F_REBUILD)) {
+    atomicAnd(D.flags, ~F_REBUILD);
+    D.stats[S_REBUILD] += 1;
+  }
   if (D.skip && *D.skip) return;
   const DevParams& P = *Pp;
   // SG lanes per atom: lane `sub` of the group takes intermediate entries
@@ -2102,29 +2122,6 @@ __global__ void k_finish(Dev D, double* energy, double* virial) {
 constexpr double FTM = 1.0 / 103.642691;   // eV / (A amu) -> A / fs^2
 constexpr double KB = 8.617333262e-5;
 
-// First half kick and drift; the forces used here are then zeroed together
-// with the step's accumulators, bond counters and queue counters (the force
-// chain of a step that starts here needs no separate zeroing).
-__global__ void k_kick_drift(Dev D, double* vel, double m0, double m1, double dt, double half_skin2) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < NSLOT * A_N) D.acc[i] = 0;
-  if (D.nsys > 1)
-    for (int k = i; k < D.nsys * A_N; k += gridDim.x * blockDim.x) D.sys_acc[k] = 0;
-  if (i < 3) D.bcount[i] = 0;
-  if (i < NSEG) D.qcount[i * QSTRIDE] = 0;
-  if (i >= D.n) return;
-  double4 x = D.x[i];
-  double im = FTM / (__double2int_rn(x.w) == 0 ? m0 : m1);
-  double v[3];
-  for (int c = 0; c < 3; ++c) v[c] = vel[3 * i + c] + 0.5 * dt * D.F[3 * i + c] * im;
-  x.x += dt * v[0]; x.y += dt * v[1]; x.z += dt * v[2];
-  for (int c = 0; c < 3; ++c) { vel[3 * i + c] = v[c]; D.F[3 * i + c] = 0; }
-  D.x[i] = x;
-  double4 xr = D.xref[i];
-  double ddx = x.x - xr.x, ddy = x.y - xr.y, ddz = x.z - xr.z;
-  if (ddx * ddx + ddy * ddy + ddz * ddz > half_skin2) atomicOr(D.flags, F_REBUILD);
-}
-
 __global__ void k_kick(Dev D, double* vel, double m0, double m1, double dt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   double ke = 0;
@@ -2158,12 +2155,12 @@ constexpr double EV_A3_TO_BAR = 1.602176634e6;
 // Thermo rows {step, PE, KE, Etot, T, rebuilds, P}: one row per system and
 // output step ([row][nsys][THERMO_W]); one block.  P (bar) = (2 KE + tr W) /
 // (3 V), defined for systems periodic in all three directions (0 otherwise).
-__global__ void k_thermo(Dev D, const MdCtl* __restrict__ ctl) {
+__device__ void thermo_rows(const Dev& D, const MdCtl* __restrict__ ctl) {
   int s = *D.step;
   double* thermo = ctl->thermo;
   int every = ctl->every, nrows = ctl->nrows;
   __syncthreads();
-  if (blockIdx.x == 0 && thermo && every > 0 && s % every == 0 && s / every < nrows) {
+  if (thermo && every > 0 && s % every == 0 && s / every < nrows) {
     for (int sid = threadIdx.x; sid < D.nsys; sid += blockDim.x) {
       double pe = 0, ke = 0, w = 0;
       int na = D.sys[sid].natoms;
@@ -2193,7 +2190,43 @@ __global__ void k_thermo(Dev D, const MdCtl* __restrict__ ctl) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && blockIdx.x == 0) *D.step = s + 1;
+  if (threadIdx.x == 0) *D.step = s + 1;
+}
+
+__global__ void k_thermo(Dev D, const MdCtl* __restrict__ ctl) {
+  if (blockIdx.x == 0) thermo_rows(D, ctl);
+}
+
+// First half kick and drift of a step.  Block 0 first writes the thermo row
+// of the state the previous step ended in (its sums are complete: a kernel
+// boundary lies between) and then clears the sums for this step; the
+// forces used here are zeroed by their atoms' threads, the bond and queue
+// counters by any thread (the force chain of a step that starts here needs
+// no separate zeroing).  A displacement beyond half the skin since the last
+// build flags a rebuild.
+__global__ void k_kick_drift(Dev D, double* vel, double m0, double m1, double dt, double half_skin2,
+                             const MdCtl* __restrict__ ctl) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0) {
+    thermo_rows(D, ctl);
+    __syncthreads();
+    for (int k = threadIdx.x; k < NSLOT * A_N; k += blockDim.x) D.acc[k] = 0;
+    if (D.nsys > 1)
+      for (int k = threadIdx.x; k < D.nsys * A_N; k += blockDim.x) D.sys_acc[k] = 0;
+  }
+  if (i < 3) D.bcount[i] = 0;
+  if (i < NSEG) D.qcount[i * QSTRIDE] = 0;
+  if (i >= D.n) return;
+  double4 x = D.x[i];
+  double im = FTM / (__double2int_rn(x.w) == 0 ? m0 : m1);
+  double v[3];
+  for (int c = 0; c < 3; ++c) v[c] = vel[3 * i + c] + 0.5 * dt * D.F[3 * i + c] * im;
+  x.x += dt * v[0]; x.y += dt * v[1]; x.z += dt * v[2];
+  for (int c = 0; c < 3; ++c) { vel[3 * i + c] = v[c]; D.F[3 * i + c] = 0; }
+  D.x[i] = x;
+  double4 xr = D.xref[i];
+  double ddx = x.x - xr.x, ddy = x.y - xr.y, ddz = x.z - xr.z;
+  if (ddx * ddx + ddy * ddy + ddz * ddz > half_skin2) atomicOr(D.flags, F_REBUILD);
 }
 
 __global__ void k_store(Dev D, double* pos) {
@@ -2690,7 +2723,13 @@ int setup(airebo_ctx* c, int nsys, const int64_t* off, const double* boxes, cons
   rc |= grow(c->acc, c->c_acc, NSLOT * A_N);
   rc |= grow(c->stats, c->c_st, S_N);
   rc |= grow(c->flags, c->c_fl, 4);
-  rc |= grow(c->step, c->c_stp, 4);
+  {
+    size_t had = c->c_stp;
+    rc |= grow(c->step, c->c_stp, 4);
+    // step counter and the last-block counters start at zero
+    if (!rc && c->c_stp != had && hipMemsetAsync(c->step, 0, 4 * sizeof(int), s) != hipSuccess)
+      rc |= fail(AIREBO_E_DEVICE, "clearing the step counters failed");
+  }
   rc |= grow(c->dsys, c->c_dsys, nsys);
   if (nsys > 1) {
     rc |= grow(c->atom_sys, c->c_asys, N);
@@ -2727,11 +2766,9 @@ inline int blocks(int64_t n, int t) { return (int)std::max<int64_t>(1, (n + t - 
 void launch_rebuild(airebo_ctx* c, hipStream_t s) {
   Dev& D = c->D;
   int ncell = c->ncell;
-  LAUNCH(c, K_BIN, k_bin, dim3(blocks(D.n, 256)), dim3(256), s, D);
-  LAUNCH(c, K_SCAN, k_scan, dim3(1), dim3(1024), s, D, ncell);
+  LAUNCH(c, K_BIN, k_bin, dim3(blocks(D.n, 1024)), dim3(1024), s, D, ncell);   // last block scans the counts
   LAUNCH(c, K_FILL, k_fill, dim3(blocks(D.n, 256)), dim3(256), s, D);
   LAUNCH(c, K_BUILD, k_build, dim3(blocks((int64_t)D.n * WAVE, 256)), dim3(256), s, D, (const DevParams*)c->dP);
-  LAUNCH(c, K_BUILD_DONE, k_build_done, dim3(1), dim3(64), s, D);
 }
 
 // Launch one force evaluation on the current positions.
@@ -2801,10 +2838,10 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
   };
   // Two streams.  The main stream runs the short list, the near LJ pairs
   // (they need the short list for the path maps) and the deferred pairs;
-  // after the near pairs the second stream runs the bonded terms and then
-  // the far LJ pairs beside them.  The latency-bound bonded and deferred
-  // kernels (one lane per bond or pair, one wavefront per SIMD) overlap each
-  // other and the far pairs; overlapping the near pairs slowed the step.
+  // after the short list the second stream runs the far LJ pairs (beside
+  // the near pairs) and then the bonded terms (beside the deferred pairs).
+  // The latency-bound bonded and deferred kernels (one lane per bond or
+  // pair, one wavefront per SIMD) overlap each other and the far pairs.
   // (The profiler's per-kernel events keep everything on one stream.)
   const bool two = !c->prof && lj && bonded;
   if (!two) {
@@ -2814,11 +2851,11 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
     if (lj) deferred_pairs(s);
   } else {
     short_list(s);
-    near_pairs(s);
     (void)hipEventRecord(c->ev_fork, s);
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    bond_terms(c->side);
     far_pairs(c->side);
+    bond_terms(c->side);
+    near_pairs(s);
     deferred_pairs(s);
   }
   if (two) {
@@ -3021,6 +3058,7 @@ int compute_static_impl(airebo_ctx_t c, int64_t n, const double* pos, const int3
   for (int attempt = 0; attempt < 3; ++attempt) {
     hipError_t e = hipMemsetAsync(D.stats, 0, S_N * sizeof(unsigned long long), s);
     if (e == hipSuccess) e = hipMemsetAsync(D.cell_count, 0, sizeof(int) * ncell, s);
+    if (e == hipSuccess) e = hipMemsetAsync(D.step, 0, 4 * sizeof(int), s);   // step and last-block counters
     if (e != hipSuccess) return done(fail(AIREBO_E_DEVICE, std::string("static clear: ") + hipGetErrorString(e)));
     hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, D, F_REBUILD);
     if (n > 0) {
@@ -3096,18 +3134,18 @@ void md_end_impl(airebo_ctx* c) {
 
 inline int thermo_block(int nsys) { return std::min(1024, std::max(64, ((nsys + 63) / 64) * 64)); }
 
-// One step: kick and drift, rebuild when flagged, forces, kick, thermo row.
+// One step: thermo row of the previous state, kick and drift, rebuild when
+// flagged, forces, kick.
 void md_step(airebo_ctx* c, hipStream_t s) {
   Dev& D = c->D;
   int64_t n = D.n;
   auto& md = c->md;
   double half_skin2 = 0.25 * c->opt.skin * c->opt.skin;
-  int kd_blocks = std::max(blocks(n, 256), blocks(NSLOT * A_N, 256));   // k_kick_drift also zeroes the sums
-  LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(kd_blocks), dim3(256), s, D, md.vel, md.m0, md.m1, md.dt, half_skin2);
+  LAUNCH(c, K_KICK_DRIFT, k_kick_drift, dim3(blocks(n, 256)), dim3(256), s, D, md.vel, md.m0, md.m1, md.dt, half_skin2,
+         (const MdCtl*)md.ctl);
   launch_rebuild(c, s);
   md.forces(s, false);
   LAUNCH(c, K_KICK, k_kick, dim3(blocks(n, 256)), dim3(256), s, D, md.vel, md.m0, md.m1, md.dt);
-  LAUNCH(c, K_THERMO, k_thermo, dim3(1), dim3(thermo_block(D.nsys)), s, D, (const MdCtl*)md.ctl);
 }
 
 // Forces and kinetic energy of the positions in the context (after a load or
@@ -3226,13 +3264,15 @@ int md_run_impl(airebo_ctx* c, int64_t nsteps, int64_t every, double* thermo, hi
   std::memcpy(md.hctl, &h, sizeof h);
   HIPCHK(hipMemcpyAsync(md.ctl, md.hctl, sizeof(MdCtl), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(c->step, 0, sizeof(int), s));
-  // row 0: the current state (its sums are those of the last evaluation)
-  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(thermo_block(D.nsys)), 0, s, D, (const MdCtl*)md.ctl);
+  // Each step's first kernel writes the row of the state before it (row 0:
+  // the current state, whose sums are those of the last evaluation); the
+  // row of the final state is written after the last step.
   if (c->prof) {   // per-kernel timing: eager launches, one event pair per kernel
     HIPCHK(hipStreamSynchronize(s));
     for (auto& e : c->ev) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     c->ev.clear();
     for (int64_t k = 0; k < nsteps; ++k) md_step(c, s);
+    hipLaunchKernelGGL(k_thermo, dim3(1), dim3(thermo_block(D.nsys)), 0, s, D, (const MdCtl*)md.ctl);
     int flags = 0;
     int rc = md_sync_flags(c, s, flags);
     if (rc) return rc;
@@ -3279,6 +3319,8 @@ int md_run_impl(airebo_ctx* c, int64_t nsteps, int64_t every, double* thermo, hi
     hipError_t e = md_capture(c);
     if (e != hipSuccess) return fail(AIREBO_E_DEVICE, std::string("md capture: ") + hipGetErrorString(e));
   }
+  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(thermo_block(D.nsys)), 0, cs, D, (const MdCtl*)md.ctl);
+  HIPCHK(hipStreamSynchronize(cs));
   return 0;
 }
 
