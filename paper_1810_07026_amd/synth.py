@@ -920,38 +920,64 @@ def _molecule(family, rng):
     return diamond_cluster(float(rng.uniform(2.5, 3.8)))
 
 
-def molecular_box(family, n_target, rng, density=0.05, min_side=13.0, min_dist=2.6, tries=200, image_gap=4.0):
+def molecular_box(family, n_target, rng, density=0.02, min_side=13.0, min_dist=2.6, tries=400, image_gap=4.0,
+                  n_max=None):
     """Molecules of one family at random positions and orientations in a
     periodic cube of side max((n/density)^(1/3), min_side, d + image_gap)
-    until ~n_target atoms, d being the first molecule's diameter.  Later
-    molecules wider than side - image_gap are rejected, so that no molecule
-    can reach its own periodic image whatever its orientation."""
+    until at least n_target atoms (at most max(1.1 n_target, n_target + 120),
+    and n_max), d being
+    the first molecule's diameter.  A molecule is placed at fresh random
+    positions and orientations until no atom comes within min_dist of an
+    atom already placed (bounding spheres first, atoms of the molecules
+    whose spheres overlap next); placement stops after `tries` failures in a
+    row.  Later molecules wider than side - image_gap are rejected, so that
+    no molecule can reach its own periodic image whatever its orientation."""
     L = max((n_target / density) ** (1.0 / 3.0), min_side)
     box = np.array([L, L, L])
     X = np.zeros((0, 3))
     S = np.zeros(0, np.int32)
+    cen, rad, rng_of = [], [], []   # placed molecules: centre, bounding radius, atom range
+    cap = max(1.1 * n_target, n_target + 120)   # room for one more molecule of any family
+    if n_max is not None:
+        cap = min(cap, n_max)
     fails = 0
+    mol = None
     while len(S) < n_target and fails < tries:
-        x, s = molecule(family, rng)
-        if len(S) + len(s) > 1.1 * n_target and len(S) > 0:
-            fails += 1
-            continue
-        diam = math.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1).max())
-        if diam > L - image_gap:
-            if len(S) > 0:
+        if mol is None:
+            x, s = molecule(family, rng)
+            if len(S) + len(s) > cap and len(S) > 0:
                 fails += 1
                 continue
-            L = diam + image_gap
-            box = np.array([L, L, L])
-        x = (x - x.mean(0)) @ _random_rotation(rng).T + rng.uniform(0, L, 3)
-        if len(S):
-            d = x[:, None, :] - X[None, :, :]
-            d -= box * np.round(d / box)
-            if (d * d).sum(-1).min() < min_dist ** 2:
-                fails += 1
-                continue
+            x = x - x.mean(0)
+            diam = math.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1).max())
+            if diam > L - image_gap:
+                if len(S) > 0:
+                    fails += 1
+                    continue
+                L = diam + image_gap
+                box = np.array([L, L, L])
+            mol = (x, s, math.sqrt((x * x).sum(1).max()))
+        x0, s0, r0 = mol
+        c = rng.uniform(0, L, 3)
+        x = x0 @ _random_rotation(rng).T + c
+        if cen:
+            dc = c - np.array(cen)
+            dc -= box * np.round(dc / box)
+            near = np.where(np.sqrt((dc * dc).sum(1)) < r0 + np.array(rad) + min_dist)[0]
+            if len(near):
+                idx = np.concatenate([np.arange(*rng_of[k]) for k in near])
+                d = x[:, None, :] - X[idx][None, :, :]
+                d -= box * np.round(d / box)
+                if (d * d).sum(-1).min() < min_dist ** 2:
+                    fails += 1
+                    continue
+        rng_of.append((len(S), len(S) + len(s0)))
+        cen.append(c)
+        rad.append(r0)
         X = np.vstack([X, x])
-        S = np.concatenate([S, s])
+        S = np.concatenate([S, s0])
+        mol = None
+        fails = 0
     return X % box, S, box
 
 
@@ -963,7 +989,7 @@ def batch_systems(nsys=512, nmin=50, nmax=5000, seed=SEED0 + 3, T=300.0):
     for k in range(nsys):
         fam = FAMILIES[k % len(FAMILIES)]
         n_target = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-        x, s, box = molecular_box(fam, n_target, rng)
+        x, s, box = molecular_box(fam, n_target, rng, n_max=nmax)
         xs.append(x); ss.append(s); boxes.append(box); sizes.append(len(s)); fams.append(fam)
         vs.append(maxwell_velocities(s, T, rng))
     return dict(x=np.vstack(xs), species=np.concatenate(ss), v=np.vstack(vs), boxes=np.array(boxes),
@@ -976,7 +1002,7 @@ def batch_cached(nsys=512, seed=SEED0 + 3):
         d = batch_systems(nsys, seed=seed)
         d["meta"] = {k: v for k, v in d["meta"].items() if k != "families"}
         return d
-    return cached(f"batch_{nsys}_s{seed}_r3", make)   # r3: saturated molecules only
+    return cached(f"batch_{nsys}_s{seed}_r4", make)   # r4: placement until the target size
 
 
 # ---- seeded initial weights of the surrogate networks (training inputs) ----

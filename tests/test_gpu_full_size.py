@@ -4,7 +4,7 @@
   GPU energy, every force and the virial against one full oracle evaluation,
   FP64 at the FP64 bar, mixed and single precision at their own bars.
 * The 25,600-atom nanotube bundle, each precision at its bar.
-* The 512-system batch (301,512 atoms) with the launch shapes the autotuner
+* The 512-system batch (565,367 atoms) with the launch shapes the autotuner
   cached for it: the smallest and the largest system of each family,
   taken whole from the batched result, against the oracle on that system
   alone, FP64, mixed and single.
