@@ -461,6 +461,7 @@ def surrogate_forms(nn, ctx, x0, v0, s, box, per, f_ref, steps, warmup, fp64_val
     sp = sp.cpu().numpy()
     rec = dict(force_err(f, f_ref), threshold_eVA=surrogate.THRESHOLD, max_spread_eVA=info["max_spread"],
                atoms_above_threshold=int((sp > surrogate.THRESHOLD).sum()))
+    rec["fallback_threshold_study"] = threshold_study(nn, ctx, x0, v0, s, box, per)
     for key, thr in (("with_fallback", surrogate.THRESHOLD), ("no_fallback", 1e30)):
         nn.md_begin(ctx, x0, v0, s, box, per, threshold=thr)
         ctx.md_run(warmup)
@@ -477,6 +478,34 @@ def surrogate_forms(nn, ctx, x0, v0, s, box, per, f_ref, steps, warmup, fp64_val
                     "fallback_steps": int(fb), "fallback_rate": fb / steps}
         log(f"bench: surrogate ({key}) {val:.4g} atom-steps/s, fallbacks {fb}/{steps}")
     return rec
+
+
+def threshold_study(nn, ctx, x0, v0, s, box, per, frames=20, stride=10):
+    """The ensemble's largest force spread per step along an FP64 AIREBO
+    trajectory from (x0, v0) (a frame every `stride` steps), with the
+    surrogate's force error against AIREBO on each frame: the threshold at
+    which fewer than 10% of the steps would fall back, and the error of the
+    steps it keeps."""
+    import torch
+    xt, vt = x0.clone(), v0.clone()
+    spreads, errs = [], []
+    for _ in range(frames):
+        ctx.nve(xt, vt, s, box, per, nsteps=stride, thermo_every=0)
+        _, fr, _ = ctx.compute(xt, s, box, per)
+        _, fs, _, sp, info = nn.compute(ctx, xt, s, box, per, threshold=1e30, want_spread=True)
+        spreads.append(float(info["max_spread"]))
+        errs.append(float(((fs - fr) ** 2).sum(1).mean().sqrt() / (fr ** 2).sum(1).mean().sqrt()))
+    spreads, errs = np.array(spreads), np.array(errs)
+    thr = float(np.quantile(spreads, 0.9))
+    keep = spreads <= thr
+    out = {"frames": frames, "stride_steps": stride,
+           "max_spread_eVA": {"min": float(spreads.min()), "median": float(np.median(spreads)),
+                              "max": float(spreads.max())},
+           "threshold_for_under_10pct_fallback_eVA": thr,
+           "fallback_rate_at_0.1_eVA": float((spreads > 0.1).mean()),
+           "force_rel_rms_err_of_kept_steps": float(errs[keep].mean())}
+    log(f"bench: surrogate spread study {json.dumps(out)}")
+    return out
 
 
 def hybrid_record(args):
