@@ -104,8 +104,25 @@ typedef struct {
                           MD session sizes the list; 0 = automatic (a quarter of the
                           largest row + 32)                                             */
   int32_t queue_per_atom; /* initial deferred-pair queue entries per atom; 0 = automatic (8) */
-  int32_t reserved;
+  int32_t schedule;    /* order of the force kernels on the two streams: AIREBO_SCHED_*   */
 } airebo_options;
+
+/* Force-kernel schedules (the main stream runs the short list, the near LJ
+ * pairs and the deferred pairs in that order; a second stream runs the far LJ
+ * pairs and the bonded terms):
+ *   AIREBO_SCHED_FAR_WITH_NEAR  the second stream starts after the short list,
+ *                               so the far pairs run beside the near pairs;
+ *   AIREBO_SCHED_FAR_AFTER_NEAR the second stream starts after the near pairs
+ *                               and runs the bonded terms, then the far pairs,
+ *                               beside the deferred pairs;
+ *   AIREBO_SCHED_AUTO           the second for an FP64 evaluation of one system
+ *                               of more than AIREBO_SCHED_AUTO_ATOMS atoms, the
+ *                               first otherwise (mixed and single precision,
+ *                               batches, small systems).
+ * The result does not depend on the schedule beyond the order of the force
+ * atomics. */
+enum { AIREBO_SCHED_AUTO = 0, AIREBO_SCHED_FAR_WITH_NEAR = 1, AIREBO_SCHED_FAR_AFTER_NEAR = 2 };
+#define AIREBO_SCHED_AUTO_ATOMS 50000
 
 void airebo_options_default(airebo_options* opt);
 

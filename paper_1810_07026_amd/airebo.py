@@ -48,9 +48,9 @@ class Options(ctypes.Structure):
                 ("lj_cap", ctypes.c_int32), ("device", ctypes.c_int32), ("bond_block", ctypes.c_int32),
                 ("bond_grid", ctypes.c_int32), ("defer_block", ctypes.c_int32), ("short_block", ctypes.c_int32),
                 ("vdw", ctypes.c_int32), ("lj_slack", ctypes.c_int32), ("queue_per_atom", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32)]
 
-    TUNABLES = ("bond_block", "bond_grid", "defer_block", "short_block")
+    TUNABLES = ("bond_block", "bond_grid", "defer_block", "short_block", "schedule")
     CAPACITIES = ("lj_slack", "queue_per_atom")
 
 

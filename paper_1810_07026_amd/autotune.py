@@ -1,10 +1,11 @@
 """Launch-shape autotuner for the AIREBO kernels.
 
 Tunables (airebo_options): threads per block of the bonded kernel (one
-wavefront: its LDS stage is sized for 64 threads), the size
-of its persistent grid, threads per block of the deferred-pair kernel and of
-the short-list kernel.  Tuning is a coordinate search: starting from the
-defaults, each tunable in turn is swept over its candidates with the others
+wavefront: its LDS stage is sized for 64 threads), the size of its
+persistent grid, threads per block of the deferred-pair kernel and of the
+short-list kernel, and the force-kernel schedule (0 automatic, 1 far LJ
+pairs beside the near pairs, 2 far pairs after them).  Tuning is a
+coordinate search: starting from the defaults, each tunable in turn is swept over its candidates with the others
 fixed, timing a short NVE run of the actual workload, and the best value is
 kept.  Results are cached in a JSON file keyed by GPU architecture, workload
 class (atom count and number of systems, rounded to powers of two) and
@@ -23,6 +24,7 @@ CANDIDATES = {
     "bond_grid": [0, 256, 512, 1024, 2048, 4096],
     "defer_block": [64],
     "short_block": [256, 512, 1024],
+    "schedule": [0, 1, 2],
 }
 
 

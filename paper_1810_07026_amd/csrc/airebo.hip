@@ -2491,6 +2491,8 @@ int check_options(const airebo_options& o) {
   if (!okb(o.bond_block) || !okb(o.defer_block) || !oks(o.short_block) || o.bond_grid < 0)
     return fail(AIREBO_E_ARG, "launch shapes: bond and deferred blocks 0 or 64 threads; "
                               "short-list block 0 or 256, 512, 1024 threads");
+  if (o.schedule < AIREBO_SCHED_AUTO || o.schedule > AIREBO_SCHED_FAR_AFTER_NEAR)
+    return fail(AIREBO_E_ARG, "unknown force-kernel schedule");
   return 0;
 }
 
@@ -2837,25 +2839,42 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
     else LAUNCH_SHM(c, K_BSTAR, (k_bstar<double, double, false>), gq, dim3(qblk), qblk * sh64, st, D, P);
   };
   // Two streams.  The main stream runs the short list, the near LJ pairs
-  // (they need the short list for the path maps) and the deferred pairs;
-  // after the short list the second stream runs the far LJ pairs (beside
-  // the near pairs) and then the bonded terms (beside the deferred pairs).
-  // The latency-bound bonded and deferred kernels (one lane per bond or
-  // pair, one wavefront per SIMD) overlap each other and the far pairs.
-  // (The profiler's per-kernel events keep everything on one stream.)
+  // (they need the short list for the path maps) and the deferred pairs; the
+  // second runs the far LJ pairs and the bonded terms, forked either after
+  // the short list (far pairs beside the near pairs, then the bonded terms
+  // beside the deferred pairs) or after the near pairs (bonded terms, then
+  // far pairs, both beside the deferred pairs).  Measured: in FP64 from about
+  // 5 x 10^4 atoms the two FP64 pair kernels side by side compete for the
+  // vector units and the second order is 1-2.5% faster; in mixed and single
+  // precision, for small systems and for batches of small systems (whose
+  // bonded and deferred work is latency-bound) the first is faster, by up to
+  // 13% on batches.  (The profiler's per-kernel events keep everything on one
+  // stream.)
   const bool two = !c->prof && lj && bonded;
+  int sched = c->opt.schedule;
+  if (sched == AIREBO_SCHED_AUTO)
+    sched = prec == AIREBO_FP64 && D.nsys == 1 && D.n > AIREBO_SCHED_AUTO_ATOMS ? AIREBO_SCHED_FAR_AFTER_NEAR
+                                                                              : AIREBO_SCHED_FAR_WITH_NEAR;
   if (!two) {
     short_list(s);
     if (lj) { near_pairs(s); far_pairs(s); }
     if (bonded) bond_terms(s);
     if (lj) deferred_pairs(s);
-  } else {
+  } else if (sched == AIREBO_SCHED_FAR_WITH_NEAR) {
     short_list(s);
     (void)hipEventRecord(c->ev_fork, s);
     (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     far_pairs(c->side);
     bond_terms(c->side);
     near_pairs(s);
+    deferred_pairs(s);
+  } else {
+    short_list(s);
+    near_pairs(s);
+    (void)hipEventRecord(c->ev_fork, s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    bond_terms(c->side);
+    far_pairs(c->side);
     deferred_pairs(s);
   }
   if (two) {

@@ -187,6 +187,33 @@ def test_far_pair_counts(ctxs):
     assert 2 * st["lj_in_cut_far"] <= st["lj_entries_far"] <= st["lj_entries"]
 
 
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_schedules_match_oracle(oracle, schedule):
+    """Both force-kernel schedules (far LJ pairs beside the near pairs, or
+    after them beside the deferred pairs) at the FP64 bar, for one evaluation
+    and for the captured MD step."""
+    import torch
+    from paper_1810_07026_amd import airebo
+    d = synth.tile(synth.pe_small(seed=synth.SEED0 + 17), (2, 2, 1))
+    d["x"] = d["x"] + np.random.default_rng(3).normal(scale=0.05, size=d["x"].shape)
+    ctx = airebo.Context(tune={"schedule": schedule})
+    try:
+        compare(run_gpu(ctx, d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"]), f"sched{schedule}")
+        x = torch.tensor(d["x"], dtype=torch.float64, device="cuda")
+        v = torch.tensor(d["v"], dtype=torch.float64, device="cuda")
+        ctx.nve(x, v, d["species"], d["box"], dt=0.5, nsteps=5, thermo_every=0)
+        xo, vo, _ = oracle.nve(d["x"], d["v"], d["species"], d["box"], dt=0.5, nsteps=5, thermo_every=5)
+        L = d["box"]
+        dx = x.cpu().numpy() - xo
+        dx -= L * np.round(dx / L)
+        assert np.abs(dx).max() < 1e-9 and np.abs(v.cpu().numpy() - vo).max() < 1e-9
+    finally:
+        ctx.close()
+    with pytest.raises(airebo.AireboError) as ex:
+        airebo.Context(tune={"schedule": 3})
+    assert ex.value.code == -1
+
+
 def test_nve_matches_oracle(oracle):
     """20 velocity-Verlet steps: GPU trajectory and thermo follow the oracle's."""
     import torch
