@@ -290,18 +290,24 @@ def record_or_error(make):
         return {"error": repr(e)}
 
 
-def timed_session(begin, ctx, n, steps, warmup, every=0):
+def timed_session(begin, ctx, n, steps, warmup, every=0, counts=None):
     """atom-steps/s of `steps` steps of an MD session: begin (untimed), warm-up
     run (untimed), then one timed run bracketed by device synchronisations.
-    Returns (atom-steps/s, ms/step, thermo rows of the timed run or None)."""
+    Returns (atom-steps/s, ms/step, thermo rows of the timed run or None);
+    `counts` (a dict), if given, receives the list rebuilds and capacity
+    regrowths of the timed run."""
     import torch
     begin()
     ctx.md_run(warmup)
     torch.cuda.synchronize()
+    s0 = ctx.stats() if counts is not None else None
     t0 = time.perf_counter()
     th = ctx.md_run(steps, thermo_every=every)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    if counts is not None:
+        s1 = ctx.stats()
+        counts.update(rebuilds=s1["rebuilds"] - s0["rebuilds"], regrowths=s1["regrowths"] - s0["regrowths"])
     return n * steps / sec, 1e3 * sec / steps, th
 
 
@@ -528,12 +534,13 @@ def hybrid_record(args):
     forces = {}
     for name, prec in (("fp64", airebo.FP64), ("mixed", airebo.MIXED)):
         c = airebo.Context(precision=prec)
-        val, ms, _ = timed_session(lambda: c.md_begin(x, v, s, box, per), c, n, args.extra_steps, 5)
+        cnt = {}
+        val, ms, _ = timed_session(lambda: c.md_begin(x, v, s, box, per), c, n, args.extra_steps, 5, counts=cnt)
         c.md_end()
         forces[name] = c.compute(x, s, box, per)[1].cpu().numpy()
         base = val if base is None else base
-        rec[name] = {"value": val, "ms_per_step": ms, "speedup_vs_fp64": val / base}
-        log(f"bench: hybrid {name} {val:.4g} atom-steps/s ({ms:.3f} ms/step)")
+        rec[name] = dict({"value": val, "ms_per_step": ms, "speedup_vs_fp64": val / base}, **cnt)
+        log(f"bench: hybrid {name} {val:.4g} atom-steps/s ({ms:.3f} ms/step), {cnt}")
         c.close()
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -575,10 +582,11 @@ def surrogate_record(args):
     f64 = ctx.compute(x, s, box, per)[1].cpu().numpy()
     fm = ctxm.compute(x, s, box, per)[1].cpu().numpy()
     for name, c in (("fp64", ctx), ("mixed", ctxm)):
-        val, ms, _ = timed_session(lambda: c.md_begin(x, v, s, box, per), c, n, steps, 5)
+        cnt = {}
+        val, ms, _ = timed_session(lambda: c.md_begin(x, v, s, box, per), c, n, steps, 5, counts=cnt)
         c.md_end()
-        rec[name] = {"value": val, "ms_per_step": ms}
-        log(f"bench: surrogate workload {name} {val:.4g} atom-steps/s ({ms:.3f} ms/step)")
+        rec[name] = dict({"value": val, "ms_per_step": ms}, **cnt)
+        log(f"bench: surrogate workload {name} {val:.4g} atom-steps/s ({ms:.3f} ms/step), {cnt}")
     rec["mixed"]["speedup_vs_fp64"] = rec["mixed"]["value"] / rec["fp64"]["value"]
     rec["mixed"].update(force_err(fm, f64))
     nn = airebo.Surrogate(path=surrogate.WEIGHTS)

@@ -66,6 +66,11 @@ static_assert(PCAP == 64, "one path candidate per lane when the lookup is filled
 __device__ __forceinline__ int hslot(int a) { return (int)(((unsigned)a * 2654435761u) >> 25); }   // 7 bits
 constexpr int LJ_BLOCK = 256;
 constexpr int WAVE = 64;
+// lanes per atom of the short-list kernel: an atom of a dense hydrocarbon has
+// about a dozen intermediate entries, so each lane takes about two; with
+// eight lanes the kernel's 110-register FP64 waves fit the device in one
+// round (with sixteen they took two)
+constexpr int SHORT_G = 8;
 
 // flag bits
 enum { F_REBUILD = 1, F_OV_SHORT = 2, F_OV_INT = 4, F_OV_LJ = 8, F_OV_PATH = 16, F_OV_BOND = 32, F_OV_QUEUE = 64,
@@ -1163,7 +1168,7 @@ __global__ __launch_bounds__(1024) void k_short(Dev D, const DevParams* __restri
   const DevParams& P = *Pp;
   // SG lanes per atom: lane `sub` of the group takes intermediate entries
   // sub, sub + SG, ...; the valid ones are compacted in entry order
-  constexpr int SG = 16;
+  constexpr int SG = SHORT_G;
   static_assert(WAVE % SG == 0 && SCAP_MAX % SG == 0, "short-list groups");
   // pair class of each short neighbour j > i of the block's atoms (-1: j < i),
   // read back by slot for the bond list
@@ -2809,9 +2814,9 @@ void launch_forces(airebo_ctx* c, hipStream_t s, bool zero = true) {
       else LAUNCH(c, K_LJF, (k_ljf<double, double, false, false>), glf, dim3(256), st, D, P);
     }
   };
-  auto short_list = [&](hipStream_t st) {   // 16 lanes per atom
-    if (single) LAUNCH(c, K_SHORT, k_short<true>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), st, D, P);
-    else LAUNCH(c, K_SHORT, k_short<false>, dim3(blocks((int64_t)D.n * 16, sblk)), dim3(sblk), st, D, P);
+  auto short_list = [&](hipStream_t st) {   // SHORT_G lanes per atom
+    if (single) LAUNCH(c, K_SHORT, k_short<true>, dim3(blocks((int64_t)D.n * SHORT_G, sblk)), dim3(sblk), st, D, P);
+    else LAUNCH(c, K_SHORT, k_short<false>, dim3(blocks((int64_t)D.n * SHORT_G, sblk)), dim3(sblk), st, D, P);
   };
   auto near_pairs = [&](hipStream_t st) {
     dim3 glj(blocks((int64_t)D.n * WAVE, LJ_BLOCK));
