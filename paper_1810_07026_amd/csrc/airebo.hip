@@ -1609,13 +1609,14 @@ __device__ __forceinline__ void vdw_pair_r2(const DevParams& P, int p, R r2, R& 
 // inside the S_r range) is deferred to a queue that k_bstar evaluates in
 // full.  Each pair is seen from both ends: each end adds half the energy and
 // virial and the full force on its own atom.
-// Minimum waves per SIMD asked of the compiler for the near LJ kernel:
-// single precision fits six (80 VGPRs) without spilling; FP64 and mixed
-// precision (FP64 sums) keep five; the Morse form (a square root and an
-// exponential more per pair) four, where five would spill.
+// Minimum waves per SIMD asked of the compiler for the near LJ kernel (the
+// wave-uniform atom data in scalar registers): FP64 and mixed precision fit
+// seven (72 and 64 VGPRs) without spilling, where eight would spill; single
+// precision eight (63 VGPRs); the Morse form (a square root and an
+// exponential more per pair) five (96 VGPRs).
 template <typename R, typename A, bool M>
 struct LjWaves {
-  static constexpr int value = M ? 4 : (std::is_same<A, float>::value ? 6 : 5);
+  static constexpr int value = M ? 5 : (std::is_same<A, float>::value ? 8 : 7);
 };
 
 template <typename R, typename A, bool M>
@@ -1643,11 +1644,13 @@ __global__ __launch_bounds__(LJ_BLOCK) __attribute__((amdgpu_waves_per_eu(LjWave
   int ndq = 0;
   int lane = threadIdx.x & (WAVE - 1);
   int wv = threadIdx.x / WAVE;
-  int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  // one atom per wavefront: the index is wave-uniform, and saying so keeps
+  // the atom's position, box, list base and count in scalar registers
+  int i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
   unsigned long long below = lanes_below();
   A e = 0;
   A fi[3] = {0, 0, 0}, W[6] = {0, 0, 0, 0, 0, 0};
-  unsigned long long n_in = 0, n_c0 = 0;
+  unsigned n_in = 0, n_c0 = 0;   // per-lane counts (at most the list length)
   int n_srch = 0;   // pairs of this wavefront sent to the sequential C_ij search
   if (i < D.n) {
     double4 xi = D.x[i];
