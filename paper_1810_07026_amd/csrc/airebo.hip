@@ -930,20 +930,25 @@ __global__ void k_bin(Dev D, int ncell) {
     atomicAdd(&D.cell_count[c], 1);
   }
   if (!last_block(D.step + 2)) return;
-  __shared__ int part[1024];
+  // block-wide exclusive scan of the per-thread sums: within each wavefront
+  // by shuffles, then over the wavefront totals
+  __shared__ int wtot[1024 / WAVE];
   int t = threadIdx.x, nt = blockDim.x;
   int per = (ncell + nt - 1) / nt;
   int lo = t * per, hi = min(ncell, lo + per);
   int sum = 0;
   for (int c = lo; c < hi; ++c) sum += D.cell_count[c];
-  part[t] = sum;
-  __syncthreads();
-  if (t == 0) {
-    int run = 0;
-    for (int q = 0; q < nt; ++q) { int v = part[q]; part[q] = run; run += v; }
+  const int lane = t & (WAVE - 1), w = t / WAVE;
+  int incl = sum;
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
   }
+  if (lane == WAVE - 1) wtot[w] = incl;
   __syncthreads();
-  int run = part[t];
+  int wbase = 0;
+  for (int q = 0; q < w; ++q) wbase += wtot[q];
+  int run = wbase + incl - sum;
   for (int c = lo; c < hi; ++c) {
     D.cell_start[c] = run;
     D.cell_cursor[c] = run;
@@ -984,13 +989,23 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
   __shared__ unsigned s_code[4][NSTEN];     // image shift code of the cell
   int lane = threadIdx.x & (WAVE - 1);
   int wv = threadIdx.x / WAVE;
-  int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  // one atom per wavefront (wave-uniform index: the atom's data in scalar registers)
+  int i = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
   if (i >= D.n) return;
   double4 xi = D.x[i];
   int si = __double2int_rn(xi.w);
   const SysBox& B = box_of(D, i);
   int ci[3] = {cell_coord(xi.x, B.invL[0], B.nc[0]), cell_coord(xi.y, B.invL[1], B.nc[1]),
                cell_coord(xi.z, B.invL[2], B.nc[2])};
+  // Cells whose box lies farther from the atom than the list cutoff (plus a
+  // margin far above rounding) hold no candidate and are dropped: about 40%
+  // of the stencil.  A wrapped atom lies in its cell's box; on a
+  // non-periodic axis the edge cells also hold the atoms beyond the box
+  // (cell_coord clamps), so they are unbounded outward.
+  const double xa[3] = {xi.x, xi.y, xi.z};
+  double hc[3];
+  for (int c = 0; c < 3; ++c) hc[c] = B.L[c] / B.nc[c];
+  const double rcut = sqrt(fmax(D.rlist2[0], fmax(D.rlist2[1], D.rlist2[2]))) + 0.01;
   int run = 0;   // candidates of the cells before this group of 64
   for (int o0 = 0; o0 < NSTEN; o0 += WAVE) {
     int o = o0 + lane;
@@ -1013,6 +1028,16 @@ __global__ __launch_bounds__(256) void k_build(Dev D, const DevParams* __restric
         }
       }
       code = (unsigned)((sh[0] + 1) * 9 + (sh[1] + 1) * 3 + (sh[2] + 1));
+      double g2 = 0.0;   // squared distance from the atom to the cell's box (image frame)
+      for (int c = 0; c < 3; ++c) {
+        int u = ci[c] + off[c];
+        double lo = u * hc[c], hi = lo + hc[c];
+        if (!B.per[c] && u == 0) lo = -INFINITY;
+        if (!B.per[c] && u == B.nc[c] - 1) hi = INFINITY;
+        double g = fmax(0.0, fmax(lo - xa[c], xa[c] - hi));
+        g2 += g * g;
+      }
+      if (g2 > rcut * rcut) skip = true;
       if (!skip) {
         int cell = B.cell_off + (cc[0] * B.nc[1] + cc[1]) * B.nc[2] + cc[2];
         start = D.cell_start[cell];
