@@ -114,6 +114,20 @@ def test_tiled_medium(ctxs, oracle):
     compare(run_gpu(ctxs[7], d), oracle.compute(d["x"], d["species"], d["box"], d["periodic"]), "tiled")
 
 
+def test_atoms_outside_nonperiodic_box(ctxs, oracle):
+    """Positions may lie outside a non-periodic side (they are binned into
+    its edge cells): the 248-atom system with y and z non-periodic in an
+    8 A box, shifted so that most atoms lie below 0 or above 8 A; the list
+    build (which drops stencil cells beyond the cutoff) must find every pair."""
+    d = synth.pe_small(seed=synth.SEED0 + 17)
+    x = d["x"] + np.array([0.0, -6.0, -6.0])
+    box = np.array([d["box"][0], 8.0, 8.0])
+    per = np.array([1, 0, 0], np.int32)
+    assert (x[:, 1] < 0).sum() > 30 and (x[:, 1] > 8).sum() > 30 and (x[:, 2] > 8).sum() > 30
+    dd = dict(x=x, species=d["species"], box=box, periodic=per)
+    compare(run_gpu(ctxs[7], dd), oracle.compute(x, d["species"], box, per), "outside")
+
+
 def test_edge_cases(ctxs, oracle):
     from paper_1810_07026_amd import airebo
     c = ctxs[7]
