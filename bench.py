@@ -24,11 +24,15 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK = 78.6e12      # MI355X vector FP64, FLOP/s
 FP32_VALU_PEAK = 157.3e12
 # Algorithmic FP64 operations per unit of work of each kernel: per LJ pair
-# inside the cutoff (each pair once), per list pair beyond it, and per REBO
-# bond (bond order forward + reverse, pair term, torsion).
+# inside the cutoff (each pair once), per list pair beyond it, per REBO bond
+# (bond order forward + reverse, pair term, torsion), and per deferred pair
+# (the b* bond order forward: half the bond's bond-order work; its reverse,
+# the other half, only where dS_b != 0).
 FLOP_PER_LJ_PAIR = 45       # per pair inside its cutoff, each pair once
 FLOP_PER_SKIN_PAIR = 8      # per list pair beyond its cutoff (distance test)
 FLOP_PER_BOND = 4000
+FLOP_PER_BSTAR_FWD = 2000   # per deferred pair
+FLOP_PER_BSTAR_REV = 2000   # per deferred pair with dS_b != 0
 # untimed preparation of the melt: capped steepest descent, then rescaled NVE
 PREP_SD_ITERS, PREP_SD_ALPHA, PREP_SD_CAP = 300, 0.01, 0.02     # iterations, A^2/eV, A
 PREP_EQ_CYCLES, PREP_EQ_STEPS = 20, 50
@@ -272,7 +276,7 @@ def main():
         "energy_drift": {"slope_eV_per_atom_per_ps": slope, "max_rel": maxrel, "rebuilds": rebuilds,
                          "T_start_K": float(th[0, 4]), "T_end_K": float(th[-1, 4])},
         "work": {k: st[k] for k in ("lj_in_cut", "lj_in_cut_far", "lj_entries", "lj_entries_far", "cij_zero",
-                                    "bstar_queued", "dsb_nonzero", "bonds")},
+                                    "bstar_queued", "deferred_pairs", "dsb_nonzero", "bonds")},
         "kernels_us": {k: round(v_["avg_us"], 3) for k, v_ in kern.items()},
         "forms": forms,
     }
@@ -317,17 +321,19 @@ def kernel_work(st):
     (within 3 max R2 + skin: k_lj) and far pairs (k_ljf): 45 flop per pair
     inside its cutoff, 8 per list pair outside it (distance test only).
     The bonded kernel: 4,000 flop per bond (forward and reverse bond order,
-    pair term, torsion)."""
+    pair term, torsion).  The deferred-pair kernel: 2,000 flop per deferred
+    pair (b* forward) and 2,000 more per pair with dS_b != 0 (reverse)."""
     far_in, far_pairs = st["lj_in_cut_far"], st["lj_entries_far"] // 2
     near_in, near_pairs = st["lj_in_cut"] - far_in, (st["lj_entries"] - st["lj_entries_far"]) // 2
     return {"k_lj": FLOP_PER_LJ_PAIR * near_in + FLOP_PER_SKIN_PAIR * max(near_pairs - near_in, 0),
             "k_ljf": FLOP_PER_LJ_PAIR * far_in + FLOP_PER_SKIN_PAIR * max(far_pairs - far_in, 0),
-            "k_bond": FLOP_PER_BOND * st["bonds"]}
+            "k_bond": FLOP_PER_BOND * st["bonds"],
+            "k_bstar": FLOP_PER_BSTAR_FWD * st["deferred_pairs"] + FLOP_PER_BSTAR_REV * st["dsb_nonzero"]}
 
 
 def roofline(kern, st, prec, args, peaks=None):
     """Roofline record of the kernel with a work model that takes the most
-    time per step (the near-pair LJ kernel on the melt), against the
+    time per step (the deferred-pair kernel on the melt), against the
     published vector peak of the arithmetic type and against the measured
     FMA-loop peak; the other modelled kernels in `kernels`."""
     from paper_1810_07026_amd import airebo
