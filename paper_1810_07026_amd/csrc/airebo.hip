@@ -288,6 +288,38 @@ __device__ __forceinline__ R gfun(const DevParams& P, int sc, R c, R N, R& dc, R
   dN = dQ * (gam - G);
   return G + Qn * (gam - G);
 }
+// The same quintic spline in FP64 without branches (clamped argument,
+// interval found by counting the interior knots below it: the knots
+// increase), so that several evaluations can run as independent chains.
+__device__ __forceinline__ double gspl_nb(const GSpline& g, double x, double& d) {
+  const double x0 = g.x[0], xn = g.x[g.n - 1];
+  const bool clamped = x <= x0 || x >= xn;
+  x = fmin(fmax(x, x0), xn);
+  int m = 0;
+#pragma unroll
+  for (int k = 1; k + 1 < kMaxKnots; ++k) m += (k + 1 < g.n && x > g.x[k]) ? 1 : 0;
+  const double t = (x - g.x[m]) * g.inv_h[m];
+  const double* c = g.c[m];
+  double v = c[5], dv = 0.0;
+  for (int q = 4; q >= 0; --q) { dv = dv * t + v; v = v * t + c[q]; }
+  d = clamped ? 0.0 : dv * g.inv_h[m];
+  return v;
+}
+// g_i(cos theta) as gfun, FP64, without branches; Qn, dQ: the blend weight
+// of the centre's coordination (cosstep of N over [gC_lo, gC_hi]).
+__device__ __forceinline__ double gfun_nb(const DevParams& P, int sc, double c, double Qn, double dQ, double& dc,
+                                          double& dN, int* st) {
+  double dG;
+  const double G = gspl_nb(sc == 1 ? P.gH : P.gC, c, dG);
+  double dgam;
+  const double gam = gspl_nb(P.gammaC, c, dgam);
+  const bool blend = sc == 0 && c > P.gammaC.x[0] && !(Qn == 0.0 && dQ == 0.0);
+  st[0] += blend ? 2 : 1;
+  dc = blend ? dG + Qn * (dgam - dG) : dG;
+  dN = blend ? dQ * (gam - G) : 0.0;
+  return blend ? G + Qn * (gam - G) : G;
+}
+
 // Bicubic P_{C s_j}(N^C, N^H) with partials.
 template <typename R>
 __device__ __forceinline__ R bicubic(const double (*Pc)[4][16], R x, R y, R& dx, R& dy, int* st, double kd) {
@@ -616,11 +648,14 @@ struct Stage {
 template <typename R>
 struct EndF {
   R NC, NH, N, S, P, dPC, dPH, p, conj, SdN;
+  // FP64: g, dg/dcos and dg/dN of the staged neighbours (slot q < NB),
+  // evaluated together by gslots and reused by the reverse pass
+  R g[NB], dgc[NB], dgN[NB];
 };
 
-template <typename R>
-__device__ void end_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG, int ee, int sc, int o, int so, V3<R> rco,
-                        R rlen, R rlam, EndF<R>& e, int* st) {
+// Coordination of end e without its partner o: N^C, N^H and N.
+template <typename R, typename SGT>
+__device__ void end_n(const Dev& D, const SGT& SG, int ee, int o, EndF<R>& e) {
   const int n = SG.len(ee);
   R NC = 0, NH = 0;
   for (int q = 0; q < n; ++q) {
@@ -628,18 +663,47 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG, in
     if (b.k == o) continue;
     if (b.s == 0) NC += b.w; else NH += b.w;
   }
-  R N = NC + NH;
+  e.NC = NC; e.NH = NH; e.N = NC + NH;
+}
+
+// The angular splines of every staged neighbour of both ends (FP64), as
+// 2 NB independent chains; slots beyond an end's list are left at zero.
+template <typename SGT>
+__device__ void gslots(const DevParams& P, const Dev& D, const SGT& SG, int i, int j, int si, int sj, V3<double> rij,
+                       double r, EndF<double>& ei, EndF<double>& ej, int* st) {
+  const double ir = rcp_nr(r);
+  double Q[2], dQ[2];
+  Q[0] = cosstep(ei.N, P.gC_lo, P.gC_hi, dQ[0]);
+  Q[1] = cosstep(ej.N, P.gC_lo, P.gC_hi, dQ[1]);
+#pragma unroll
+  for (int u = 0; u < 2 * NB; ++u) {
+    const int e = u / NB, q = u % NB;
+    EndF<double>& ef = e ? ej : ei;
+    const Nb<double> b = SG.get(D, e, q);
+    const bool valid = q < SG.len(e) && b.k != (e ? i : j);
+    const double sgn = e ? -1.0 : 1.0;
+    const double cth = sgn * dot(rij, b.d) * (ir * rcp_nr(b.r));
+    double dc, dN;
+    int stq[1] = {0};
+    const double g = gfun_nb(P, e ? sj : si, cth, Q[e], dQ[e], dc, dN, stq);
+    if (valid) st[0] += stq[0];
+    ef.g[q] = valid ? g : 0.0;
+    ef.dgc[q] = valid ? dc : 0.0;
+    ef.dgN[q] = valid ? dN : 0.0;
+  }
+}
+
+template <typename R>
+__device__ void end_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG, int ee, int sc, int o, int so, V3<R> rco,
+                        R rlen, R rlam, EndF<R>& e, int* st) {
+  // e.NC, e.NH, e.N from end_n; in FP64 the staged neighbours' splines from gslots
+  const int n = SG.len(ee);
+  const R NC = e.NC, NH = e.NH, N = e.N;
   R S = 0, conj = 0, SdN = 0;
   const R irlen = rcp_nr(rlen);
-  for (int q = 0; q < n; ++q) {
-    const Nb<R> b = SG.get(D, ee, q);
-    if (b.k == o) continue;
+  auto term = [&](const Nb<R>& b, R g, R dgN) {
     const int sk = b.s;
     const R r = b.r, w = b.w;
-    const V3<R> d = b.d;
-    R cth = dot(rco, d) * (irlen * rcp_nr(r));
-    R dgc, dgN;
-    R g = gfun(P, sc, cth, N, dgc, dgN, st);
     R el = 1;
     if (sc == 1) el = xexp((R)P.lambda_pref * (((R)P.rho[sk] - r) - ((R)P.rho[so] - rlam)));
     S += w * g * el;
@@ -649,10 +713,29 @@ __device__ void end_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG, in
       R dF;
       conj += w * cosstep(xk, P.conj_lo, P.conj_hi, dF);
     }
+  };
+  int q0 = 0;
+  if constexpr (std::is_same<R, double>::value) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (q < n) {
+        const Nb<R> b = SG.get(D, ee, q);
+        if (b.k != o) term(b, e.g[q], e.dgN[q]);
+      }
+    }
+    q0 = NB;
+  }
+  for (int q = q0; q < n; ++q) {
+    const Nb<R> b = SG.get(D, ee, q);
+    if (b.k == o) continue;
+    R cth = dot(rco, b.d) * (irlen * rcp_nr(b.r));
+    R dgc, dgN;
+    R g = gfun(P, sc, cth, N, dgc, dgN, st);
+    term(b, g, dgN);
   }
   R Pv = 0, dPC = 0, dPH = 0;
   if (sc == 0) Pv = bicubic(P.Pc[so], NC, NH, dPC, dPH, st, P.knot_delta);
-  e.NC = NC; e.NH = NH; e.N = N; e.S = S; e.P = Pv; e.dPC = dPC; e.dPH = dPH;
+  e.S = S; e.P = Pv; e.dPC = dPC; e.dPH = dPH;
   e.p = rsq_nr((R)1 + S + Pv);
   e.conj = conj;
   e.SdN = SdN;
@@ -670,18 +753,14 @@ __device__ void end_rev(const DevParams& P, const Dev& D, const Stage<R>& SG, in
   R GNC = GS * e.dPC + GNt, GNH = GS * e.dPH + GNt;
   R Grlen = 0;
   const R irlen = rcp_nr(rlen);
-  for (int q = 0; q < n; ++q) {
-    const Nb<R> b = SG.get(D, ee, q);
+  auto term = [&](const Nb<R>& b, R g, R dgc) {
     const int k = b.k;
-    if (k == o) continue;
     const int sk = b.s;
     const R r = b.r, w = b.w, dw = b.dw;
     const V3<R> d = b.d;
     const R ir = rcp_nr(r);
     R inv = irlen * ir;
     R cth = dot(rco, d) * inv;
-    R dgc, dgN;
-    R g = gfun(P, sc, cth, e.N, dgc, dgN, acc.st);
     R el = 1;
     R Gr = 0;
     if (sc == 1) {
@@ -714,6 +793,25 @@ __device__ void end_rev(const DevParams& P, const Dev& D, const Stage<R>& SG, in
     V3<R> gk = (Gr * ir) * d + Gcos * (inv * rco - (cth * ir * ir) * d);
     gco = gco + Gcos * (inv * d - (cth * irlen * irlen) * rco);
     acc.vec(c, k, d, gk);
+  };
+  int q0 = 0;
+  if constexpr (std::is_same<R, double>::value) {   // the forward pass's slot splines
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (q < n) {
+        const Nb<R> b = SG.get(D, ee, q);
+        if (b.k != o) term(b, e.g[q], e.dgc[q]);
+      }
+    }
+    q0 = NB;
+  }
+  for (int q = q0; q < n; ++q) {
+    const Nb<R> b = SG.get(D, ee, q);
+    if (b.k == o) continue;
+    R cth = dot(rco, b.d) * (irlen * rcp_nr(b.r));
+    R dgc, dgN;
+    R g = gfun(P, sc, cth, e.N, dgc, dgN, acc.st);
+    term(b, g, dgc);
   }
   gco = gco + (Grlen * irlen) * rco;
 }
@@ -809,6 +907,9 @@ __device__ R bond_order_fwd(const DevParams& P, const Dev& D, const Stage<R>& SG
   f.si = si; f.sj = sj;
   f.rlam = (bstar && P.bstar_use_R1) ? (R)P.R1[p] : r;
   V3<R> rji = -rij;
+  end_n(D, SG, 0, j, f.ei);
+  end_n(D, SG, 1, i, f.ej);
+  if constexpr (std::is_same<R, double>::value) gslots(P, D, SG, i, j, si, sj, rij, r, f.ei, f.ej, st);
   end_fwd(P, D, SG, 0, si, j, sj, rij, r, f.rlam, f.ei, st);
   end_fwd(P, D, SG, 1, sj, i, si, rji, r, f.rlam, f.ej, st);
   R Nconj = (R)1 + f.ei.conj * f.ei.conj + f.ej.conj * f.ej.conj;
