@@ -461,6 +461,10 @@ int airebo_nn_load(const char* path, int32_t device, airebo_nn_t* out);
  * device matrices.  The inputs are rounded to BF16 and the products
  * accumulated in FP32.  Asynchronous on `stream`. */
 int airebo_nn_mfma_check(const float* A, const float* B, float* D, void* stream);
+/* The same for the 16x16x32 BF16 tile the networks use for full 32-deep
+ * slices: D [16][16] = A [16][32] B [32][16], row-major FP32 device matrices
+ * rounded to BF16, FP32 accumulation.  Asynchronous on `stream`. */
+int airebo_nn_mfma32_check(const float* A, const float* B, float* D, void* stream);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* airebo_last_error(void);

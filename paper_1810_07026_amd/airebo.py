@@ -30,7 +30,7 @@ EXPORTS = ["airebo_options_default", "airebo_ctx_create", "airebo_ctx_free", "ai
            "airebo_nn_get_params", "airebo_nn_get_grad", "airebo_nn_set_norm", "airebo_nn_get_norm",
            "airebo_nn_moments", "airebo_nn_descriptors", "airebo_nn_descriptor_jvp", "airebo_nn_descriptor_vjp",
            "airebo_nn_compute", "airebo_nn_gradient", "airebo_nn_adam", "airebo_nn_nve", "airebo_nn_profile_nve",
-           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check", "airebo_peak_copy", "airebo_peak_fma",
+           "airebo_nn_save", "airebo_nn_load", "airebo_nn_mfma_check", "airebo_nn_mfma32_check", "airebo_peak_copy", "airebo_peak_fma",
            "airebo_params_load", "airebo_params_parse", "airebo_params_free", "airebo_ctx_create_from_params",
            "airebo_compute_host", "airebo_nn_train_step",
            "airebo_md_begin", "airebo_batch_md_begin", "airebo_md_run", "airebo_md_state", "airebo_md_end",
@@ -157,6 +157,7 @@ def load_library(path=LIB_PATH):
         "airebo_nn_save": [vp, ctypes.c_char_p],
         "airebo_nn_load": [ctypes.c_char_p, c_i32, ctypes.POINTER(ctypes.c_void_p)],
         "airebo_nn_mfma_check": [dp, dp, dp, vp],
+        "airebo_nn_mfma32_check": [dp, dp, dp, vp],
         "airebo_peak_copy": [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp],
         "airebo_peak_fma": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp],
     }
@@ -674,6 +675,19 @@ def mfma_check(A, B):
     B = B.contiguous()
     _check(L, L.airebo_nn_mfma_check(_p(A), _p(B), _p(D),
                                       ctypes.c_void_p(torch.cuda.current_stream(A.device).cuda_stream)))
+    return D
+
+
+def mfma32_check(A, B):
+    """D = A B for FP32 device matrices A [16][32], B [32][16] through the
+    library's 16x16x32 matrix-core tile."""
+    import torch
+    L = load_library()
+    D = torch.empty((16, 16), dtype=torch.float32, device=A.device)
+    A = A.contiguous()
+    B = B.contiguous()
+    _check(L, L.airebo_nn_mfma32_check(_p(A), _p(B), _p(D),
+                                        ctypes.c_void_p(torch.cuda.current_stream(A.device).cuda_stream)))
     return D
 
 

@@ -44,7 +44,7 @@ constexpr int OW1 = 0, OB1 = OW1 + HID * DIM, OW2 = OB1 + HID, OB2 = OW2 + HID *
 // accumulators of the surrogate (doubles, NSLOT copies)
 enum { N_E = 0, N_EFAR = 4, N_VIR = 5, N_LOSSF = 11, N_A = 16 };
 // padded LDS row strides (BF16 elements) against bank conflicts
-constexpr int SD = DIM + 4, SH = HID + 4;
+constexpr int SD = DIM + 8, SH = HID + 8;   // LDS row strides: 16-byte rows for 8-element loads
 constexpr float RAD_H = 5.2f / 31.0f;
 constexpr float RAD_ETA = 1.0f / (2.0f * (2.0f * RAD_H) * (2.0f * RAD_H));
 
@@ -546,14 +546,21 @@ __global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __r
 }
 
 // ---------------------------------------------------------------------------
-// Network tiles on MFMA 16x16x16 BF16.  Lane l holds A[l % 16][4 (l / 16) + v],
-// B[4 (l / 16) + v][l % 16] and D[4 (l / 16) + v][l % 16], v = 0..3.
+// Network tiles on the BF16 matrix cores: MFMA 16x16x32 (gfx950) for every
+// full 32-deep slice of K, 16x16x16 for a 16-deep remainder.  16x16x32: lane
+// l holds A[l % 16][8 (l / 16) + v] and B[8 (l / 16) + v][l % 16], v = 0..7;
+// 16x16x16: A[l % 16][4 (l / 16) + v] and B[4 (l / 16) + v][l % 16],
+// v = 0..3; both give D[4 (l / 16) + v][l % 16], v = 0..3.
 // ---------------------------------------------------------------------------
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // D = A B for one 16x16 tile (A, B row-major FP32, rounded to BF16): a check
@@ -567,6 +574,19 @@ __global__ void k_mfma_check(const float* __restrict__ A, const float* __restric
   }
   f32x4 d = {0, 0, 0, 0};
   d = mfma(a, b, d);
+  for (int v = 0; v < 4; ++v) Dout[(4 * (l / 16) + v) * 16 + l % 16] = d[v];
+}
+
+// The same for the 16x16x32 tile: A [16][32], B [32][16] row-major FP32.
+__global__ void k_mfma32_check(const float* __restrict__ A, const float* __restrict__ B, float* __restrict__ Dout) {
+  int l = threadIdx.x;
+  bf16x8 a, b;
+  for (int v = 0; v < 8; ++v) {
+    a[v] = __builtin_bit_cast(__bf16, f2bf(A[(l % 16) * 32 + 8 * (l / 16) + v]));
+    b[v] = __builtin_bit_cast(__bf16, f2bf(B[(8 * (l / 16) + v) * 16 + l % 16]));
+  }
+  f32x4 d = {0, 0, 0, 0};
+  d = mfma32(a, b, d);
   for (int v = 0; v < 4; ++v) Dout[(4 * (l / 16) + v) * 16 + l % 16] = d[v];
 }
 
@@ -604,16 +624,26 @@ __device__ void load_net(NetLDS& N, const float* __restrict__ P, int t, int nt) 
 // stride SX), both BF16 in LDS.  y[ct][v] = Y[4 (l / 16) + v][16 ct + l % 16].
 template <int K, int NO, int SX, int SW>
 __device__ __forceinline__ void mm(const unsigned short* X, const unsigned short* W, f32x4 (&y)[NO / 16]) {
+  static_assert(K % 16 == 0 && (SX * 2) % 16 == 0 && (SW * 2) % 16 == 0, "tile shapes and 16-byte rows");
   int l = threadIdx.x & (WAVE - 1);
-  int row = l % 16, kg = 4 * (l / 16);
+  int row = l % 16, g = l / 16;
 #pragma unroll
   for (int ct = 0; ct < NO / 16; ++ct) y[ct] = f32x4{0, 0, 0, 0};
 #pragma unroll
-  for (int kt = 0; kt < K / 16; ++kt) {
-    bf16x4 a = *reinterpret_cast<const bf16x4*>(X + row * SX + kt * 16 + kg);
+  for (int kt = 0; kt < K / 32; ++kt) {
+    bf16x8 a = *reinterpret_cast<const bf16x8*>(X + row * SX + kt * 32 + 8 * g);
 #pragma unroll
     for (int ct = 0; ct < NO / 16; ++ct) {
-      bf16x4 b = *reinterpret_cast<const bf16x4*>(W + (ct * 16 + row) * SW + kt * 16 + kg);
+      bf16x8 b = *reinterpret_cast<const bf16x8*>(W + (ct * 16 + row) * SW + kt * 32 + 8 * g);
+      y[ct] = mfma32(a, b, y[ct]);
+    }
+  }
+  if constexpr (K % 32 == 16) {   // the last 16 of K
+    constexpr int k0 = K - 16;
+    bf16x4 a = *reinterpret_cast<const bf16x4*>(X + row * SX + k0 + 4 * g);
+#pragma unroll
+    for (int ct = 0; ct < NO / 16; ++ct) {
+      bf16x4 b = *reinterpret_cast<const bf16x4*>(W + (ct * 16 + row) * SW + k0 + 4 * g);
       y[ct] = mfma(a, b, y[ct]);
     }
   }
@@ -1708,6 +1738,13 @@ int airebo_nn_load(const char* path, int32_t device, airebo_nn_t* out) {
 int airebo_nn_mfma_check(const float* A, const float* B, float* Dout, void* stream) {
   if (!A || !B || !Dout) return fail(AIREBO_E_ARG, "null argument");
   hipLaunchKernelGGL(k_mfma_check, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, Dout);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int airebo_nn_mfma32_check(const float* A, const float* B, float* Dout, void* stream) {
+  if (!A || !B || !Dout) return fail(AIREBO_E_ARG, "null argument");
+  hipLaunchKernelGGL(k_mfma32_check, dim3(1), dim3(64), 0, (hipStream_t)stream, A, B, Dout);
   HIPCHK(hipGetLastError());
   return 0;
 }

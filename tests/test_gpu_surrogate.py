@@ -91,6 +91,17 @@ def test_mfma_lane_layout(lib):
     assert np.abs(D - want).max() <= 1e-5 * np.abs(want).max()
 
 
+def test_mfma32_lane_layout(lib):
+    """The 16x16x32 BF16 tile (gfx950) the networks use for full 32-deep
+    slices of K."""
+    rng = np.random.default_rng(1)
+    A = rng.normal(size=(16, 32)).astype(np.float32)
+    B = rng.normal(size=(32, 16)).astype(np.float32)
+    D = lib.mfma32_check(torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda")).cpu().numpy()
+    want = bf16(A) @ bf16(B)
+    assert np.abs(D - want).max() <= 1e-5 * np.abs(want).max()
+
+
 @pytest.mark.parametrize("name", list(SYS))
 def test_descriptors(lib, ctx, name):
     x, s, box, per = SYS[name]
