@@ -11,26 +11,28 @@
 // GPU design (one process, one device; everything stays in HBM):
 //   rebuild (when any atom moved more than half the skin):
 //     k_bin / k_fill             counting sort of atoms into cells >= half of LJ cutoff + skin
-//     k_build                    one wavefront per atom: full LJ list (with image
-//                                shift codes) and the intermediate REBO list
-//                                (R2 + skin), both filled by wave-ballot compaction
+//     k_build                    one wavefront per atom: LJ list (with image shift
+//                                codes) split into near pairs (within 3 max R2 +
+//                                skin) and far pairs, and the intermediate REBO
+//                                list (R2 + skin), filled by wave-ballot compaction
 //                                (the vectorised list insertion of Sec. 4.1)
 //   every step:
 //     k_short                    exact short list from the intermediate list,
 //                                w, dw/dr, coordination N^C, N^H; species-bucketed
 //                                bond list (CC / CH / HH batches, Sec. 4.2)
-//     k_bond                     one lane per bond: bond order, REBO pair term and
-//                                torsion merged (Sec. 4.2), forward then reverse;
-//                                runs on a second stream beside the LJ chain
 //     k_lj                       one wavefront per atom: first the atom's path map
 //                                in LDS (every atom reachable over <= 3 short bonds
 //                                with its weight product and path: the reversed
-//                                C_ij search of Sec. 4.3), then the full LJ list:
-//                                far pairs (r >= 3 max R2) are plain LJ; near pairs
-//                                look up C_ij; pairs with 0 < C_ij < 1 or inside the
-//                                S_r range are deferred to a queue (Sec. 4.3)
+//                                C_ij search of Sec. 4.3), then its near pairs:
+//                                look up C_ij; pairs with 0 < C_ij < 1 or inside
+//                                the S_r range are deferred to a queue (Sec. 4.3)
 //     k_bstar                    one lane per queued pair: C_ij, b*, S_b, full
 //                                gradient
+//     k_ljf                      16 lanes per atom: the far pairs, plain LJ
+//     k_bond                     one lane per bond: bond order, REBO pair term and
+//                                torsion merged (Sec. 4.2), forward then reverse
+//   The main stream runs k_short, k_lj, k_bstar; a second stream runs k_ljf
+//   and k_bond beside them (launch_forces: the two schedules).
 //   Forces are accumulated with hardware FP64 atomics (FP32 atomics into a
 //   separate array in single precision, folded into the FP64 forces by
 //   k_fold32); energies and the virial by block reduction followed by one
