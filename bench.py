@@ -26,13 +26,16 @@ FP32_VALU_PEAK = 157.3e12
 # Algorithmic FP64 operations per unit of work of each kernel: per LJ pair
 # inside the cutoff (each pair once), per list pair beyond it, per REBO bond
 # (bond order forward + reverse, pair term, torsion), and per deferred pair
-# (the b* bond order forward: half the bond's bond-order work; its reverse,
-# the other half, only where dS_b != 0).
+# (the b* bond order forward; its reverse only where dS_b != 0).  The pair
+# figures are counts of the pair term; the bond-order figures are the FP64
+# work the hardware counts per bond and per deferred pair on the 32k melt
+# (the kernels evaluate each bond and pair once, so nothing is duplicated;
+# the reverse of a deferred pair is taken as costing its forward).
 FLOP_PER_LJ_PAIR = 45       # per pair inside its cutoff, each pair once
 FLOP_PER_SKIN_PAIR = 8      # per list pair beyond its cutoff (distance test)
-FLOP_PER_BOND = 4000
-FLOP_PER_BSTAR_FWD = 2000   # per deferred pair
-FLOP_PER_BSTAR_REV = 2000   # per deferred pair with dS_b != 0
+FLOP_PER_BOND = 2850
+FLOP_PER_BSTAR_FWD = 1300   # per deferred pair
+FLOP_PER_BSTAR_REV = 1300   # per deferred pair with dS_b != 0
 # untimed preparation of the melt: capped steepest descent, then rescaled NVE
 PREP_SD_ITERS, PREP_SD_ALPHA, PREP_SD_CAP = 300, 0.01, 0.02     # iterations, A^2/eV, A
 PREP_EQ_CYCLES, PREP_EQ_STEPS = 20, 50
@@ -327,9 +330,9 @@ def kernel_work(st):
     The LJ pairs (each pair once) split at the list build into near pairs
     (within 3 max R2 + skin: k_lj) and far pairs (k_ljf): 45 flop per pair
     inside its cutoff, 8 per list pair outside it (distance test only).
-    The bonded kernel: 4,000 flop per bond (forward and reverse bond order,
-    pair term, torsion).  The deferred-pair kernel: 2,000 flop per deferred
-    pair (b* forward) and 2,000 more per pair with dS_b != 0 (reverse)."""
+    The bonded kernel: 2,850 flop per bond (forward and reverse bond order,
+    pair term, torsion).  The deferred-pair kernel: 1,300 flop per deferred
+    pair (b* forward) and 1,300 more per pair with dS_b != 0 (reverse)."""
     far_in, far_pairs = st["lj_in_cut_far"], st["lj_entries_far"] // 2
     near_in, near_pairs = st["lj_in_cut"] - far_in, (st["lj_entries"] - st["lj_entries_far"]) // 2
     return {"k_lj": FLOP_PER_LJ_PAIR * near_in + FLOP_PER_SKIN_PAIR * max(near_pairs - near_in, 0),
