@@ -21,8 +21,8 @@
 // Kernels: neighbour staging from the LJ list; descriptors and their
 // Jacobian-vector product (lane per neighbour or neighbour pair, per-lane
 // feature accumulators reduced by a butterfly reduce-scatter); descriptor
-// vector-Jacobian product (forces; per-neighbour sums in LDS, then one atomic
-// per neighbour and component); the networks on BF16 MFMA 16x16x16 tiles with
+// vector-Jacobian product (forces; leg sums by shuffles, then one atomic per
+// neighbour and component); the networks on BF16 MFMA 16x16x16 tiles with
 // FP32 accumulation, both orientations of every weight matrix staged in LDS
 // (inference: forward pass and input gradient; training: also the double
 // backward of the force loss and the weight gradients); far-field pairs;
@@ -355,22 +355,23 @@ __global__ __launch_bounds__(256) void k_desc(Dev D, float* __restrict__ out, co
 // virial of the mean over the sets (sum over contributions of
 // (x_a - x_i) (x) F_a) goes to acc[slot][N_VIR..].  One wavefront per centre
 // atom i.
-//   angular: lane per neighbour pair (a, b) forms dE/du_a and dE/du_b and
-//     writes them to LDS slots; then lane per leg a sums the slots of its
-//     pairs (no atomics);
-//     and adds each leg's force to its atom (one atomic per component and
-//     set);
+//   angular: lane per neighbour pair (a, b) forms dE/du_a and dE/du_b; the
+//     legs' sums are formed by shuffles (a segmented scan along each row of
+//     the pair triangle, a gather down its columns) and each leg's force is
+//     added to its atom (one atomic per component and set);
 //   radial: gathered from both ends of each pair (the neighbour's dE/dG
 //     slice is read from memory), no atomics.
 // The centre's own force is a wavefront sum.
 // With FAR, the same pass over the LJ list evaluates the far-field term into
 // Ff [n][3] and acc.
-// One wavefront per block.  The centre's dE/dG rows are staged in LDS: the
+// One wavefront per block, register budget for four wavefronts per SIMD
+// (a few registers spill; three per SIMD without the bound, and a budget for
+// five spills heavily).  The centre's dE/dG rows are staged in LDS: the
 // angular and radial terms index them by the species of the pair or the
 // neighbour, which differs between lanes (a per-lane select of global
 // addresses made every pair wait on its own loads: ~2/3 of the kernel).
 template <bool FAR>
-__global__ __launch_bounds__(WAVE) void k_desc_force(Dev D, const DevParams* __restrict__ Pp, const float* __restrict__ g,
+__global__ __launch_bounds__(WAVE, 4) void k_desc_force(Dev D, const DevParams* __restrict__ Pp, const float* __restrict__ g,
                                                      int nm, float* __restrict__ F, double* __restrict__ Ff,
                                                      double* __restrict__ acc) {
   __shared__ NbList nb;
