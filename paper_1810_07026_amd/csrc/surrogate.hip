@@ -270,8 +270,11 @@ __device__ __forceinline__ void pair_ang(const NbList& nb, int a, int b, PairAng
 
 // Descriptors (MODE 0) or their Jacobian-vector product with w [n][3]
 // (MODE 1): out[i][f] = sum_a dG_if/dx_a . w_a.  One wavefront per atom.
+// The descriptors take a register budget for six wavefronts per SIMD (what
+// the LDS of four-atom blocks allows; a small spill).
 template <int MODE>
-__global__ __launch_bounds__(256) void k_desc(Dev D, float* __restrict__ out, const float* __restrict__ w) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == 0 ? 6 : 1, 8)))
+void k_desc(Dev D, float* __restrict__ out, const float* __restrict__ w) {
   __shared__ NbList nbs[4];
   int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   int i = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
