@@ -39,6 +39,20 @@ def test_options_default_on_cpu():
     assert L.airebo_last_error() is not None
 
 
+def test_options_layout_matches_library_on_cpu():
+    """The binding's Options has the C struct's size: airebo_options_default
+    clears exactly sizeof(Options) bytes (the last field, schedule, included)
+    and nothing beyond."""
+    import ctypes
+    L = airebo.load_library()
+    n = ctypes.sizeof(airebo.Options)
+    buf = (ctypes.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
+    L.airebo_options_default(ctypes.cast(buf, ctypes.POINTER(airebo.Options)))
+    assert all(b == 0xAB for b in buf[n:])
+    o = airebo.Options.from_buffer(buf)
+    assert o.schedule == 0 and o.precision == 0 and o.term_mask == 7
+
+
 def test_params_from_file_and_text_on_cpu():
     """The parameter set parses on the host alone, from the file and from its
     text; malformed text is rejected with the failing record named."""
